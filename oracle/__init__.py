@@ -1,0 +1,20 @@
+"""Plain FP64 CPU oracle for Kronecker-product exact exchange.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package: it exists so that ``tests/``, the ``smoke()`` check and
+the CPU-baseline leg of the benchmark can compare the HIP library against an
+obviously correct, slow implementation written directly from the paper.
+"""
+from .kx_oracle import (  # noqa: F401
+    Grid,
+    apply_fL,
+    exchange,
+    fd_weights,
+    forward_transform,
+    kernel_values,
+    laplacian_1d,
+    make_grid,
+    pair_energy,
+    pair_potential,
+    vx_orbital,
+)
