@@ -1,0 +1,168 @@
+/*
+ * kx — Kronecker-product exact exchange on AMD MI355X (gfx950).
+ *
+ * C ABI of the HIP library libkx.so.  It applies functions of the real-space
+ * finite-difference Laplacian through its Kronecker factorisation (Jing &
+ * Suryanarayana, "Efficient real space formalism for hybrid density
+ * functionals", Sec. III, Eqs. (11)-(21)) and uses them to apply the
+ * exact-exchange operator to a set of orbitals (Sec. II, Eqs. (3)-(5) and
+ * (8)-(10)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid layout: a field on an n1 x n2 x n3 grid is a contiguous array indexed
+ *   idx = i1 + n1*(i2 + n2*i3)   (axis 1 fastest);
+ * item b of a batch (or orbital j) starts at b*N, N = n1*n2*n3.
+ * Laplacian: L = I3 (x) I2 (x) L1 + I3 (x) L2 (x) I1 + L3 (x) I2 (x) I1 (Eq. (12)),
+ *   L_k the centred FD second-derivative matrix of even order fd_order on n_k
+ *   nodes of spacing h_k.  Dirichlet axes are homogeneous (values outside the
+ *   n_k nodes are zero); periodic axes wrap the stencil.
+ * Kernels f on the spectrum lam >= 0 of -L:
+ *   KX_KERNEL_COULOMB  f(lam) = 4 pi / lam                      (Eq. (5))
+ *   KX_KERNEL_ERFC     f(lam) = 4 pi (1 - exp(-lam/(4 w^2))) / lam,
+ *                      f(0) = pi / w^2                         (Eq. (10); the
+ *                      screened Coulomb kernel erfc(w r)/r, whose Fourier
+ *                      transform fixes the exponent constant)
+ * Device pointers (*_dev) are owned by the caller, must be device memory
+ * visible to the stream given at setup, and must not overlap each other.
+ * Host pointers (*_host) are read or written before the call returns, except
+ * where stated.
+ * Work is enqueued on the handle's stream; calls return before it finishes
+ * unless stated.  Calls on one handle must not run concurrently from several
+ * host threads.
+ * Errors: every argument is validated on the host before any device work is
+ * enqueued; on an error the handle and all outputs are left unchanged and a
+ * status other than KX_OK is returned.  Nothing aborts or throws across the
+ * ABI.
+ */
+#ifndef KX_H
+#define KX_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KX_OK = 0,
+  KX_ERR_INVALID_ARG = 1,   /* bad size, spacing, order, enum, pointer or count */
+  KX_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement      */
+  KX_ERR_SINGULAR = 3,      /* unscreened kernel with a zero eigenvalue of -L   */
+  KX_ERR_OUT_OF_MEMORY = 4, /* device or pinned host allocation failed          */
+  KX_ERR_DEVICE = 5,        /* a HIP runtime call failed                         */
+  KX_ERR_STATE = 6,         /* e.g. energy requested before any exchange call   */
+  KX_ERR_NUMERIC = 7        /* eigen-solver did not converge / non-finite input */
+} kx_status;
+
+typedef enum { KX_BC_DIRICHLET = 0, KX_BC_PERIODIC = 1 } kx_bc;
+typedef enum { KX_KERNEL_COULOMB = 0, KX_KERNEL_ERFC = 1 } kx_kernel;
+/* Arithmetic of the mode products.  The spectral scaling and the energy
+ * reduction are FP64 in every mode. */
+typedef enum {
+  KX_PREC_FP64 = 0,    /* FP64 MFMA                                          */
+  KX_PREC_FP32 = 1,    /* FP32 MFMA, FP32 intermediates                      */
+  KX_PREC_BF16X3 = 2,  /* three-term BF16 split of both operands, FP32 accumulate */
+  KX_PREC_FP16X3 = 3   /* three-term FP16 split, FP32 accumulate             */
+} kx_prec;
+/* Storage type of psi / rho / phi / vxpsi. */
+typedef enum { KX_F64 = 0, KX_F32 = 1 } kx_dtype;
+
+/* Opaque handle: owns the device copies of V_k and lam_k, the cached f table,
+ * the pair schedule and the intermediate workspace. */
+typedef struct kx_grid kx_grid;
+
+/* Build L_1, L_2, L_3 (Sec. III, Eq. (12)) and diagonalise each on the device
+ * in FP64: -L_k V_k = V_k diag(lam_k), lam_k ascending (Eq. (13)).
+ *   n[3]      grid points per axis, 1 <= n_k <= 160
+ *   h[3]      spacings, finite and > 0
+ *   fd_order  even, 2..24 (stencil radius fd_order/2)
+ *   bc[3]     kx_bc per axis
+ *   hip_stream  hipStream_t for all work of this handle (NULL = default stream)
+ *   out       receives the handle; set only on KX_OK.
+ * Synchronises the stream before returning (the eigen-solver result is
+ * checked on the host).  KX_ERR_NUMERIC if the Jacobi solver does not reach
+ * orthogonality ~1e-13. */
+kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
+                             const int bc[3], void* hip_stream, kx_grid** out);
+
+/* phi = f(-L) rho for a batch of fields (Eqs. (20)-(21)).
+ *   kernel, omega  see above; omega > 0 required for KX_KERNEL_ERFC
+ *   batch          number of fields, >= 0 (0 is a no-op)
+ *   dtype, prec    storage and arithmetic (this build: KX_F64 with KX_PREC_FP64)
+ *   rho_dev        batch*N input values;  phi_dev  batch*N outputs (overwritten)
+ * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic. */
+kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
+                      const void* rho_dev, void* phi_dev, int prec);
+
+/* Exact-exchange operator on norb real orbitals (Sec. II, Eqs. (3), (8)):
+ *   (Vx psi)_j = - sum_i occ_i phi_ij psi_i,   phi_ij = f(-L)(psi_i psi_j),
+ * evaluated over the norb(norb+1)/2 symmetric pairs i <= j; each pair
+ * updates orbital j and, if i != j, orbital i.  occ_host[norb] are the
+ * spin-summed occupations used as literal weights (a closed shell with
+ * occ = 2 gives twice the per-spin operator of Eq. (3)).
+ *   psi_dev    norb*N orbitals (read only)
+ *   vxpsi_dev  norb*N outputs, overwritten (not accumulated into)
+ * Also prepares E_x = -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h with
+ * (u,v)_h = h1 h2 h3 sum_r u v (Eqs. (4), (9)) and the per-pair energies,
+ * read back by kx_exchange_energy / kx_pair_energies.  The reduction order is
+ * fixed: results are bitwise reproducible run to run. */
+kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
+                            const void* psi_dev, const double* occ_host, void* vxpsi_dev,
+                            int prec);
+
+/* E_x of the last kx_apply_exchange on this handle.  Synchronises the stream.
+ * KX_ERR_STATE if there was none. */
+kx_status kx_exchange_energy(kx_grid* g, double* ex_out);
+
+/* e_ij = (rho_ij, phi_ij)_h of the last kx_apply_exchange for npairs pairs
+ * given as pairs_host[2k] = i, pairs_host[2k+1] = j (any order of i, j).
+ * Synchronises the stream.  A test hook for sampled-pair checks. */
+kx_status kx_pair_energies(kx_grid* g, int npairs, const int* pairs_host, double* e_out_host);
+
+/* Copy lam_axis (n_axis values, ascending) and V_axis (n_axis x n_axis,
+ * row-major, V[i*n + a] = component i of eigenvector a) to the host.  Either
+ * output may be NULL.  Synchronises the stream.  A test hook. */
+kx_status kx_get_eigensystem(kx_grid* g, int axis, double* lam_host, double* V_host);
+
+/* Optional launch timing.  kx_profile(g, 1) clears the record and brackets
+ * every later kernel launch of this handle with hipEvents on its stream;
+ * kx_profile(g, 0) stops.  kx_profile_read returns the summed elapsed time and
+ * the launch count of one phase since the last kx_profile(g, 1).  Both
+ * synchronise the stream. */
+typedef enum {
+  KX_PHASE_FORWARD = 0,  /* pair product + modes 2, 1 (per z-slab)          */
+  KX_PHASE_PENCIL = 1,   /* mode 3, f(Lambda) scaling + energy, mode 3 back  */
+  KX_PHASE_INVERSE = 2,  /* modes 1, 2 back + Vx psi accumulation            */
+  KX_PHASE_ENERGY = 3    /* deterministic energy reductions                  */
+} kx_phase;
+kx_status kx_profile(kx_grid* g, int enable);
+kx_status kx_profile_read(kx_grid* g, int phase, double* total_ms, long long* launches);
+
+/* Free every device allocation of the handle (after synchronising its stream).
+ * NULL is accepted. */
+kx_status kx_destroy(kx_grid* g);
+
+/* Static English text for a status code. */
+const char* kx_status_string(int status);
+
+/* ---- host-only helpers: no device is touched; usable without a GPU ---- */
+
+/* Centred FD weights for d^2/dx^2 of order fd_order (Sec. III): w_out[0..m],
+ * m = fd_order/2, with h^2 f''(x) ~ w0 f(x) + sum_p w_p (f(x+ph) + f(x-ph)). */
+kx_status kx_fd_weights(int fd_order, double* w_out);
+
+/* The 1-D matrix L_k (n x n, row-major, includes the 1/h^2) of Eq. (12). */
+kx_status kx_laplacian_1d(int n, double h, int fd_order, int bc, double* L_out);
+
+/* The pair schedule used by kx_apply_exchange: the symmetric pairs grouped
+ * into batches in which no orbital appears in two different pairs, so every
+ * batch can update vxpsi without atomics.  With pairs_out == NULL only the
+ * counts are returned.  pairs_out receives 2*npairs ints (i, j),
+ * batch_offsets_out nbatches+1 offsets into it; max_batch caps the batch size
+ * (<= 0: no cap). */
+kx_status kx_pair_schedule(int norb, int max_batch, int* npairs_out, int* nbatches_out,
+                           int* pairs_out, int* batch_offsets_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KX_H */

@@ -1,0 +1,681 @@
+// Host side of the kx C ABI: argument validation, FD weights and 1-D
+// Laplacian assembly (Sec. III, Eq. (12)), the pair schedule, workspace
+// management and the launch sequence of the transform kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kx_internal.h"
+
+using namespace kx;
+
+// ============================================================ host helpers
+namespace {
+
+bool valid_order(int order) { return order >= 2 && order <= 24 && order % 2 == 0; }
+
+// Closed form of the centred second-derivative weights of order 2m:
+//   w_p = 2 (-1)^(p+1) (m!)^2 / (p^2 (m-p)! (m+p)!),   w_0 = -2 sum_{p>=1} w_p.
+// The factorial ratio is accumulated as a product to stay in range.
+void fd_weights_closed_form(int order, double* w) {
+  const int m = order / 2;
+  double s = 0.0;
+  for (int p = 1; p <= m; ++p) {
+    // (m!)^2 / ((m-p)! (m+p)!) = prod_{k=1..p} (m-p+k) / (m+k)
+    double ratio = 1.0;
+    for (int k = 1; k <= p; ++k) ratio *= double(m - p + k) / double(m + k);
+    const double sign = (p % 2 == 1) ? 1.0 : -1.0;
+    w[p] = 2.0 * sign * ratio / (double(p) * double(p));
+    s += w[p];
+  }
+  w[0] = -2.0 * s;
+}
+
+void laplacian_1d(int n, double h, int order, int bc, double* L) {
+  double w[13];
+  fd_weights_closed_form(order, w);
+  const int m = order / 2;
+  const double ih2 = 1.0 / (h * h);
+  std::fill(L, L + (size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    for (int p = -m; p <= m; ++p) {
+      int j = i + p;
+      const double v = w[p < 0 ? -p : p] * ih2;
+      if (bc == KX_BC_DIRICHLET) {
+        if (j >= 0 && j < n) L[(size_t)i * n + j] += v;
+      } else {
+        j %= n;
+        if (j < 0) j += n;
+        L[(size_t)i * n + j] += v;
+      }
+    }
+  }
+}
+
+// Symmetric pairs i <= j grouped into batches with no orbital shared between
+// two pairs of a batch: first all diagonal pairs (i, i), then the rounds of a
+// round-robin tournament on norb (plus a dummy when norb is odd), each batch
+// optionally cut to max_batch pairs.
+void build_schedule(int norb, int max_batch, std::vector<Item>& pairs, std::vector<int>& offsets) {
+  pairs.clear();
+  offsets.clear();
+  auto flush_round = [&](const std::vector<Item>& round) {
+    size_t k = 0;
+    while (k < round.size()) {
+      const size_t take =
+          max_batch > 0 ? std::min(round.size() - k, (size_t)max_batch) : round.size() - k;
+      offsets.push_back((int)pairs.size());
+      pairs.insert(pairs.end(), round.begin() + k, round.begin() + k + take);
+      k += take;
+    }
+  };
+  std::vector<Item> round;
+  for (int i = 0; i < norb; ++i) round.push_back({i, i});
+  flush_round(round);
+  const int m = (norb + 1) & ~1;
+  for (int r = 0; r < m - 1; ++r) {
+    round.clear();
+    for (int k = 0; k < m / 2; ++k) {
+      const int pa = k, pb = m - 1 - k;
+      const int p0 = (pa == 0) ? 0 : 1 + (pa - 1 + r) % (m - 1);
+      const int q0 = 1 + (pb - 1 + r) % (m - 1);
+      const int i = std::min(p0, q0), j = std::max(p0, q0);
+      if (j < norb) round.push_back({i, j});
+    }
+    flush_round(round);
+  }
+  offsets.push_back((int)pairs.size());
+}
+
+}  // namespace
+
+// ============================================================ the handle
+struct kx_grid {
+  int n[3];
+  double h[3];
+  int order;
+  int bc[3];
+  hipStream_t stream;
+  Geom geom;
+  // eigensystems (device): padded V, V^T, lambda per axis
+  double* dV[3] = {nullptr, nullptr, nullptr};
+  double* dVT[3] = {nullptr, nullptr, nullptr};
+  double* dLam[3] = {nullptr, nullptr, nullptr};
+  std::vector<double> lam_host[3];
+  std::vector<double> V_host[3];
+  // f table cache
+  double* dF = nullptr;
+  int f_kernel = -1;
+  double f_omega = 0.0;
+  // workspace
+  double* dT = nullptr;
+  int slots = 0;
+  double* dEpart = nullptr;
+  int epart_slots = 0;
+  int max_slots = 64;
+  // item lists (device), cached by their key
+  Item* dItems = nullptr;
+  size_t items_cap = 0;
+  int items_key_kind = -1;  // 0 = fields (batch), 1 = pair schedule (norb)
+  int items_key = -1;
+  int items_maxb = -1;
+  std::vector<Item> sched_pairs;
+  std::vector<int> sched_offsets;
+  // exchange results
+  double* dOcc = nullptr;
+  int occ_cap = 0;
+  double* hOcc = nullptr;  // pinned staging
+  hipEvent_t occ_done = nullptr;
+  double* dPairE = nullptr;
+  long long pairE_cap = 0;
+  double* dEx = nullptr;
+  int last_norb = -1;
+  // optional per-launch timing (hipEvents on the handle's stream)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_kind;
+};
+
+namespace {
+
+#define KX_HIP(call)                   \
+  do {                                 \
+    if ((call) != hipSuccess) {        \
+      (void)hipGetLastError();         \
+      return KX_ERR_DEVICE;            \
+    }                                  \
+  } while (0)
+
+kx_status dev_alloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return KX_ERR_OUT_OF_MEMORY;
+  }
+  return KX_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+Eig eig_of(const kx_grid* g) {
+  Eig e;
+  for (int k = 0; k < 3; ++k) {
+    e.V[k] = g->dV[k];
+    e.VT[k] = g->dVT[k];
+  }
+  return e;
+}
+
+bool all_periodic(const kx_grid* g) {
+  return g->bc[0] == KX_BC_PERIODIC && g->bc[1] == KX_BC_PERIODIC && g->bc[2] == KX_BC_PERIODIC;
+}
+
+double lam_min_host(const kx_grid* g) {
+  return g->lam_host[0][0] + g->lam_host[1][0] + g->lam_host[2][0];
+}
+
+kx_status check_kernel_args(const kx_grid* g, int kernel, double omega) {
+  if (kernel != KX_KERNEL_COULOMB && kernel != KX_KERNEL_ERFC) return KX_ERR_INVALID_ARG;
+  if (kernel == KX_KERNEL_ERFC && !(std::isfinite(omega) && omega > 0.0)) return KX_ERR_INVALID_ARG;
+  if (kernel == KX_KERNEL_COULOMB && (all_periodic(g) || !(lam_min_host(g) > 0.0)))
+    return KX_ERR_SINGULAR;
+  return KX_OK;
+}
+
+kx_status check_types(int dtype, int prec) {
+  if (dtype != KX_F64 && dtype != KX_F32) return KX_ERR_INVALID_ARG;
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_FP16X3) return KX_ERR_INVALID_ARG;
+  if (dtype != KX_F64 || prec != KX_PREC_FP64) return KX_ERR_UNSUPPORTED;
+  return KX_OK;
+}
+
+kx_status ensure_ftable(kx_grid* g, int kernel, double omega) {
+  const double om = (kernel == KX_KERNEL_ERFC) ? omega : 0.0;
+  if (g->dF && g->f_kernel == kernel && g->f_omega == om) return KX_OK;
+  if (!g->dF) {
+    kx_status st = dev_alloc((void**)&g->dF, sizeof(double) * g->geom.slot);
+    if (st != KX_OK) return st;
+  }
+  KX_HIP(launch_ftable(g->dLam[0], g->dLam[1], g->dLam[2], g->geom, kernel, om, g->dF, g->stream));
+  g->f_kernel = kernel;
+  g->f_omega = om;
+  return KX_OK;
+}
+
+kx_status ensure_workspace(kx_grid* g, int slots) {
+  if (slots <= g->slots) return KX_OK;
+  // the previous buffers may still be in use by queued work
+  KX_HIP(hipStreamSynchronize(g->stream));
+  dev_free(g->dT);
+  dev_free(g->dEpart);
+  g->dT = nullptr;
+  g->dEpart = nullptr;
+  g->slots = 0;
+  kx_status st = dev_alloc((void**)&g->dT, sizeof(double) * (size_t)g->geom.slot * slots);
+  if (st != KX_OK) return st;
+  // padded rows are never written by the kernels; keep them zero
+  KX_HIP(hipMemsetAsync(g->dT, 0, sizeof(double) * (size_t)g->geom.slot * slots, g->stream));
+  const size_t nstrips = (size_t)(g->geom.slab / kTile);
+  st = dev_alloc((void**)&g->dEpart, sizeof(double) * nstrips * slots);
+  if (st != KX_OK) return st;
+  g->slots = slots;
+  return KX_OK;
+}
+
+// Bracket one kernel launch with timing events when profiling is on.
+template <class F>
+hipError_t timed(kx_grid* g, int kind, F&& launch) {
+  if (!g->prof_on) return launch();
+  const size_t k = g->prof_kind.size();
+  while (g->prof_ev.size() < 2 * (k + 1)) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return hipErrorOutOfMemory;
+    g->prof_ev.push_back(ev);
+  }
+  hipError_t e = hipEventRecord(g->prof_ev[2 * k], g->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(g->prof_ev[2 * k + 1], g->stream);
+  g->prof_kind.push_back(kind);
+  return e;
+}
+
+kx_status upload_items(kx_grid* g, int kind, int key, int maxb, const std::vector<Item>& items) {
+  if (g->items_key_kind == kind && g->items_key == key && g->items_maxb == maxb) return KX_OK;
+  KX_HIP(hipStreamSynchronize(g->stream));
+  if (items.size() > g->items_cap) {
+    dev_free(g->dItems);
+    g->dItems = nullptr;
+    g->items_cap = 0;
+    kx_status st = dev_alloc((void**)&g->dItems, sizeof(Item) * std::max<size_t>(items.size(), 1));
+    if (st != KX_OK) return st;
+    g->items_cap = items.size();
+  }
+  if (!items.empty())
+    KX_HIP(hipMemcpy(g->dItems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+  g->items_key_kind = kind;
+  g->items_key = key;
+  g->items_maxb = maxb;
+  return KX_OK;
+}
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+const char* kx_status_string(int s) {
+  switch (s) {
+    case KX_OK: return "ok";
+    case KX_ERR_INVALID_ARG: return "invalid argument";
+    case KX_ERR_UNSUPPORTED: return "unsupported in this build";
+    case KX_ERR_SINGULAR: return "singular: unscreened kernel with a zero eigenvalue";
+    case KX_ERR_OUT_OF_MEMORY: return "out of memory";
+    case KX_ERR_DEVICE: return "HIP runtime error";
+    case KX_ERR_STATE: return "invalid state";
+    case KX_ERR_NUMERIC: return "numerical failure";
+    default: return "unknown status";
+  }
+}
+
+kx_status kx_fd_weights(int fd_order, double* w_out) {
+  if (!valid_order(fd_order) || !w_out) return KX_ERR_INVALID_ARG;
+  fd_weights_closed_form(fd_order, w_out);
+  return KX_OK;
+}
+
+kx_status kx_laplacian_1d(int n, double h, int fd_order, int bc, double* L_out) {
+  if (n < 1 || n > kMaxN || !(std::isfinite(h) && h > 0.0) || !valid_order(fd_order) || !L_out ||
+      (bc != KX_BC_DIRICHLET && bc != KX_BC_PERIODIC))
+    return KX_ERR_INVALID_ARG;
+  laplacian_1d(n, h, fd_order, bc, L_out);
+  return KX_OK;
+}
+
+kx_status kx_pair_schedule(int norb, int max_batch, int* npairs_out, int* nbatches_out,
+                           int* pairs_out, int* batch_offsets_out) {
+  if (norb < 0 || norb > 65535 || !npairs_out || !nbatches_out) return KX_ERR_INVALID_ARG;
+  std::vector<Item> pairs;
+  std::vector<int> offs;
+  build_schedule(norb, max_batch, pairs, offs);
+  // drop empty batches (norb == 0)
+  std::vector<int> o2;
+  for (size_t b = 0; b + 1 < offs.size(); ++b)
+    if (offs[b + 1] > offs[b]) o2.push_back(offs[b]);
+  o2.push_back((int)pairs.size());
+  *npairs_out = (int)pairs.size();
+  *nbatches_out = (int)o2.size() - 1;
+  if (pairs_out) {
+    for (size_t k = 0; k < pairs.size(); ++k) {
+      pairs_out[2 * k] = pairs[k].i;
+      pairs_out[2 * k + 1] = pairs[k].j;
+    }
+  }
+  if (batch_offsets_out)
+    for (size_t b = 0; b < o2.size(); ++b) batch_offsets_out[b] = o2[b];
+  return KX_OK;
+}
+
+kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, const int bc[3],
+                             void* hip_stream, kx_grid** out) {
+  if (!n || !h || !bc || !out) return KX_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k) {
+    if (n[k] < 1 || n[k] > kMaxN) return KX_ERR_INVALID_ARG;
+    if (!(std::isfinite(h[k]) && h[k] > 0.0)) return KX_ERR_INVALID_ARG;
+    if (bc[k] != KX_BC_DIRICHLET && bc[k] != KX_BC_PERIODIC) return KX_ERR_INVALID_ARG;
+  }
+  if (!valid_order(fd_order)) return KX_ERR_INVALID_ARG;
+
+  kx_grid* g = new (std::nothrow) kx_grid();
+  if (!g) return KX_ERR_OUT_OF_MEMORY;
+  for (int k = 0; k < 3; ++k) {
+    g->n[k] = n[k];
+    g->h[k] = h[k];
+    g->bc[k] = bc[k];
+  }
+  g->order = fd_order;
+  g->stream = (hipStream_t)hip_stream;
+  Geom& G = g->geom;
+  G.n1 = n[0];
+  G.n2 = n[1];
+  G.n3 = n[2];
+  G.p1 = pad16(n[0]);
+  G.p2 = pad16(n[1]);
+  G.p3 = pad16(n[2]);
+  G.N = (long long)n[0] * n[1] * n[2];
+  G.slab = (long long)G.p1 * G.p2;
+  G.slot = G.slab * G.p3;
+  if (const char* env = std::getenv("KX_MAX_SLOTS")) {
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= 4096) g->max_slots = v;
+  }
+
+  auto fail = [&](kx_status st) {
+    kx_destroy(g);
+    return st;
+  };
+  double* dA = nullptr;
+  double* dW = nullptr;
+  double* dDiag = nullptr;
+  kx_status st = dev_alloc((void**)&dA, sizeof(double) * kMaxN * kMaxN);
+  if (st != KX_OK) return fail(st);
+  st = dev_alloc((void**)&dW, sizeof(double) * kMaxN * kMaxN);
+  if (st != KX_OK) {
+    dev_free(dA);
+    return fail(st);
+  }
+  st = dev_alloc((void**)&dDiag, sizeof(double) * 8);
+  if (st != KX_OK) {
+    dev_free(dA);
+    dev_free(dW);
+    return fail(st);
+  }
+  auto cleanup = [&]() {
+    dev_free(dA);
+    dev_free(dW);
+    dev_free(dDiag);
+  };
+  std::vector<double> L;
+  for (int k = 0; k < 3; ++k) {
+    const int nk = n[k], pk = pad16(nk);
+    if (dev_alloc((void**)&g->dV[k], sizeof(double) * pk * pk) != KX_OK ||
+        dev_alloc((void**)&g->dVT[k], sizeof(double) * pk * pk) != KX_OK ||
+        dev_alloc((void**)&g->dLam[k], sizeof(double) * pk) != KX_OK) {
+      cleanup();
+      return fail(KX_ERR_OUT_OF_MEMORY);
+    }
+    L.assign((size_t)nk * nk, 0.0);
+    laplacian_1d(nk, h[k], fd_order, bc[k], L.data());
+    for (double& v : L) v = -v;  // diagonalise -L_k (eigenvalues >= 0)
+    double diag[2] = {0.0, 0.0};
+    if (hipMemcpyAsync(dA, L.data(), sizeof(double) * nk * nk, hipMemcpyHostToDevice, g->stream) !=
+            hipSuccess ||
+        launch_jacobi(dA, dW, nk, 60, g->dLam[k], g->dV[k], g->dVT[k], pk, dDiag, g->stream) !=
+            hipSuccess ||
+        launch_check_orth(g->dV[k], nk, pk, dDiag + 1, g->stream) != hipSuccess ||
+        hipMemcpyAsync(diag, dDiag, sizeof(double) * 2, hipMemcpyDeviceToHost, g->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(g->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      cleanup();
+      return fail(KX_ERR_DEVICE);
+    }
+    if (diag[0] >= 60.0 || !(diag[1] < 1e-12)) {
+      cleanup();
+      return fail(KX_ERR_NUMERIC);
+    }
+    g->lam_host[k].resize(pk);
+    g->V_host[k].resize((size_t)pk * pk);
+    if (hipMemcpy(g->lam_host[k].data(), g->dLam[k], sizeof(double) * pk, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(g->V_host[k].data(), g->dV[k], sizeof(double) * pk * pk,
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      cleanup();
+      return fail(KX_ERR_DEVICE);
+    }
+  }
+  cleanup();
+  if (dev_alloc((void**)&g->dEx, sizeof(double) * 2) != KX_OK) return fail(KX_ERR_OUT_OF_MEMORY);
+  if (hipEventCreateWithFlags(&g->occ_done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    g->occ_done = nullptr;
+    return fail(KX_ERR_DEVICE);
+  }
+  *out = g;
+  return KX_OK;
+}
+
+kx_status kx_destroy(kx_grid* g) {
+  if (!g) return KX_OK;
+  (void)hipStreamSynchronize(g->stream);
+  for (int k = 0; k < 3; ++k) {
+    dev_free(g->dV[k]);
+    dev_free(g->dVT[k]);
+    dev_free(g->dLam[k]);
+  }
+  dev_free(g->dF);
+  dev_free(g->dT);
+  dev_free(g->dEpart);
+  dev_free(g->dItems);
+  dev_free(g->dOcc);
+  dev_free(g->dPairE);
+  dev_free(g->dEx);
+  if (g->hOcc) (void)hipHostFree(g->hOcc);
+  if (g->occ_done) (void)hipEventDestroy(g->occ_done);
+  for (hipEvent_t ev : g->prof_ev) (void)hipEventDestroy(ev);
+  (void)hipGetLastError();
+  delete g;
+  return KX_OK;
+}
+
+kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
+                      const void* rho_dev, void* phi_dev, int prec) {
+  if (!g || batch < 0) return KX_ERR_INVALID_ARG;
+  kx_status st = check_kernel_args(g, kernel, omega);
+  if (st != KX_OK) return st;
+  st = check_types(dtype, prec);
+  if (st != KX_OK) return st;
+  if (batch == 0) return KX_OK;
+  if (!rho_dev || !phi_dev) return KX_ERR_INVALID_ARG;
+  if ((double)batch * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
+  if (rho_dev == phi_dev) return KX_ERR_INVALID_ARG;
+
+  const int chunk = std::min(batch, g->max_slots);
+  st = ensure_workspace(g, chunk);
+  if (st != KX_OK) return st;
+  st = ensure_ftable(g, kernel, omega);
+  if (st != KX_OK) return st;
+  std::vector<Item> items(batch);
+  for (int b = 0; b < batch; ++b) items[b] = {b, -1};
+  st = upload_items(g, 0, batch, chunk, items);
+  if (st != KX_OK) return st;
+  const Eig e = eig_of(g);
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = std::min(chunk, batch - b0);
+    const Item* it = g->dItems + b0;
+    KX_HIP(timed(g, KX_PHASE_FORWARD, [&] {
+      return launch_forward_f64(0, g->geom, e, (const double*)rho_dev, it, nb, g->dT, g->stream);
+    }));
+    KX_HIP(timed(g, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_f64(g->geom, e, g->dF, nb, g->dT, nullptr, g->stream);
+    }));
+    KX_HIP(timed(g, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_f64(0, g->geom, e, g->dT, it, nb, nullptr, nullptr, (double*)phi_dev,
+                                g->stream);
+    }));
+  }
+  return KX_OK;
+}
+
+kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
+                            const void* psi_dev, const double* occ_host, void* vxpsi_dev,
+                            int prec) {
+  if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
+  kx_status st = check_kernel_args(g, kernel, omega);
+  if (st != KX_OK) return st;
+  st = check_types(dtype, prec);
+  if (st != KX_OK) return st;
+  if (norb > 0 && (!psi_dev || !vxpsi_dev || !occ_host)) return KX_ERR_INVALID_ARG;
+  if (psi_dev && psi_dev == vxpsi_dev) return KX_ERR_INVALID_ARG;
+  if ((double)norb * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
+  for (int i = 0; i < norb; ++i)
+    if (!std::isfinite(occ_host[i])) return KX_ERR_INVALID_ARG;
+
+  const long long npairs = (long long)norb * (norb + 1) / 2;
+  // results buffers
+  if (npairs > g->pairE_cap) {
+    KX_HIP(hipStreamSynchronize(g->stream));
+    dev_free(g->dPairE);
+    g->dPairE = nullptr;
+    g->pairE_cap = 0;
+    st = dev_alloc((void**)&g->dPairE, sizeof(double) * std::max<long long>(npairs, 1));
+    if (st != KX_OK) return st;
+    g->pairE_cap = npairs;
+  }
+  if (norb > g->occ_cap) {
+    KX_HIP(hipStreamSynchronize(g->stream));
+    dev_free(g->dOcc);
+    if (g->hOcc) (void)hipHostFree(g->hOcc);
+    g->dOcc = nullptr;
+    g->hOcc = nullptr;
+    g->occ_cap = 0;
+    st = dev_alloc((void**)&g->dOcc, sizeof(double) * norb);
+    if (st != KX_OK) return st;
+    if (hipHostMalloc((void**)&g->hOcc, sizeof(double) * norb, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      g->hOcc = nullptr;
+      return KX_ERR_OUT_OF_MEMORY;
+    }
+    g->occ_cap = norb;
+  }
+  if (norb == 0) {
+    KX_HIP(hipMemsetAsync(g->dEx, 0, sizeof(double), g->stream));
+    g->last_norb = 0;
+    return KX_OK;
+  }
+
+  // schedule (cached per norb and batch cap)
+  const int cap = g->max_slots;
+  if (!(g->items_key_kind == 1 && g->items_key == norb && g->items_maxb == cap)) {
+    build_schedule(norb, cap, g->sched_pairs, g->sched_offsets);
+  }
+  int maxb = 0;
+  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b)
+    maxb = std::max(maxb, g->sched_offsets[b + 1] - g->sched_offsets[b]);
+  st = ensure_workspace(g, maxb);
+  if (st != KX_OK) return st;
+  st = ensure_ftable(g, kernel, omega);
+  if (st != KX_OK) return st;
+  st = upload_items(g, 1, norb, cap, g->sched_pairs);
+  if (st != KX_OK) return st;
+
+  // occupations: pinned staging, reused once the previous upload finished
+  KX_HIP(hipEventSynchronize(g->occ_done));
+  std::memcpy(g->hOcc, occ_host, sizeof(double) * norb);
+  KX_HIP(hipMemcpyAsync(g->dOcc, g->hOcc, sizeof(double) * norb, hipMemcpyHostToDevice, g->stream));
+  KX_HIP(hipEventRecord(g->occ_done, g->stream));
+  KX_HIP(hipMemsetAsync(vxpsi_dev, 0, sizeof(double) * (size_t)norb * g->geom.N, g->stream));
+
+  const Eig e = eig_of(g);
+  const double dV = g->h[0] * g->h[1] * g->h[2];
+  const int nstrips = (int)(g->geom.slab / kTile);
+  const double* psi = (const double*)psi_dev;
+  double* vx = (double*)vxpsi_dev;
+  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
+    const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
+    if (nb <= 0) continue;
+    const Item* it = g->dItems + o0;
+    KX_HIP(timed(g, KX_PHASE_FORWARD, [&] {
+      return launch_forward_f64(1, g->geom, e, psi, it, nb, g->dT, g->stream);
+    }));
+    KX_HIP(timed(g, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_f64(g->geom, e, g->dF, nb, g->dT, g->dEpart, g->stream);
+    }));
+    KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
+      return launch_pair_energy(g->dEpart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
+    }));
+    KX_HIP(timed(g, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_f64(1, g->geom, e, g->dT, it, nb, psi, g->dOcc, vx, g->stream);
+    }));
+  }
+  KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
+    return launch_exchange_energy(g->dPairE, g->dOcc, norb, g->dEx, g->stream);
+  }));
+  g->last_norb = norb;
+  return KX_OK;
+}
+
+kx_status kx_exchange_energy(kx_grid* g, double* ex_out) {
+  if (!g || !ex_out) return KX_ERR_INVALID_ARG;
+  if (g->last_norb < 0) return KX_ERR_STATE;
+  double v = 0.0;
+  if (hipMemcpyAsync(&v, g->dEx, sizeof(double), hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+      hipStreamSynchronize(g->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return KX_ERR_DEVICE;
+  }
+  *ex_out = v;
+  return KX_OK;
+}
+
+kx_status kx_pair_energies(kx_grid* g, int npairs, const int* pairs_host, double* e_out_host) {
+  if (!g || npairs < 0) return KX_ERR_INVALID_ARG;
+  if (npairs > 0 && (!pairs_host || !e_out_host)) return KX_ERR_INVALID_ARG;
+  if (g->last_norb < 0) return KX_ERR_STATE;
+  const int norb = g->last_norb;
+  for (int k = 0; k < npairs; ++k) {
+    const int i = pairs_host[2 * k], j = pairs_host[2 * k + 1];
+    if (i < 0 || j < 0 || i >= norb || j >= norb) return KX_ERR_INVALID_ARG;
+  }
+  if (npairs == 0) return KX_OK;
+  const long long total = (long long)norb * (norb + 1) / 2;
+  std::vector<double> all(total);
+  if (hipStreamSynchronize(g->stream) != hipSuccess ||
+      hipMemcpy(all.data(), g->dPairE, sizeof(double) * total, hipMemcpyDeviceToHost) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return KX_ERR_DEVICE;
+  }
+  for (int k = 0; k < npairs; ++k) {
+    const int i = std::min(pairs_host[2 * k], pairs_host[2 * k + 1]);
+    const int j = std::max(pairs_host[2 * k], pairs_host[2 * k + 1]);
+    e_out_host[k] = all[pair_index(i, j, norb)];
+  }
+  return KX_OK;
+}
+
+kx_status kx_get_eigensystem(kx_grid* g, int axis, double* lam_host, double* V_host) {
+  if (!g || axis < 0 || axis > 2) return KX_ERR_INVALID_ARG;
+  const int nk = g->n[axis], pk = pad16(nk);
+  if (lam_host)
+    for (int a = 0; a < nk; ++a) lam_host[a] = g->lam_host[axis][a];
+  if (V_host)
+    for (int i = 0; i < nk; ++i)
+      for (int a = 0; a < nk; ++a) V_host[(size_t)i * nk + a] = g->V_host[axis][(size_t)i * pk + a];
+  return KX_OK;
+}
+
+kx_status kx_profile(kx_grid* g, int enable) {
+  if (!g || (enable != 0 && enable != 1)) return KX_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(g->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return KX_ERR_DEVICE;
+  }
+  g->prof_on = enable == 1;
+  g->prof_kind.clear();
+  return KX_OK;
+}
+
+kx_status kx_profile_read(kx_grid* g, int phase, double* total_ms, long long* launches) {
+  if (!g || !total_ms || !launches || phase < 0 || phase > KX_PHASE_ENERGY) return KX_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(g->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return KX_ERR_DEVICE;
+  }
+  double tot = 0.0;
+  long long cnt = 0;
+  for (size_t k = 0; k < g->prof_kind.size(); ++k) {
+    if (g->prof_kind[k] != phase) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, g->prof_ev[2 * k], g->prof_ev[2 * k + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      return KX_ERR_DEVICE;
+    }
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return KX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""Thin ctypes binding of libkx (include/kx.h): argument marshalling only.
+
+Every numerical step runs inside the HIP library.  PyTorch supplies device
+memory and the stream.  If libkx.so is missing this module raises on first
+use; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkx.so")
+
+KX_OK = 0
+STATUS = {
+    0: "KX_OK", 1: "KX_ERR_INVALID_ARG", 2: "KX_ERR_UNSUPPORTED", 3: "KX_ERR_SINGULAR",
+    4: "KX_ERR_OUT_OF_MEMORY", 5: "KX_ERR_DEVICE", 6: "KX_ERR_STATE", 7: "KX_ERR_NUMERIC",
+}
+BC = {"dirichlet": 0, "periodic": 1}
+KERNEL = {"coulomb": 0, "erfc": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
+DTYPE = {"f64": 0, "f32": 1}
+
+# every symbol include/kx.h declares
+EXPORTS = (
+    "kx_setup_laplacian", "kx_apply_fL", "kx_apply_exchange", "kx_exchange_energy",
+    "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
+    "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
+)
+PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
+
+
+class KxError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+_lib = None
+
+
+def lib():
+    """Load libkx.so (after torch, so one HIP runtime serves both)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        try:
+            import torch  # noqa: F401  (load torch's HIP runtime first)
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        c_int, c_double, vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        ip, dp = ctypes.POINTER(c_int), ctypes.POINTER(c_double)
+        sig = {
+            "kx_setup_laplacian": [ip, dp, c_int, ip, vp, ctypes.POINTER(vp)],
+            "kx_apply_fL": [vp, c_int, c_double, c_int, c_int, vp, vp, c_int],
+            "kx_apply_exchange": [vp, c_int, c_double, c_int, c_int, vp, dp, vp, c_int],
+            "kx_exchange_energy": [vp, dp],
+            "kx_pair_energies": [vp, c_int, ip, dp],
+            "kx_get_eigensystem": [vp, c_int, dp, dp],
+            "kx_destroy": [vp],
+            "kx_status_string": [c_int],
+            "kx_fd_weights": [c_int, dp],
+            "kx_laplacian_1d": [c_int, c_double, c_int, c_int, dp],
+            "kx_pair_schedule": [c_int, c_int, ip, ip, ip, ip],
+            "kx_profile": [vp, c_int],
+            "kx_profile_read": [vp, c_int, dp, ctypes.POINTER(ctypes.c_longlong)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "kx_status_string" else c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, where):
+    if st != KX_OK:
+        raise KxError(st, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+# ---------------------------------------------------------------- host-only
+def fd_weights(order):
+    import numpy as np
+    w = np.zeros(order // 2 + 1)
+    _check(lib().kx_fd_weights(order, _dptr(w)), "kx_fd_weights")
+    return w
+
+
+def laplacian_1d(n, h, order, bc):
+    import numpy as np
+    L = np.zeros((n, n))
+    _check(lib().kx_laplacian_1d(n, float(h), order, BC.get(bc, bc), _dptr(L)), "kx_laplacian_1d")
+    return L
+
+
+def pair_schedule(norb, max_batch=0):
+    import numpy as np
+    npairs, nb = ctypes.c_int(), ctypes.c_int()
+    _check(lib().kx_pair_schedule(norb, max_batch, ctypes.byref(npairs), ctypes.byref(nb), None, None),
+           "kx_pair_schedule")
+    pairs = np.zeros((max(npairs.value, 1), 2), dtype=np.int32)
+    offs = np.zeros(nb.value + 1, dtype=np.int32)
+    _check(lib().kx_pair_schedule(norb, max_batch, ctypes.byref(npairs), ctypes.byref(nb),
+                                  _iptr(pairs), _iptr(offs)), "kx_pair_schedule")
+    return pairs[:npairs.value], offs
+
+
+# ---------------------------------------------------------------- device
+class Grid:
+    """One kx_grid handle (Laplacian eigensystems, f table, workspace)."""
+
+    def __init__(self, n, h, order, bc, stream=None):
+        import numpy as np
+        import torch
+        self.n = tuple(int(v) for v in n)
+        self.h = tuple(float(v) for v in h)
+        self.order = int(order)
+        self.bc = tuple(bc)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        n_c = (ctypes.c_int * 3)(*self.n)
+        h_c = (ctypes.c_double * 3)(*self.h)
+        bc_c = (ctypes.c_int * 3)(*[BC.get(b, b) for b in self.bc])
+        handle = ctypes.c_void_p()
+        st = lib().kx_setup_laplacian(n_c, h_c, self.order, bc_c, ctypes.c_void_p(stream.cuda_stream),
+                                      ctypes.byref(handle))
+        _check(st, "kx_setup_laplacian")
+        self._h = handle
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self._np = np
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_fL(self, rho, kernel, omega=0.0, prec="fp64", out=None):
+        """phi = f(-L) rho; rho is a (batch, n3, n2, n1) device tensor."""
+        import torch
+        dtype = "f64" if rho.dtype == torch.float64 else "f32"
+        batch = rho.shape[0] if rho.dim() == 4 else 1
+        if out is None:
+            out = torch.empty_like(rho)
+        st = lib().kx_apply_fL(self._h, KERNEL[kernel], float(omega), batch, DTYPE[dtype], _ptr(rho),
+                               _ptr(out), PREC[prec])
+        _check(st, "kx_apply_fL")
+        return out
+
+    def apply_exchange(self, psi, occ, kernel, omega=0.0, prec="fp64", out=None):
+        """(Vx psi) for psi of shape (norb, n3, n2, n1); occ a host sequence."""
+        import numpy as np
+        import torch
+        dtype = "f64" if psi.dtype == torch.float64 else "f32"
+        norb = psi.shape[0]
+        occ_a = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        if out is None:
+            out = torch.empty_like(psi)
+        st = lib().kx_apply_exchange(self._h, KERNEL[kernel], float(omega), norb, DTYPE[dtype], _ptr(psi),
+                                     _dptr(occ_a), _ptr(out), PREC[prec])
+        _check(st, "kx_apply_exchange")
+        return out
+
+    def exchange_energy(self):
+        v = ctypes.c_double()
+        _check(lib().kx_exchange_energy(self._h, ctypes.byref(v)), "kx_exchange_energy")
+        return v.value
+
+    def pair_energies(self, pairs):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        e = np.zeros(len(p))
+        _check(lib().kx_pair_energies(self._h, len(p), _iptr(p), _dptr(e)), "kx_pair_energies")
+        return e
+
+    def profile(self, enable=True):
+        _check(lib().kx_profile(self._h, 1 if enable else 0), "kx_profile")
+
+    def profile_read(self, phase):
+        """(total ms, launches) of one phase since profile(True)."""
+        ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+        _check(lib().kx_profile_read(self._h, PHASE[phase], ctypes.byref(ms), ctypes.byref(cnt)),
+               "kx_profile_read")
+        return ms.value, cnt.value
+
+    def eigensystem(self, axis):
+        import numpy as np
+        n = self.n[axis]
+        lam = np.zeros(n)
+        V = np.zeros((n, n))
+        _check(lib().kx_get_eigensystem(self._h, axis, _dptr(lam), _dptr(V)), "kx_get_eigensystem")
+        return lam, V

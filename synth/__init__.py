@@ -11,4 +11,5 @@ from .orbitals import (  # noqa: F401
     gaussian_orbitals,
     make_workload,
     orthonormalise_cgs2,
+    random_fields,
 )
