@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "kx_internal.h"
@@ -102,10 +103,16 @@ struct kx_grid {
   int bc[3];
   hipStream_t stream;
   Geom geom;
+  Plan plan;
   // eigensystems (device): padded V, V^T, lambda per axis
-  double* dV[3] = {nullptr, nullptr, nullptr};
-  double* dVT[3] = {nullptr, nullptr, nullptr};
-  double* dLam[3] = {nullptr, nullptr, nullptr};
+  // folded eigen-blocks per axis (device): even / odd halves and transposes
+  double* dVE[3] = {nullptr, nullptr, nullptr};
+  double* dVO[3] = {nullptr, nullptr, nullptr};
+  double* dVET[3] = {nullptr, nullptr, nullptr};
+  double* dVOT[3] = {nullptr, nullptr, nullptr};
+  double* dLamE[3] = {nullptr, nullptr, nullptr};
+  double* dLamO[3] = {nullptr, nullptr, nullptr};
+  // full eigensystem per axis (host), lam ascending, V[i*n + a]
   std::vector<double> lam_host[3];
   std::vector<double> V_host[3];
   // f table cache
@@ -167,8 +174,10 @@ void dev_free(void* p) {
 Eig eig_of(const kx_grid* g) {
   Eig e;
   for (int k = 0; k < 3; ++k) {
-    e.V[k] = g->dV[k];
-    e.VT[k] = g->dVT[k];
+    e.VE[k] = g->dVE[k];
+    e.VO[k] = g->dVO[k];
+    e.VET[k] = g->dVET[k];
+    e.VOT[k] = g->dVOT[k];
   }
   return e;
 }
@@ -178,6 +187,7 @@ bool all_periodic(const kx_grid* g) {
 }
 
 double lam_min_host(const kx_grid* g) {
+  // lam_host is ascending per axis
   return g->lam_host[0][0] + g->lam_host[1][0] + g->lam_host[2][0];
 }
 
@@ -200,10 +210,12 @@ kx_status ensure_ftable(kx_grid* g, int kernel, double omega) {
   const double om = (kernel == KX_KERNEL_ERFC) ? omega : 0.0;
   if (g->dF && g->f_kernel == kernel && g->f_omega == om) return KX_OK;
   if (!g->dF) {
-    kx_status st = dev_alloc((void**)&g->dF, sizeof(double) * g->geom.slot);
+    kx_status st = dev_alloc((void**)&g->dF, sizeof(double) * g->geom.fsize);
     if (st != KX_OK) return st;
   }
-  KX_HIP(launch_ftable(g->dLam[0], g->dLam[1], g->dLam[2], g->geom, kernel, om, g->dF, g->stream));
+  const double* le[3] = {g->dLamE[0], g->dLamE[1], g->dLamE[2]};
+  const double* lo[3] = {g->dLamO[0], g->dLamO[1], g->dLamO[2]};
+  KX_HIP(launch_ftable(le, lo, g->geom, kernel, om, g->dF, g->stream));
   g->f_kernel = kernel;
   g->f_omega = om;
   return KX_OK;
@@ -347,12 +359,35 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
   G.n1 = n[0];
   G.n2 = n[1];
   G.n3 = n[2];
-  G.p1 = pad16(n[0]);
-  G.p2 = pad16(n[1]);
-  G.p3 = pad16(n[2]);
+  {
+    int* me[3] = {&G.me1, &G.me2, &G.me3};
+    int* mo[3] = {&G.mo1, &G.mo2, &G.mo3};
+    int* pe[3] = {&G.pe1, &G.pe2, &G.pe3};
+    int* po[3] = {&G.po1, &G.po2, &G.po3};
+    int* pp[3] = {&G.p1, &G.p2, &G.p3};
+    for (int k = 0; k < 3; ++k) {
+      *mo[k] = n[k] / 2;
+      *me[k] = n[k] - n[k] / 2;
+      *pe[k] = pad16(*me[k]);
+      *po[k] = pad16(*mo[k]);
+      *pp[k] = *pe[k] + *po[k];
+    }
+  }
   G.N = (long long)n[0] * n[1] * n[2];
   G.slab = (long long)G.p1 * G.p2;
-  G.slot = G.slab * G.p3;
+  G.slot = G.slab * G.n3;
+  G.fsize = G.slab * G.p3;
+  {
+    int dev = 0, lds = 64 * 1024;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        lds > 0) {
+      g->plan = make_plan(G, (size_t)lds);
+    } else {
+      (void)hipGetLastError();
+      g->plan = make_plan(G, 64 * 1024);
+    }
+  }
   if (const char* env = std::getenv("KX_MAX_SLOTS")) {
     const int v = std::atoi(env);
     if (v >= 1 && v <= 4096) g->max_slots = v;
@@ -383,44 +418,109 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
     dev_free(dW);
     dev_free(dDiag);
   };
-  std::vector<double> L;
+  // Per axis: fold -L_k into its even block E (me x me) and odd block O
+  // (mo x mo) in the bases (e_i + e_{n-1-i})/sqrt2, e_m (middle of odd n) and
+  // (e_i - e_{n-1-i})/sqrt2; diagonalise both on the device; the stored half
+  // eigenvectors are U/sqrt2 except the middle row (kept as is).
+  std::vector<double> L, B;
+  const double rs = 1.0 / std::sqrt(2.0);
   for (int k = 0; k < 3; ++k) {
-    const int nk = n[k], pk = pad16(nk);
-    if (dev_alloc((void**)&g->dV[k], sizeof(double) * pk * pk) != KX_OK ||
-        dev_alloc((void**)&g->dVT[k], sizeof(double) * pk * pk) != KX_OK ||
-        dev_alloc((void**)&g->dLam[k], sizeof(double) * pk) != KX_OK) {
+    const int nk = n[k], m = nk / 2, me = nk - m, mo = m;
+    const int pe = pad16(me), po = pad16(mo);
+    if (dev_alloc((void**)&g->dVE[k], sizeof(double) * pe * pe) != KX_OK ||
+        dev_alloc((void**)&g->dVET[k], sizeof(double) * pe * pe) != KX_OK ||
+        dev_alloc((void**)&g->dLamE[k], sizeof(double) * pe) != KX_OK ||
+        dev_alloc((void**)&g->dVO[k], sizeof(double) * std::max(po * po, 1)) != KX_OK ||
+        dev_alloc((void**)&g->dVOT[k], sizeof(double) * std::max(po * po, 1)) != KX_OK ||
+        dev_alloc((void**)&g->dLamO[k], sizeof(double) * std::max(po, 1)) != KX_OK) {
       cleanup();
       return fail(KX_ERR_OUT_OF_MEMORY);
     }
     L.assign((size_t)nk * nk, 0.0);
     laplacian_1d(nk, h[k], fd_order, bc[k], L.data());
-    for (double& v : L) v = -v;  // diagonalise -L_k (eigenvalues >= 0)
-    double diag[2] = {0.0, 0.0};
-    if (hipMemcpyAsync(dA, L.data(), sizeof(double) * nk * nk, hipMemcpyHostToDevice, g->stream) !=
-            hipSuccess ||
-        launch_jacobi(dA, dW, nk, 60, g->dLam[k], g->dV[k], g->dVT[k], pk, dDiag, g->stream) !=
-            hipSuccess ||
-        launch_check_orth(g->dV[k], nk, pk, dDiag + 1, g->stream) != hipSuccess ||
-        hipMemcpyAsync(diag, dDiag, sizeof(double) * 2, hipMemcpyDeviceToHost, g->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(g->stream) != hipSuccess) {
-      (void)hipGetLastError();
-      cleanup();
-      return fail(KX_ERR_DEVICE);
+    auto A = [&](int i, int j) { return -L[(size_t)i * nk + j]; };
+    std::vector<double> lamE(pe, 0.0), lamO(std::max(po, 1), 0.0);
+    std::vector<double> VE((size_t)pe * pe), VO((size_t)std::max(po * po, 1));
+    for (int par = 0; par < 2; ++par) {
+      const int dim = par == 0 ? me : mo;
+      if (dim == 0) continue;
+      B.assign((size_t)dim * dim, 0.0);
+      for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+          double v;
+          if (i < m && j < m) {
+            v = par == 0 ? A(i, j) + A(i, nk - 1 - j) : A(i, j) - A(i, nk - 1 - j);
+          } else if (i == m && j == m) {
+            v = A(m, m);
+          } else {
+            v = std::sqrt(2.0) * A(i < m ? i : j, m);  // even block only: odd n
+          }
+          B[(size_t)i * dim + j] = v;
+        }
+      const int np = par == 0 ? pe : po;
+      double* dVh = par == 0 ? g->dVE[k] : g->dVO[k];
+      double* dVhT = par == 0 ? g->dVET[k] : g->dVOT[k];
+      double* dLam = par == 0 ? g->dLamE[k] : g->dLamO[k];
+      const int keep = (par == 0 && (nk & 1)) ? m : -1;
+      double diag = 0.0;
+      if (hipMemcpyAsync(dA, B.data(), sizeof(double) * dim * dim, hipMemcpyHostToDevice,
+                         g->stream) != hipSuccess ||
+          launch_jacobi(dA, dW, dim, 60, rs, keep, dLam, dVh, dVhT, np, dDiag, g->stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(&diag, dDiag, sizeof(double), hipMemcpyDeviceToHost, g->stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(par == 0 ? lamE.data() : lamO.data(), dLam, sizeof(double) * np,
+                         hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+          hipMemcpyAsync(par == 0 ? VE.data() : VO.data(), dVh, sizeof(double) * np * np,
+                         hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+          hipStreamSynchronize(g->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(KX_ERR_DEVICE);
+      }
+      if (diag >= 60.0) {
+        cleanup();
+        return fail(KX_ERR_NUMERIC);
+      }
     }
-    if (diag[0] >= 60.0 || !(diag[1] < 1e-12)) {
+    // unfold into the full eigensystem (host copy), sorted by eigenvalue
+    std::vector<std::pair<double, int>> order;
+    for (int a = 0; a < me; ++a) order.push_back({lamE[a], a});
+    for (int a = 0; a < mo; ++a) order.push_back({lamO[a], me + a});
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+                       return x.first < y.first;
+                     });
+    g->lam_host[k].assign(nk, 0.0);
+    g->V_host[k].assign((size_t)nk * nk, 0.0);
+    for (int col = 0; col < nk; ++col) {
+      const int src = order[col].second;
+      g->lam_host[k][col] = order[col].first;
+      for (int i = 0; i < me; ++i) {
+        double* V = g->V_host[k].data();
+        if (src < me) {
+          const double v = VE[(size_t)i * pe + src];
+          V[(size_t)i * nk + col] = v;
+          if (i < m) V[(size_t)(nk - 1 - i) * nk + col] = v;
+        } else if (i < m) {
+          const double v = VO[(size_t)i * po + (src - me)];
+          V[(size_t)i * nk + col] = v;
+          V[(size_t)(nk - 1 - i) * nk + col] = -v;
+        }
+      }
+    }
+    // orthonormality of the unfolded basis
+    double worst = 0.0;
+    const double* V = g->V_host[k].data();
+    for (int a = 0; a < nk; ++a)
+      for (int b = a; b < nk; ++b) {
+        double sum = 0.0;
+        for (int i = 0; i < nk; ++i) sum += V[(size_t)i * nk + a] * V[(size_t)i * nk + b];
+        worst = std::max(worst, std::fabs(sum - (a == b ? 1.0 : 0.0)));
+      }
+    if (!(worst < 1e-12)) {
       cleanup();
       return fail(KX_ERR_NUMERIC);
-    }
-    g->lam_host[k].resize(pk);
-    g->V_host[k].resize((size_t)pk * pk);
-    if (hipMemcpy(g->lam_host[k].data(), g->dLam[k], sizeof(double) * pk, hipMemcpyDeviceToHost) !=
-            hipSuccess ||
-        hipMemcpy(g->V_host[k].data(), g->dV[k], sizeof(double) * pk * pk,
-                  hipMemcpyDeviceToHost) != hipSuccess) {
-      (void)hipGetLastError();
-      cleanup();
-      return fail(KX_ERR_DEVICE);
     }
   }
   cleanup();
@@ -438,9 +538,12 @@ kx_status kx_destroy(kx_grid* g) {
   if (!g) return KX_OK;
   (void)hipStreamSynchronize(g->stream);
   for (int k = 0; k < 3; ++k) {
-    dev_free(g->dV[k]);
-    dev_free(g->dVT[k]);
-    dev_free(g->dLam[k]);
+    dev_free(g->dVE[k]);
+    dev_free(g->dVO[k]);
+    dev_free(g->dVET[k]);
+    dev_free(g->dVOT[k]);
+    dev_free(g->dLamE[k]);
+    dev_free(g->dLamO[k]);
   }
   dev_free(g->dF);
   dev_free(g->dT);
@@ -483,13 +586,13 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
     const int nb = std::min(chunk, batch - b0);
     const Item* it = g->dItems + b0;
     KX_HIP(timed(g, KX_PHASE_FORWARD, [&] {
-      return launch_forward_f64(0, g->geom, e, (const double*)rho_dev, it, nb, g->dT, g->stream);
+      return launch_forward_f64(0, g->geom, g->plan, e, (const double*)rho_dev, it, nb, g->dT, g->stream);
     }));
     KX_HIP(timed(g, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_f64(g->geom, e, g->dF, nb, g->dT, nullptr, g->stream);
+      return launch_pencil_f64(g->geom, g->plan, e, g->dF, nb, g->dT, nullptr, g->stream);
     }));
     KX_HIP(timed(g, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_f64(0, g->geom, e, g->dT, it, nb, nullptr, nullptr, (double*)phi_dev,
+      return launch_inverse_f64(0, g->geom, g->plan, e, g->dT, it, nb, nullptr, nullptr, (double*)phi_dev,
                                 g->stream);
     }));
   }
@@ -575,16 +678,16 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
     if (nb <= 0) continue;
     const Item* it = g->dItems + o0;
     KX_HIP(timed(g, KX_PHASE_FORWARD, [&] {
-      return launch_forward_f64(1, g->geom, e, psi, it, nb, g->dT, g->stream);
+      return launch_forward_f64(1, g->geom, g->plan, e, psi, it, nb, g->dT, g->stream);
     }));
     KX_HIP(timed(g, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_f64(g->geom, e, g->dF, nb, g->dT, g->dEpart, g->stream);
+      return launch_pencil_f64(g->geom, g->plan, e, g->dF, nb, g->dT, g->dEpart, g->stream);
     }));
     KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
       return launch_pair_energy(g->dEpart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
     }));
     KX_HIP(timed(g, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_f64(1, g->geom, e, g->dT, it, nb, psi, g->dOcc, vx, g->stream);
+      return launch_inverse_f64(1, g->geom, g->plan, e, g->dT, it, nb, psi, g->dOcc, vx, g->stream);
     }));
   }
   KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
@@ -635,12 +738,11 @@ kx_status kx_pair_energies(kx_grid* g, int npairs, const int* pairs_host, double
 
 kx_status kx_get_eigensystem(kx_grid* g, int axis, double* lam_host, double* V_host) {
   if (!g || axis < 0 || axis > 2) return KX_ERR_INVALID_ARG;
-  const int nk = g->n[axis], pk = pad16(nk);
+  const int nk = g->n[axis];
   if (lam_host)
     for (int a = 0; a < nk; ++a) lam_host[a] = g->lam_host[axis][a];
   if (V_host)
-    for (int i = 0; i < nk; ++i)
-      for (int a = 0; a < nk; ++a) V_host[(size_t)i * nk + a] = g->V_host[axis][(size_t)i * pk + a];
+    for (size_t idx = 0; idx < (size_t)nk * nk; ++idx) V_host[idx] = g->V_host[axis][idx];
   return KX_OK;
 }
 

@@ -12,53 +12,95 @@
 
 namespace kx {
 
-constexpr int kTile = 16;     // MFMA tile edge (v_mfma_f64_16x16x4f64)
-constexpr int kMaxN = 160;    // largest supported n_k
-constexpr int kMaxNT = kMaxN / kTile;
+constexpr int kTile = 16;  // MFMA tile edge (v_mfma_f64_16x16x4f64)
+constexpr int kMaxN = 160; // largest supported n_k
 
 inline int pad16(int n) { return (n + kTile - 1) / kTile * kTile; }
 
-// Geometry passed by value to every transform kernel.
+// Every 1-D matrix L_k is centrosymmetric (J L_k J = L_k with J the index
+// reversal): symmetric Toeplitz for homogeneous Dirichlet ends, symmetric
+// circulant for periodic ones.  Its eigenvectors therefore split into even
+// (v = J v) and odd (v = -J v) ones, and a product with V_k^T becomes two
+// half-size products on the folded vector:
+//   x_e[i] = x[i] + x[n-1-i] (i < n/2),  x_e[m] = x[m] for the middle of odd n,
+//   x_o[i] = x[i] - x[n-1-i] (i < n/2),
+//   (V^T x)_even = VE^T x_e,  (V^T x)_odd = VO^T x_o,
+// with VE, VO the upper halves of the even / odd eigenvectors.  The inverse
+// product unfolds: p = VE y_e, q = VO y_o, x[i] = p[i] + q[i],
+// x[n-1-i] = p[i] - q[i].  Mode indices are stored "parity-blocked": even
+// modes a in [0, pe), odd modes at pe + [0, po).
 struct Geom {
-  int n1, n2, n3;     // grid points
-  int p1, p2, p3;     // padded to multiples of 16
+  int n1, n2, n3;
+  int me1, me2, me3;  // even half length: ceil(n/2)
+  int mo1, mo2, mo3;  // odd half length: floor(n/2)
+  int pe1, pe2, pe3;  // pad16(me)
+  int po1, po2, po3;  // pad16(mo)
+  int p1, p2, p3;     // pe + po: blocked mode-index extent
   long long N;        // n1*n2*n3 (field stride in psi / rho / vxpsi)
-  long long slab;     // p1*p2  (one z-slab of the intermediate, [a][b])
-  long long slot;     // p3*p1*p2 (one intermediate field)
+  long long slab;     // p1*p2: one z-slab of the intermediate, [a][b] blocked
+  long long slot;     // n3*slab: one intermediate field, [z][a][b]
+  long long fsize;    // p3*slab: the f table, [c][a][b]
 };
 
-// Device copies of the per-axis eigensystems, padded with zeros:
-//   V[k]  [i][a] row-major (p_k x p_k), column a = eigenvector a
-//   VT[k] [a][i] row-major
-//   lam[k] p_k values (zeros beyond n_k)
+// Device copies of the half eigenvector blocks, zero padded:
+//   VE[k] [i][a] row-major pe_k x pe_k (i < me_k spatial, a < me_k mode)
+//   VO[k] [i][a] row-major po_k x po_k
+//   VET, VOT their transposes.
 struct Eig {
-  const double* V[3];
-  const double* VT[3];
+  const double* VE[3];
+  const double* VO[3];
+  const double* VET[3];
+  const double* VOT[3];
 };
 
-// One item of a transform batch: for exchange (i, j) orbital indices; for
-// apply_fL (b, -1) with b the field index.
+// One item of a transform batch: an orbital pair (i, j) for the exchange,
+// (b, -1) with b the field index for apply_fL.
 struct Item {
   int i, j;
 };
 
-// ---- setup kernels (kx_setup.hip) ----
-hipError_t launch_jacobi(double* A, double* V, int n, int max_sweeps, double* lam_pad, double* Vpad,
-                         double* VTpad, int np, double* diag_out, hipStream_t s);
-hipError_t launch_ftable(const double* lam1, const double* lam2, const double* lam3, const Geom& g,
-                         int kernel, double omega, double* F, hipStream_t s);
-hipError_t launch_check_orth(const double* V, int n, int np, double* out2, hipStream_t s);
+// Launch shapes, chosen once per grid from the LDS size.
+struct SlabPlan {
+  int slabs = 1;      // z-slabs per workgroup
+  int kc = 8;         // folded K rows staged per chunk
+  int waves = 1;      // waves per workgroup
+  int qsplit = 1;     // forward: 2 = one x-parity per workgroup
+  bool vlds = false;  // the second product's V blocks resident in LDS
+  size_t lds_bytes = 0;
+};
+struct PencilPlan {
+  int waves = 8;
+  size_t lds_bytes = 0;  // 0: V3 blocks read from global memory
+};
+struct Plan {
+  SlabPlan fwd, inv;
+  PencilPlan pen;
+};
+Plan make_plan(const Geom& g, size_t max_lds);
 
-// ---- FP64 transform kernels (kx_fp64.hip) ----
+// ---- set-up kernels (kx_setup.hip) ----
+// Jacobi eigensolver of the symmetric n x n matrix A (global memory); writes
+// eigenvalues ascending into lam_pad[0..n) and the eigenvectors, row i
+// scaled by rs except row keep_row, into Vpad[i*np + a] and VTpad[a*np + i].
+hipError_t launch_jacobi(double* A, double* V, int n, int max_sweeps, double rs, int keep_row,
+                         double* lam_pad, double* Vpad, double* VTpad, int np, double* diag_out,
+                         hipStream_t s);
+// f of the summed eigenvalues in the blocked [c][a][b] order, zero on padding
+hipError_t launch_ftable(const double* const lamE[3], const double* const lamO[3], const Geom& g,
+                         int kernel, double omega, double* F, hipStream_t s);
+
+// ---- FP64 transform kernels (kx_fold64.hip) ----
 // mode: 0 = apply_fL (rho -> phi), 1 = exchange (psi -> vxpsi)
-hipError_t launch_forward_f64(int mode, const Geom& g, const Eig& e, const double* src,
-                              const Item* items, int nitems, double* T, hipStream_t s);
-hipError_t launch_pencil_f64(const Geom& g, const Eig& e, const double* F, int nitems, double* T,
-                             double* epart, hipStream_t s);
-hipError_t launch_inverse_f64(int mode, const Geom& g, const Eig& e, const double* T,
-                              const Item* items, int nitems, const double* psi, const double* occ,
-                              double* dst, hipStream_t s);
-// per-item energies: pair_e[idx[k]] = dV * sum_s epart[k*nstrips + s]
+hipError_t launch_forward_f64(int mode, const Geom& g, const Plan& pl, const Eig& e,
+                              const double* src, const Item* items, int nitems, double* T,
+                              hipStream_t s);
+// epart receives one partial energy per 16-column strip: nitems * (slab/16)
+hipError_t launch_pencil_f64(const Geom& g, const Plan& pl, const Eig& e, const double* F,
+                             int nitems, double* T, double* epart, hipStream_t s);
+hipError_t launch_inverse_f64(int mode, const Geom& g, const Plan& pl, const Eig& e,
+                              const double* T, const Item* items, int nitems, const double* psi,
+                              const double* occ, double* dst, hipStream_t s);
+// per-item energies: pair_e[index(i, j)] = dV * sum_s epart[k*nstrips + s]
 hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* items, int nitems,
                               int norb, double dV, double* pair_e, hipStream_t s);
 // E_x = -1/4 sum_{i<=j} m_ij occ_i occ_j pair_e, m = 1 (i == j) or 2

@@ -25,9 +25,9 @@ constexpr int kJacobiThreads = 1024;
 //   c = 1/sqrt(1+t^2), s = t c;  A <- J^T A J,  V <- V J,
 //   J = I except J_pp = J_qq = c, J_pq = s, J_qp = -s.
 __global__ void __launch_bounds__(kJacobiThreads)
-jacobi_kernel(double* __restrict__ A, double* __restrict__ V, int n, int max_sweeps,
-              double* __restrict__ lam_pad, double* __restrict__ Vpad, double* __restrict__ VTpad,
-              int np, double* __restrict__ diag_out) {
+jacobi_kernel(double* __restrict__ A, double* __restrict__ V, int n, int max_sweeps, double rs,
+              int keep_row, double* __restrict__ lam_pad, double* __restrict__ Vpad,
+              double* __restrict__ VTpad, int np, double* __restrict__ diag_out) {
   __shared__ double cs[kMaxN / 2 + 1], sn[kMaxN / 2 + 1];
   __shared__ int pp[kMaxN / 2 + 1], qq[kMaxN / 2 + 1];
   __shared__ double lam_s[kMaxN];
@@ -127,7 +127,7 @@ jacobi_kernel(double* __restrict__ A, double* __restrict__ V, int n, int max_swe
     }
     lam_pad[rank] = lt;
     for (int i = 0; i < n; ++i) {
-      const double v = V[i * n + t];
+      const double v = V[i * n + t] * (i == keep_row ? 1.0 : rs);
       Vpad[i * np + rank] = v;
       VTpad[rank * np + i] = v;
     }
@@ -135,21 +135,39 @@ jacobi_kernel(double* __restrict__ A, double* __restrict__ V, int n, int max_swe
   if (tid == 0) diag_out[0] = (double)sweep;  // == max_sweeps: not converged
 }
 
-// f(lam1[a] + lam2[b] + lam3[c]) stored as F[c][a][b] (b fastest), zero on
+// f(lam1[a] + lam2[b] + lam3[c]) stored as F[c][a][b] (b fastest) with every
+// mode index parity-blocked (even modes first, odd modes after pe), zero on
 // padded indices.  Unscreened: 4 pi / lam.  Screened: (pi/w^2) g(x) with
 // x = lam/(4 w^2), g(x) = -expm1(-x)/x, g(0) = 1 (equal to
 // 4 pi (1 - exp(-lam/(4 w^2))) / lam without cancellation near lam = 0).
-__global__ void ftable_kernel(const double* __restrict__ lam1, const double* __restrict__ lam2,
-                              const double* __restrict__ lam3, Geom g, int kernel, double omega,
-                              double* __restrict__ F) {
+struct LamPtrs {
+  const double* e[3];
+  const double* o[3];
+};
+
+__device__ __forceinline__ bool blocked_lam(const LamPtrs& L, int axis, int idx, int me, int mo,
+                                            int pe, double& lam) {
+  if (idx < pe) {
+    if (idx >= me) return false;
+    lam = L.e[axis][idx];
+    return true;
+  }
+  idx -= pe;
+  if (idx >= mo) return false;
+  lam = L.o[axis][idx];
+  return true;
+}
+
+__global__ void ftable_kernel(LamPtrs L, Geom g, int kernel, double omega, double* __restrict__ F) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= g.slot) return;
+  if (idx >= g.fsize) return;
   const int b = (int)(idx % g.p2);
   const int a = (int)((idx / g.p2) % g.p1);
   const int c = (int)(idx / g.slab);
-  double f = 0.0;
-  if (a < g.n1 && b < g.n2 && c < g.n3) {
-    const double lam = lam1[a] + lam2[b] + lam3[c];
+  double l1, l2, l3, f = 0.0;
+  if (blocked_lam(L, 0, a, g.me1, g.mo1, g.pe1, l1) && blocked_lam(L, 1, b, g.me2, g.mo2, g.pe2, l2) &&
+      blocked_lam(L, 2, c, g.me3, g.mo3, g.pe3, l3)) {
+    const double lam = l1 + l2 + l3;
     if (kernel == KX_KERNEL_COULOMB) {
       f = 4.0 * M_PI / lam;
     } else {
@@ -161,47 +179,28 @@ __global__ void ftable_kernel(const double* __restrict__ lam1, const double* __r
   F[idx] = f;
 }
 
-// out2[0] = max |V^T V - I|, out2[1] unused; V padded np x np, first n used.
-__global__ void orth_kernel(const double* __restrict__ V, int n, int np, double* __restrict__ out2) {
-  __shared__ double red[256 / 64];
-  double worst = 0.0;
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    const int a = idx / n, b = idx % n;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += V[i * np + a] * V[i * np + b];
-    worst = fmax(worst, fabs(s - (a == b ? 1.0 : 0.0)));
-  }
-  for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = worst;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double w = 0.0;
-    for (int k = 0; k < (int)(blockDim.x / 64); ++k) w = fmax(w, red[k]);
-    out2[0] = w;
-  }
-}
-
 }  // namespace
 
-hipError_t launch_jacobi(double* A, double* V, int n, int max_sweeps, double* lam_pad, double* Vpad,
-                         double* VTpad, int np, double* diag_out, hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, s, A, V, n, max_sweeps,
-                     lam_pad, Vpad, VTpad, np, diag_out);
+hipError_t launch_jacobi(double* A, double* V, int n, int max_sweeps, double rs, int keep_row,
+                         double* lam_pad, double* Vpad, double* VTpad, int np, double* diag_out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacobiThreads), 0, s, A, V, n, max_sweeps, rs,
+                     keep_row, lam_pad, Vpad, VTpad, np, diag_out);
   return hipGetLastError();
 }
 
-hipError_t launch_ftable(const double* lam1, const double* lam2, const double* lam3, const Geom& g,
+hipError_t launch_ftable(const double* const lamE[3], const double* const lamO[3], const Geom& g,
                          int kernel, double omega, double* F, hipStream_t s) {
-  const long long total = g.slot;
+  LamPtrs L;
+  for (int k = 0; k < 3; ++k) {
+    L.e[k] = lamE[k];
+    L.o[k] = lamO[k];
+  }
+  const long long total = g.fsize;
   const int threads = 256;
   const long long blocks = (total + threads - 1) / threads;
-  hipLaunchKernelGGL(ftable_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, lam1, lam2, lam3,
-                     g, kernel, omega, F);
-  return hipGetLastError();
-}
-
-hipError_t launch_check_orth(const double* V, int n, int np, double* out2, hipStream_t s) {
-  hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(256), 0, s, V, n, np, out2);
+  hipLaunchKernelGGL(ftable_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, L, g, kernel,
+                     omega, F);
   return hipGetLastError();
 }
 
