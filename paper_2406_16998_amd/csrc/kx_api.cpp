@@ -103,7 +103,7 @@ struct kx_grid {
   int bc[3];
   hipStream_t stream;
   Geom geom;
-  Plan plan;
+  Plan plan_d, plan_f;  // launch shapes for double / float operands
   // eigensystems (device): padded V, V^T, lambda per axis
   // folded eigen-blocks per axis (device): even / odd halves and transposes
   double* dVE[3] = {nullptr, nullptr, nullptr};
@@ -112,6 +112,11 @@ struct kx_grid {
   double* dVOT[3] = {nullptr, nullptr, nullptr};
   double* dLamE[3] = {nullptr, nullptr, nullptr};
   double* dLamO[3] = {nullptr, nullptr, nullptr};
+  // the same blocks rounded to float, for FP32 mode products
+  float* fVE[3] = {nullptr, nullptr, nullptr};
+  float* fVO[3] = {nullptr, nullptr, nullptr};
+  float* fVET[3] = {nullptr, nullptr, nullptr};
+  float* fVOT[3] = {nullptr, nullptr, nullptr};
   // full eigensystem per axis (host), lam ascending, V[i*n + a]
   std::vector<double> lam_host[3];
   std::vector<double> V_host[3];
@@ -171,8 +176,8 @@ void dev_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
-Eig eig_of(const kx_grid* g) {
-  Eig e;
+EigR<double> eig_of(const kx_grid* g) {
+  EigR<double> e;
   for (int k = 0; k < 3; ++k) {
     e.VE[k] = g->dVE[k];
     e.VO[k] = g->dVO[k];
@@ -181,6 +186,19 @@ Eig eig_of(const kx_grid* g) {
   }
   return e;
 }
+
+EigR<float> eigf_of(const kx_grid* g) {
+  EigR<float> e;
+  for (int k = 0; k < 3; ++k) {
+    e.VE[k] = g->fVE[k];
+    e.VO[k] = g->fVO[k];
+    e.VET[k] = g->fVET[k];
+    e.VOT[k] = g->fVOT[k];
+  }
+  return e;
+}
+
+size_t elem_size(int dtype) { return dtype == KX_F64 ? sizeof(double) : sizeof(float); }
 
 bool all_periodic(const kx_grid* g) {
   return g->bc[0] == KX_BC_PERIODIC && g->bc[1] == KX_BC_PERIODIC && g->bc[2] == KX_BC_PERIODIC;
@@ -202,7 +220,7 @@ kx_status check_kernel_args(const kx_grid* g, int kernel, double omega) {
 kx_status check_types(int dtype, int prec) {
   if (dtype != KX_F64 && dtype != KX_F32) return KX_ERR_INVALID_ARG;
   if (prec < KX_PREC_FP64 || prec > KX_PREC_FP16X3) return KX_ERR_INVALID_ARG;
-  if (dtype != KX_F64 || prec != KX_PREC_FP64) return KX_ERR_UNSUPPORTED;
+  if (prec != KX_PREC_FP64 && prec != KX_PREC_FP32) return KX_ERR_UNSUPPORTED;
   return KX_OK;
 }
 
@@ -258,6 +276,56 @@ hipError_t timed(kx_grid* g, int kind, F&& launch) {
   e = hipEventRecord(g->prof_ev[2 * k + 1], g->stream);
   g->prof_kind.push_back(kind);
   return e;
+}
+
+// One batch of nb items through the three transform passes (and, for the
+// exchange, the per-pair energy reduction), in the arithmetic of prec.
+hipError_t run_batch(kx_grid* g, int mode, int prec, int dtype, const void* src, const Item* it,
+                     int nb, const void* psi, const double* occ, void* dst, int norb, double dV) {
+  const Geom& G = g->geom;
+  double* epart = mode == 1 ? g->dEpart : nullptr;
+  const int nstrips = (int)(G.slab / kTile);
+  hipError_t e;
+  if (prec == KX_PREC_FP64) {
+    const EigR<double> E = eig_of(g);
+    double* T = (double*)g->dT;
+    e = timed(g, KX_PHASE_FORWARD, [&] {
+      return launch_forward_d(dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, g->stream);
+    });
+    if (e != hipSuccess) return e;
+    e = timed(g, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, epart, g->stream);
+    });
+    if (e != hipSuccess) return e;
+    if (mode == 1) {
+      e = timed(g, KX_PHASE_ENERGY, [&] {
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
+      });
+      if (e != hipSuccess) return e;
+    }
+    return timed(g, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_d(dtype, mode, G, g->plan_d.inv, E, T, it, nb, psi, occ, dst, g->stream);
+    });
+  }
+  const EigR<float> E = eigf_of(g);
+  float* T = (float*)g->dT;
+  e = timed(g, KX_PHASE_FORWARD, [&] {
+    return launch_forward_f(dtype, mode, G, g->plan_f.fwd, E, src, it, nb, T, g->stream);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(g, KX_PHASE_PENCIL, [&] {
+    return launch_pencil_f(G, g->plan_f.pen, E, g->dF, nb, T, epart, g->stream);
+  });
+  if (e != hipSuccess) return e;
+  if (mode == 1) {
+    e = timed(g, KX_PHASE_ENERGY, [&] {
+      return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
+    });
+    if (e != hipSuccess) return e;
+  }
+  return timed(g, KX_PHASE_INVERSE, [&] {
+    return launch_inverse_f(dtype, mode, G, g->plan_f.inv, E, T, it, nb, psi, occ, dst, g->stream);
+  });
 }
 
 kx_status upload_items(kx_grid* g, int kind, int key, int maxb, const std::vector<Item>& items) {
@@ -382,10 +450,12 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
         lds > 0) {
-      g->plan = make_plan(G, (size_t)lds);
+      g->plan_d = make_plan(G, (size_t)lds, sizeof(double));
+      g->plan_f = make_plan(G, (size_t)lds, sizeof(float));
     } else {
       (void)hipGetLastError();
-      g->plan = make_plan(G, 64 * 1024);
+      g->plan_d = make_plan(G, 64 * 1024, sizeof(double));
+      g->plan_f = make_plan(G, 64 * 1024, sizeof(float));
     }
   }
   if (const char* env = std::getenv("KX_MAX_SLOTS")) {
@@ -483,6 +553,36 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
         return fail(KX_ERR_NUMERIC);
       }
     }
+    // float copies of the half blocks and their transposes
+    {
+      const int pes = pe * pe, pos = std::max(po * po, 1);
+      std::vector<float> fe(pes), fet(pes), fo(pos, 0.0f), fot(pos, 0.0f);
+      for (int i = 0; i < pe; ++i)
+        for (int a = 0; a < pe; ++a) {
+          fe[(size_t)i * pe + a] = (float)VE[(size_t)i * pe + a];
+          fet[(size_t)a * pe + i] = (float)VE[(size_t)i * pe + a];
+        }
+      for (int i = 0; i < po; ++i)
+        for (int a = 0; a < po; ++a) {
+          fo[(size_t)i * po + a] = (float)VO[(size_t)i * po + a];
+          fot[(size_t)a * po + i] = (float)VO[(size_t)i * po + a];
+        }
+      if (dev_alloc((void**)&g->fVE[k], sizeof(float) * pes) != KX_OK ||
+          dev_alloc((void**)&g->fVET[k], sizeof(float) * pes) != KX_OK ||
+          dev_alloc((void**)&g->fVO[k], sizeof(float) * pos) != KX_OK ||
+          dev_alloc((void**)&g->fVOT[k], sizeof(float) * pos) != KX_OK) {
+        cleanup();
+        return fail(KX_ERR_OUT_OF_MEMORY);
+      }
+      if (hipMemcpy(g->fVE[k], fe.data(), sizeof(float) * pes, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(g->fVET[k], fet.data(), sizeof(float) * pes, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(g->fVO[k], fo.data(), sizeof(float) * pos, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(g->fVOT[k], fot.data(), sizeof(float) * pos, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(KX_ERR_DEVICE);
+      }
+    }
     // unfold into the full eigensystem (host copy), sorted by eigenvalue
     std::vector<std::pair<double, int>> order;
     for (int a = 0; a < me; ++a) order.push_back({lamE[a], a});
@@ -544,6 +644,10 @@ kx_status kx_destroy(kx_grid* g) {
     dev_free(g->dVOT[k]);
     dev_free(g->dLamE[k]);
     dev_free(g->dLamO[k]);
+    dev_free(g->fVE[k]);
+    dev_free(g->fVO[k]);
+    dev_free(g->fVET[k]);
+    dev_free(g->fVOT[k]);
   }
   dev_free(g->dF);
   dev_free(g->dT);
@@ -581,20 +685,10 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   for (int b = 0; b < batch; ++b) items[b] = {b, -1};
   st = upload_items(g, 0, batch, chunk, items);
   if (st != KX_OK) return st;
-  const Eig e = eig_of(g);
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
-    const Item* it = g->dItems + b0;
-    KX_HIP(timed(g, KX_PHASE_FORWARD, [&] {
-      return launch_forward_f64(0, g->geom, g->plan, e, (const double*)rho_dev, it, nb, g->dT, g->stream);
-    }));
-    KX_HIP(timed(g, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_f64(g->geom, g->plan, e, g->dF, nb, g->dT, nullptr, g->stream);
-    }));
-    KX_HIP(timed(g, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_f64(0, g->geom, g->plan, e, g->dT, it, nb, nullptr, nullptr, (double*)phi_dev,
-                                g->stream);
-    }));
+    KX_HIP(run_batch(g, 0, prec, dtype, rho_dev, g->dItems + b0, nb, nullptr, nullptr, phi_dev, 0,
+                     0.0));
   }
   return KX_OK;
 }
@@ -666,29 +760,14 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
   std::memcpy(g->hOcc, occ_host, sizeof(double) * norb);
   KX_HIP(hipMemcpyAsync(g->dOcc, g->hOcc, sizeof(double) * norb, hipMemcpyHostToDevice, g->stream));
   KX_HIP(hipEventRecord(g->occ_done, g->stream));
-  KX_HIP(hipMemsetAsync(vxpsi_dev, 0, sizeof(double) * (size_t)norb * g->geom.N, g->stream));
+  KX_HIP(hipMemsetAsync(vxpsi_dev, 0, elem_size(dtype) * (size_t)norb * g->geom.N, g->stream));
 
-  const Eig e = eig_of(g);
   const double dV = g->h[0] * g->h[1] * g->h[2];
-  const int nstrips = (int)(g->geom.slab / kTile);
-  const double* psi = (const double*)psi_dev;
-  double* vx = (double*)vxpsi_dev;
   for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
     const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
     if (nb <= 0) continue;
-    const Item* it = g->dItems + o0;
-    KX_HIP(timed(g, KX_PHASE_FORWARD, [&] {
-      return launch_forward_f64(1, g->geom, g->plan, e, psi, it, nb, g->dT, g->stream);
-    }));
-    KX_HIP(timed(g, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_f64(g->geom, g->plan, e, g->dF, nb, g->dT, g->dEpart, g->stream);
-    }));
-    KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
-      return launch_pair_energy(g->dEpart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
-    }));
-    KX_HIP(timed(g, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_f64(1, g->geom, g->plan, e, g->dT, it, nb, psi, g->dOcc, vx, g->stream);
-    }));
+    KX_HIP(run_batch(g, 1, prec, dtype, psi_dev, g->dItems + o0, nb, psi_dev, g->dOcc, vxpsi_dev,
+                     norb, dV));
   }
   KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
     return launch_exchange_energy(g->dPairE, g->dOcc, norb, g->dEx, g->stream);

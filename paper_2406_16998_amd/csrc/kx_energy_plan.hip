@@ -1,0 +1,142 @@
+// Deterministic energy reductions and the launch-shape planner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kx_internal.h"
+
+namespace kx {
+namespace {
+// ================================================================ energies
+constexpr int kRedThreads = 256;
+
+__device__ double block_sum_fixed(double v, double* red) {
+  // fixed shape: wave tree, then waves summed in index order by thread 0
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  }
+  return s;
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+pair_energy_kernel(const double* __restrict__ epart, int nstrips, const Item* __restrict__ items,
+                   int norb, double dV, double* __restrict__ pair_e) {
+  __shared__ double red[kRedThreads / 64];
+  const int it = blockIdx.x;
+  const double* __restrict__ p = epart + (long long)it * nstrips;
+  double v = 0.0;
+  for (int s = threadIdx.x; s < nstrips; s += blockDim.x) v += p[s];
+  const double tot = block_sum_fixed(v, red);
+  if (threadIdx.x == 0) {
+    const Item item = items[it];
+    const int i = item.i < item.j ? item.i : item.j;
+    const int j = item.i < item.j ? item.j : item.i;
+    pair_e[pair_index(i, j, norb)] = dV * tot;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+exchange_energy_kernel(const double* __restrict__ pair_e, const double* __restrict__ occ, int norb,
+                       double* __restrict__ ex) {
+  __shared__ double red[kRedThreads / 64];
+  const long long npairs = (long long)norb * (norb + 1) / 2;
+  double v = 0.0;
+  int i = 0;
+  long long row_end = norb;  // first pair index of row i+1
+  for (long long p = threadIdx.x; p < npairs; p += blockDim.x) {
+    while (p >= row_end) {
+      ++i;
+      row_end += norb - i;
+    }
+    const int j = (int)(p - (row_end - (norb - i))) + i;
+    const double m = (i == j) ? 1.0 : 2.0;
+    v += m * occ[i] * occ[j] * pair_e[p];
+  }
+  const double tot = block_sum_fixed(v, red);
+  if (threadIdx.x == 0) ex[0] = -0.25 * tot;
+}
+
+}  // namespace
+
+// ================================================================ planning
+Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
+  Plan pl;
+  const int ntx = g.pe1 / kTile;  // forward register tiles (x' / a)
+  const int nty = g.pe2 / kTile;  // inverse register tiles (b / y')
+  // forward: waves per slab = 2 * p2/16 (both x parities) or p2/16 (split)
+  {
+    SlabPlan& f = pl.fwd;
+    const int maxw = fwd_mt(ntx) / 64;
+    int wps = 2 * (g.p2 / kTile);
+    f.qsplit = 1;
+    if (wps > maxw) {
+      f.qsplit = 2;
+      wps /= 2;
+    }
+    f.slabs = 1;
+    while (f.slabs * 2 * wps <= maxw && (f.slabs * wps) % 4 != 0) f.slabs *= 2;
+    f.waves = f.slabs * wps;
+    const int wrow = f.qsplit == 1 ? g.p1 : g.pe1;
+    const size_t vb = (size_t)(f.qsplit == 1 ? g.pe1 * g.pe1 + g.po1 * g.po1 : g.pe1 * g.pe1) * esize;
+    f.kc = 4;
+    for (int c : {32, 16, 8, 4}) {
+      if ((size_t)c * g.pe1 <= (size_t)kFwdPos * wps * 64 &&
+          (size_t)f.slabs * 2 * 2 * c * wrow * esize + vb <= max_lds) {
+        f.kc = c;
+        break;
+      }
+    }
+    const size_t chunk = (size_t)f.slabs * 2 * 2 * f.kc * wrow * esize;
+    f.vlds = chunk + vb <= max_lds;
+    f.lds_bytes = chunk + (f.vlds ? vb : 0);
+  }
+  // inverse: waves per slab = pe1/16
+  {
+    SlabPlan& v = pl.inv;
+    const int maxw = inv_mt(nty) / 64;
+    const int wps = g.pe1 / kTile;
+    v.slabs = 1;
+    while ((v.slabs + 1) * wps <= maxw && (v.slabs * wps) % 4 != 0) ++v.slabs;
+    v.waves = v.slabs * wps;
+    const size_t vb = (size_t)(g.pe2 * g.pe2 + g.po2 * g.po2) * esize;
+    v.kc = 4;
+    for (int c : {16, 8, 4}) {
+      if ((size_t)2 * c * g.p2 <= (size_t)kInvEl * wps * 64 &&
+          (size_t)v.slabs * 2 * 2 * c * g.p2 * esize + vb <= max_lds) {
+        v.kc = c;
+        break;
+      }
+    }
+    const size_t chunk = (size_t)v.slabs * 2 * 2 * v.kc * g.p2 * esize;
+    v.vlds = chunk + vb <= max_lds;
+    v.lds_bytes = chunk + (v.vlds ? vb : 0);
+  }
+  {
+    PencilPlan& p = pl.pen;
+    p.waves = 8;
+    const size_t vb = (size_t)(g.pe3 * (g.pe3 + 1) + g.po3 * (g.po3 + 1)) * esize;
+    p.lds_bytes = vb <= max_lds ? vb : 0;
+  }
+  return pl;
+}
+
+hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* items, int nitems,
+                              int norb, double dV, double* pair_e, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pair_energy_kernel, dim3(nitems), dim3(kRedThreads), 0, s, epart, nstrips,
+                     items, norb, dV, pair_e);
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange_energy(const double* pair_e, const double* occ, int norb, double* ex,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(exchange_energy_kernel, dim3(1), dim3(kRedThreads), 0, s, pair_e, occ, norb,
+                     ex);
+  return hipGetLastError();
+}
+
+}  // namespace kx

@@ -42,16 +42,26 @@ struct Geom {
   long long fsize;    // p3*slab: the f table, [c][a][b]
 };
 
-// Device copies of the half eigenvector blocks, zero padded:
+// Device copies of the half eigenvector blocks, zero padded, in the operand
+// type R of the mode products:
 //   VE[k] [i][a] row-major pe_k x pe_k (i < me_k spatial, a < me_k mode)
 //   VO[k] [i][a] row-major po_k x po_k
 //   VET, VOT their transposes.
-struct Eig {
-  const double* VE[3];
-  const double* VO[3];
-  const double* VET[3];
-  const double* VOT[3];
+template <class R>
+struct EigR {
+  const R* VE[3];
+  const R* VO[3];
+  const R* VET[3];
+  const R* VOT[3];
 };
+
+// Staging budgets of the slab kernels and their launch bounds (threads per
+// workgroup) by register tile count NT, shared by kernels and planner.
+constexpr int kFwdPos = 2;  // folded positions staged per thread per chunk (forward)
+constexpr int kInvEl = 8;   // elements staged per thread per chunk (inverse)
+constexpr int fwd_mt(int nt) { return nt <= 3 ? 1024 : (nt == 4 ? 768 : 640); }
+constexpr int inv_mt(int nt) { return nt <= 2 ? 1024 : (nt == 3 ? 768 : 512); }
+constexpr int pen_mt(int nt) { return nt <= 2 ? 1024 : 512; }
 
 // One item of a transform batch: an orbital pair (i, j) for the exchange,
 // (b, -1) with b the field index for apply_fL.
@@ -76,7 +86,8 @@ struct Plan {
   SlabPlan fwd, inv;
   PencilPlan pen;
 };
-Plan make_plan(const Geom& g, size_t max_lds);
+// esize: bytes per element of the mode-product operands (8 or 4)
+Plan make_plan(const Geom& g, size_t max_lds, size_t esize);
 
 // ---- set-up kernels (kx_setup.hip) ----
 // Jacobi eigensolver of the symmetric n x n matrix A (global memory); writes
@@ -89,17 +100,27 @@ hipError_t launch_jacobi(double* A, double* V, int n, int max_sweeps, double rs,
 hipError_t launch_ftable(const double* const lamE[3], const double* const lamO[3], const Geom& g,
                          int kernel, double omega, double* F, hipStream_t s);
 
-// ---- FP64 transform kernels (kx_fold64.hip) ----
-// mode: 0 = apply_fL (rho -> phi), 1 = exchange (psi -> vxpsi)
-hipError_t launch_forward_f64(int mode, const Geom& g, const Plan& pl, const Eig& e,
-                              const double* src, const Item* items, int nitems, double* T,
-                              hipStream_t s);
-// epart receives one partial energy per 16-column strip: nitems * (slab/16)
-hipError_t launch_pencil_f64(const Geom& g, const Plan& pl, const Eig& e, const double* F,
-                             int nitems, double* T, double* epart, hipStream_t s);
-hipError_t launch_inverse_f64(int mode, const Geom& g, const Plan& pl, const Eig& e,
-                              const double* T, const Item* items, int nitems, const double* psi,
-                              const double* occ, double* dst, hipStream_t s);
+// ---- transform kernels (kx_fold_d.hip: double operands, kx_fold_f.hip: float)
+// mode: 0 = apply_fL (rho -> phi), 1 = exchange (psi -> vxpsi);
+// storage: KX_F64 / KX_F32 element type of src / psi / dst.
+// The pencil pass writes one partial energy per 16-column strip into epart
+// (nitems * slab/16 values) when epart is not null.
+hipError_t launch_forward_d(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigR<double>& e, const void* src, const Item* items, int nitems,
+                            double* T, hipStream_t s);
+hipError_t launch_pencil_d(const Geom& g, const PencilPlan& p, const EigR<double>& e,
+                           const double* F, int nitems, double* T, double* epart, hipStream_t s);
+hipError_t launch_inverse_d(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigR<double>& e, const double* T, const Item* items, int nitems,
+                            const void* psi, const double* occ, void* dst, hipStream_t s);
+hipError_t launch_forward_f(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigR<float>& e, const void* src, const Item* items, int nitems,
+                            float* T, hipStream_t s);
+hipError_t launch_pencil_f(const Geom& g, const PencilPlan& p, const EigR<float>& e,
+                           const double* F, int nitems, float* T, double* epart, hipStream_t s);
+hipError_t launch_inverse_f(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigR<float>& e, const float* T, const Item* items, int nitems,
+                            const void* psi, const double* occ, void* dst, hipStream_t s);
 // per-item energies: pair_e[index(i, j)] = dV * sum_s epart[k*nstrips + s]
 hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* items, int nitems,
                               int norb, double dV, double* pair_e, hipStream_t s);

@@ -226,3 +226,72 @@ def test_error_statuses_on_device(torch_cuda):
     L = kx.lib()
     assert L.kx_apply_fL(g._h, 1, 0.1, 0, 0, None, None, 0) == 0  # empty batch is a no-op
     g.close()
+
+
+# ------------------------------------------------------------------ reduced precision
+# FP32 mode products: unit roundoff 2^-24 ~ 6e-8, K <= 80 per product, six
+# products in sequence -> a few 1e-6 relative per element in the worst case;
+# the energy sums many independent roundings and is tighter.
+TOL32_FIELD = 1e-5
+TOL32_ENERGY = 1e-6
+
+
+@pytest.mark.parametrize("n,h,order,bc,kernel,omega", FL_CASES[:5])
+def test_apply_fL_fp32_arithmetic(torch_cuda, n, h, order, bc, kernel, omega):
+    torch = torch_cuda
+    kx = _kx()
+    rho = random_fields(n, 2, seed=sum(n) + 1)
+    g = kx.Grid(n, h, order, bc)
+    phi = g.apply_fL(torch.from_numpy(rho).cuda(), kernel, omega, prec="fp32").cpu().numpy()
+    g.close()
+    ref = orc.apply_fL(rho, orc.make_grid(n, h, order, bc), kernel, omega)
+    for b in range(2):
+        assert _rel(phi[b], ref[b]) <= TOL32_FIELD
+
+
+@pytest.mark.parametrize("name", ["mixed40x36x44_erfc", "dirichlet32_coulomb"])
+def test_exchange_fp32_arithmetic(torch_cuda, name):
+    torch = torch_cuda
+    kx = _kx()
+    w, psi, occ = make_workload(name)
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    vx = g.apply_exchange(torch.from_numpy(psi).cuda(), occ, w.kernel, w.omega, prec="fp32")
+    ex = g.exchange_energy()
+    vx = vx.cpu().numpy()
+    g.close()
+    vx_ref, ex_ref = orc.exchange(psi, occ, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
+    print(f"fp32 {name}: dE/E={abs(ex - ex_ref) / abs(ex_ref):.2e}", flush=True)
+    assert abs(ex - ex_ref) <= TOL32_ENERGY * abs(ex_ref)
+    for j in range(w.norb):
+        assert _rel(vx[j], vx_ref[j]) <= TOL32_FIELD, j
+
+
+def test_exchange_f32_storage_fp64_arithmetic(torch_cuda):
+    """Orbitals stored as float32 (promoted exactly to FP64 by the oracle),
+    FP64 mode products; Vx psi is rounded to float32 on output."""
+    torch = torch_cuda
+    kx = _kx()
+    w, psi, occ = make_workload("mixed40x36x44_erfc")
+    psi32 = psi.astype(np.float32)
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    vx = g.apply_exchange(torch.from_numpy(psi32).cuda(), occ, w.kernel, w.omega, prec="fp64")
+    ex = g.exchange_energy()
+    assert vx.dtype == torch.float32
+    vx = vx.cpu().numpy().astype(np.float64)
+    g.close()
+    grid = orc.make_grid(w.n, w.h, w.order, w.bc)
+    vx_ref, ex_ref = orc.exchange(psi32.astype(np.float64), occ, grid, w.kernel, w.omega)
+    assert abs(ex - ex_ref) <= TOL64 * abs(ex_ref)
+    for j in range(w.norb):
+        assert _rel(vx[j], vx_ref[j]) <= 1e-6, j
+
+
+def test_unsupported_precision_reports_status(torch_cuda):
+    torch = torch_cuda
+    kx = _kx()
+    g = kx.Grid((16, 16, 16), (0.3,) * 3, 12, ("dirichlet",) * 3)
+    rho = torch.zeros((1, 16, 16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(kx.KxError) as e:
+        g.apply_fL(rho, "coulomb", prec="fp16x3")
+    assert e.value.status == 2
+    g.close()
