@@ -87,7 +87,12 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
 /* phi = f(-L) rho for a batch of fields (Eqs. (20)-(21)).
  *   kernel, omega  see above; omega > 0 required for KX_KERNEL_ERFC
  *   batch          number of fields, >= 0 (0 is a no-op)
- *   dtype, prec    storage and arithmetic (this build: KX_F64 with KX_PREC_FP64)
+ *   dtype          storage of rho / phi: KX_F64 or KX_F32
+ *   prec           arithmetic of the mode products: KX_PREC_FP64, KX_PREC_FP32
+ *                  or KX_PREC_BF16X3 (KX_PREC_FP16X3: KX_ERR_UNSUPPORTED).
+ *                  FP64 and FP32 also return KX_ERR_UNSUPPORTED on grids whose
+ *                  y extent exceeds about four times the x extent (staging
+ *                  limit of their inverse pass); BF16X3 has no shape limit.
  *   rho_dev        batch*N input values;  phi_dev  batch*N outputs (overwritten)
  * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic. */
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
@@ -99,6 +104,7 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
  * updates orbital j and, if i != j, orbital i.  occ_host[norb] are the
  * spin-summed occupations used as literal weights (a closed shell with
  * occ = 2 gives twice the per-spin operator of Eq. (3)).
+ *   dtype, prec  as for kx_apply_fL
  *   psi_dev    norb*N orbitals (read only)
  *   vxpsi_dev  norb*N outputs, overwritten (not accumulated into)
  * Also prepares E_x = -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h with

@@ -103,7 +103,7 @@ struct kx_grid {
   int bc[3];
   hipStream_t stream;
   Geom geom;
-  Plan plan_d, plan_f;  // launch shapes for double / float operands
+  Plan plan_d, plan_f, plan_s;  // launch shapes: double / float / split-bf16 operands
   // eigensystems (device): padded V, V^T, lambda per axis
   // folded eigen-blocks per axis (device): even / odd halves and transposes
   double* dVE[3] = {nullptr, nullptr, nullptr};
@@ -117,6 +117,11 @@ struct kx_grid {
   float* fVO[3] = {nullptr, nullptr, nullptr};
   float* fVET[3] = {nullptr, nullptr, nullptr};
   float* fVOT[3] = {nullptr, nullptr, nullptr};
+  // the same blocks as three-term bf16 splits, for the split-BF16 products
+  short* sVE[3] = {nullptr, nullptr, nullptr};
+  short* sVO[3] = {nullptr, nullptr, nullptr};
+  short* sVET[3] = {nullptr, nullptr, nullptr};
+  short* sVOT[3] = {nullptr, nullptr, nullptr};
   // full eigensystem per axis (host), lam ascending, V[i*n + a]
   std::vector<double> lam_host[3];
   std::vector<double> V_host[3];
@@ -198,6 +203,48 @@ EigR<float> eigf_of(const kx_grid* g) {
   return e;
 }
 
+EigS eigs_of(const kx_grid* g) {
+  EigS e;
+  for (int k = 0; k < 3; ++k) {
+    e.E[k] = g->sVE[k];
+    e.O[k] = g->sVO[k];
+    e.ET[k] = g->sVET[k];
+    e.OT[k] = g->sVOT[k];
+  }
+  return e;
+}
+
+// bf16 bit pattern of x, rounded to nearest even (x finite)
+short bf16_rne(double x) {
+  const float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(uint16_t)(u >> 16);
+}
+double bf16_to_double(short b) {
+  const uint32_t u = (uint32_t)(uint16_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, sizeof f);
+  return f;
+}
+
+// Three bf16 planes of an n x n block: x ~ x0 + x1 + x2 with x0 = bf16(x),
+// x1 = bf16(x - x0), x2 = bf16(x - x0 - x1), residuals taken in FP64.
+std::vector<short> split3(const std::vector<double>& a, int n) {
+  const size_t m = (size_t)n * n;
+  std::vector<short> out(3 * std::max<size_t>(m, 1), 0);
+  for (size_t i = 0; i < m; ++i) {
+    double r = a[i];
+    for (int s = 0; s < 3; ++s) {
+      const short b = bf16_rne(r);
+      out[s * m + i] = b;
+      r -= bf16_to_double(b);
+    }
+  }
+  return out;
+}
+
 size_t elem_size(int dtype) { return dtype == KX_F64 ? sizeof(double) : sizeof(float); }
 
 bool all_periodic(const kx_grid* g) {
@@ -217,10 +264,12 @@ kx_status check_kernel_args(const kx_grid* g, int kernel, double omega) {
   return KX_OK;
 }
 
-kx_status check_types(int dtype, int prec) {
+kx_status check_types(const kx_grid* g, int dtype, int prec) {
   if (dtype != KX_F64 && dtype != KX_F32) return KX_ERR_INVALID_ARG;
   if (prec < KX_PREC_FP64 || prec > KX_PREC_FP16X3) return KX_ERR_INVALID_ARG;
-  if (prec != KX_PREC_FP64 && prec != KX_PREC_FP32) return KX_ERR_UNSUPPORTED;
+  if (prec == KX_PREC_FP16X3) return KX_ERR_UNSUPPORTED;
+  const Plan& p = prec == KX_PREC_FP64 ? g->plan_d : (prec == KX_PREC_FP32 ? g->plan_f : g->plan_s);
+  if (!p.fwd.ok || !p.inv.ok) return KX_ERR_UNSUPPORTED;
   return KX_OK;
 }
 
@@ -305,6 +354,27 @@ hipError_t run_batch(kx_grid* g, int mode, int prec, int dtype, const void* src,
     }
     return timed(g, KX_PHASE_INVERSE, [&] {
       return launch_inverse_d(dtype, mode, G, g->plan_d.inv, E, T, it, nb, psi, occ, dst, g->stream);
+    });
+  }
+  if (prec == KX_PREC_BF16X3) {
+    const EigS E = eigs_of(g);
+    float* T = (float*)g->dT;
+    e = timed(g, KX_PHASE_FORWARD, [&] {
+      return launch_forward_s(dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, g->stream);
+    });
+    if (e != hipSuccess) return e;
+    e = timed(g, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_s(G, g->plan_s.pen, E, g->dF, nb, T, epart, g->stream);
+    });
+    if (e != hipSuccess) return e;
+    if (mode == 1) {
+      e = timed(g, KX_PHASE_ENERGY, [&] {
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
+      });
+      if (e != hipSuccess) return e;
+    }
+    return timed(g, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, E, T, it, nb, psi, occ, dst, g->stream);
     });
   }
   const EigR<float> E = eigf_of(g);
@@ -452,10 +522,12 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
         lds > 0) {
       g->plan_d = make_plan(G, (size_t)lds, sizeof(double));
       g->plan_f = make_plan(G, (size_t)lds, sizeof(float));
+      g->plan_s = make_split_plan(G, (size_t)lds);
     } else {
       (void)hipGetLastError();
       g->plan_d = make_plan(G, 64 * 1024, sizeof(double));
       g->plan_f = make_plan(G, 64 * 1024, sizeof(float));
+      g->plan_s = make_split_plan(G, 64 * 1024);
     }
   }
   if (const char* env = std::getenv("KX_MAX_SLOTS")) {
@@ -583,6 +655,37 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
         return fail(KX_ERR_DEVICE);
       }
     }
+    // three-term bf16 splits of the same blocks
+    {
+      std::vector<double> vet((size_t)pe * pe), vot((size_t)std::max(po * po, 1), 0.0);
+      std::vector<double> ve((size_t)pe * pe), vo((size_t)std::max(po * po, 1), 0.0);
+      for (int i = 0; i < pe; ++i)
+        for (int a = 0; a < pe; ++a) {
+          ve[(size_t)i * pe + a] = VE[(size_t)i * pe + a];
+          vet[(size_t)a * pe + i] = VE[(size_t)i * pe + a];
+        }
+      for (int i = 0; i < po; ++i)
+        for (int a = 0; a < po; ++a) {
+          vo[(size_t)i * po + a] = VO[(size_t)i * po + a];
+          vot[(size_t)a * po + i] = VO[(size_t)i * po + a];
+        }
+      const std::vector<short> se = split3(ve, pe), set = split3(vet, pe);
+      const std::vector<short> so = split3(vo, po), sot = split3(vot, po);
+      short** dst[4] = {&g->sVE[k], &g->sVET[k], &g->sVO[k], &g->sVOT[k]};
+      const std::vector<short>* srcs[4] = {&se, &set, &so, &sot};
+      for (int b = 0; b < 4; ++b) {
+        const size_t bytes = sizeof(short) * srcs[b]->size();
+        if (dev_alloc((void**)dst[b], bytes) != KX_OK) {
+          cleanup();
+          return fail(KX_ERR_OUT_OF_MEMORY);
+        }
+        if (hipMemcpy(*dst[b], srcs[b]->data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+          (void)hipGetLastError();
+          cleanup();
+          return fail(KX_ERR_DEVICE);
+        }
+      }
+    }
     // unfold into the full eigensystem (host copy), sorted by eigenvalue
     std::vector<std::pair<double, int>> order;
     for (int a = 0; a < me; ++a) order.push_back({lamE[a], a});
@@ -648,6 +751,10 @@ kx_status kx_destroy(kx_grid* g) {
     dev_free(g->fVO[k]);
     dev_free(g->fVET[k]);
     dev_free(g->fVOT[k]);
+    dev_free(g->sVE[k]);
+    dev_free(g->sVO[k]);
+    dev_free(g->sVET[k]);
+    dev_free(g->sVOT[k]);
   }
   dev_free(g->dF);
   dev_free(g->dT);
@@ -669,7 +776,7 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   if (!g || batch < 0) return KX_ERR_INVALID_ARG;
   kx_status st = check_kernel_args(g, kernel, omega);
   if (st != KX_OK) return st;
-  st = check_types(dtype, prec);
+  st = check_types(g, dtype, prec);
   if (st != KX_OK) return st;
   if (batch == 0) return KX_OK;
   if (!rho_dev || !phi_dev) return KX_ERR_INVALID_ARG;
@@ -699,7 +806,7 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
   if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
   kx_status st = check_kernel_args(g, kernel, omega);
   if (st != KX_OK) return st;
-  st = check_types(dtype, prec);
+  st = check_types(g, dtype, prec);
   if (st != KX_OK) return st;
   if (norb > 0 && (!psi_dev || !vxpsi_dev || !occ_host)) return KX_ERR_INVALID_ARG;
   if (psi_dev && psi_dev == vxpsi_dev) return KX_ERR_INVALID_ARG;

@@ -82,14 +82,20 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     f.waves = f.slabs * wps;
     const int wrow = f.qsplit == 1 ? g.p1 : g.pe1;
     const size_t vb = (size_t)(f.qsplit == 1 ? g.pe1 * g.pe1 + g.po1 * g.po1 : g.pe1 * g.pe1) * esize;
-    f.kc = 4;
-    for (int c : {32, 16, 8, 4}) {
-      if ((size_t)c * g.pe1 <= (size_t)kFwdPos * wps * 64 &&
-          (size_t)f.slabs * 2 * 2 * c * wrow * esize + vb <= max_lds) {
-        f.kc = c;
-        break;
+    // every staged position of a chunk must have a register slot
+    f.kc = 0;
+    for (size_t extra : {vb, (size_t)0}) {
+      for (int c : {32, 16, 8, 4}) {
+        if ((size_t)c * g.pe1 <= (size_t)kFwdPos * wps * 64 &&
+            (size_t)f.slabs * 2 * 2 * c * wrow * esize + extra <= max_lds) {
+          f.kc = c;
+          break;
+        }
       }
+      if (f.kc) break;
     }
+    f.ok = f.kc != 0;
+    if (!f.ok) f.kc = 4;
     const size_t chunk = (size_t)f.slabs * 2 * 2 * f.kc * wrow * esize;
     f.vlds = chunk + vb <= max_lds;
     f.lds_bytes = chunk + (f.vlds ? vb : 0);
@@ -103,14 +109,20 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     while ((v.slabs + 1) * wps <= maxw && (v.slabs * wps) % 4 != 0) ++v.slabs;
     v.waves = v.slabs * wps;
     const size_t vb = (size_t)(g.pe2 * g.pe2 + g.po2 * g.po2) * esize;
-    v.kc = 4;
-    for (int c : {16, 8, 4}) {
-      if ((size_t)2 * c * g.p2 <= (size_t)kInvEl * wps * 64 &&
-          (size_t)v.slabs * 2 * 2 * c * g.p2 * esize + vb <= max_lds) {
-        v.kc = c;
-        break;
+    // every staged element of a chunk must have a register slot
+    v.kc = 0;
+    for (size_t extra : {vb, (size_t)0}) {
+      for (int c : {16, 8, 4}) {
+        if ((size_t)2 * c * g.p2 <= (size_t)kInvEl * wps * 64 &&
+            (size_t)v.slabs * 2 * 2 * c * g.p2 * esize + extra <= max_lds) {
+          v.kc = c;
+          break;
+        }
       }
+      if (v.kc) break;
     }
+    v.ok = v.kc != 0;
+    if (!v.ok) v.kc = 4;
     const size_t chunk = (size_t)v.slabs * 2 * 2 * v.kc * g.p2 * esize;
     v.vlds = chunk + vb <= max_lds;
     v.lds_bytes = chunk + (v.vlds ? vb : 0);

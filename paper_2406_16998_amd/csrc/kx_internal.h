@@ -55,6 +55,18 @@ struct EigR {
   const R* VOT[3];
 };
 
+// Pre-split copies of the same blocks for the split-BF16 products: each is
+// three bf16 planes (bit patterns) of pe_k x pe_k (po_k x po_k) elements,
+// plane s at offset s * pe_k^2, with V ~ plane0 + plane1 + plane2.
+//   E[k] = split(VE[k]) [i][a],  O[k] = split(VO[k]),
+//   ET[k] = split(VET[k]) [a][i], OT[k] = split(VOT[k]).
+struct EigS {
+  const short* E[3];
+  const short* O[3];
+  const short* ET[3];
+  const short* OT[3];
+};
+
 // Staging budgets of the slab kernels and their launch bounds (threads per
 // workgroup) by register tile count NT, shared by kernels and planner.
 constexpr int kFwdPos = 2;  // folded positions staged per thread per chunk (forward)
@@ -77,6 +89,7 @@ struct SlabPlan {
   int qsplit = 1;     // forward: 2 = one x-parity per workgroup
   bool vlds = false;  // the second product's V blocks resident in LDS
   size_t lds_bytes = 0;
+  bool ok = true;     // false: the grid's shape does not fit these kernels
 };
 struct PencilPlan {
   int waves = 8;
@@ -120,6 +133,16 @@ hipError_t launch_pencil_f(const Geom& g, const PencilPlan& p, const EigR<float>
                            const double* F, int nitems, float* T, double* epart, hipStream_t s);
 hipError_t launch_inverse_f(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigR<float>& e, const float* T, const Item* items, int nitems,
+                            const void* psi, const double* occ, void* dst, hipStream_t s);
+// ---- split-BF16 transform kernels (kx_split.hip): FP32 intermediates T
+Plan make_split_plan(const Geom& g, size_t max_lds);
+hipError_t launch_forward_s(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigS& e, const void* src, const Item* items, int nitems,
+                            float* T, hipStream_t s);
+hipError_t launch_pencil_s(const Geom& g, const PencilPlan& p, const EigS& e, const double* F,
+                           int nitems, float* T, double* epart, hipStream_t s);
+hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigS& e, const float* T, const Item* items, int nitems,
                             const void* psi, const double* occ, void* dst, hipStream_t s);
 // per-item energies: pair_e[index(i, j)] = dV * sum_s epart[k*nstrips + s]
 hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* items, int nitems,

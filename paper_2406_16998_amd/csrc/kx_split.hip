@@ -1,0 +1,684 @@
+// Split-BF16 transform kernels: the same three folded passes as kx_fold.inc,
+// with every mode product computed from three-term bfloat16 splits of both
+// operands on v_mfma_f32_16x16x16_bf16 (FP32 accumulation):
+//
+//   x ~ x0 + x1 + x2,  x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1)
+//   A B ~ sum_{s + t <= 2} A_s B_t      (six products, smallest first)
+//
+// Products of two bf16 values are exact in FP32, so the error is the split
+// truncation (~2^-24 relative) plus FP32 rounding of the accumulation.  The
+// f(Lambda) scaling, the pair energies and the Vx psi update stay in FP64;
+// intermediates between passes are FP32.
+//
+// Operand layout of the instruction (li = lane % 16, lg = lane / 16): lane l
+// holds four k-consecutive values of A row li and of B column li in k-slots
+// (lg, e), e = 0..3; the accumulator tile is D[4 lg + r][li] (measured).  Any
+// assignment of k values to slots works as long as A and B use the same one;
+// here slot (lg, e) of the k-step starting at k0 holds k = k0 + 4 lg + e, so
+// accumulator tile t (rows 16 t + 4 lg + r) is, element for element, the B
+// operand of the k-step starting at 16 t.
+#include <hip/hip_runtime.h>
+
+#include "kx_internal.h"
+
+namespace kx {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+struct Split4 {
+  s4 h[3];  // bf16 bit patterns of the three terms, 4 k-slots
+};
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  const __bf16 b = (__bf16)x;  // round to nearest even
+  return __builtin_bit_cast(short, b);
+}
+__device__ __forceinline__ float bf16_value(short s) {
+  return __builtin_bit_cast(float, (unsigned)(unsigned short)s << 16);
+}
+
+__device__ __forceinline__ Split4 split4(float v0, float v1, float v2, float v3) {
+  Split4 o;
+  const float v[4] = {v0, v1, v2, v3};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float r = v[e];
+    const short a = bf16_bits(r);
+    r -= bf16_value(a);
+    const short b = bf16_bits(r);
+    r -= bf16_value(b);
+    const short c = bf16_bits(r);
+    o.h[0][e] = a;
+    o.h[1][e] = b;
+    o.h[2][e] = c;
+  }
+  return o;
+}
+
+__device__ __forceinline__ Split4 load_split(const short* __restrict__ p, int plane_stride) {
+  // pre-split operand: 4 k-consecutive bf16 of each plane
+  Split4 o;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) o.h[s] = *reinterpret_cast<const s4*>(p + s * plane_stride);
+  return o;
+}
+
+__device__ __forceinline__ f4 mma6(const Split4& a, const Split4& b, f4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[2], b.h[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[1], b.h[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[0], b.h[2], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[1], b.h[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[0], b.h[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[0], b.h[0], c, 0, 0, 0);
+  return c;
+}
+
+constexpr f4 kZ = {0.f, 0.f, 0.f, 0.f};
+constexpr int kSInvEl = 16;  // inverse: staged elements per thread per chunk
+constexpr int kSplitKc = 16; // staged K rows per chunk: one MFMA k-step
+
+extern __shared__ __align__(16) float kx_split_lds[];
+
+// ================================================================ forward
+template <int NTQ>
+__device__ __forceinline__ void sf_k_step(f4* acc1, const float* __restrict__ arow, int wrow,
+                                          const Split4& b) {
+  // A slot (lg, e) = S[k0 + 4 lg + e][16 t + li]: arow points at row k0 + 4 lg
+#pragma unroll
+  for (int t = 0; t < NTQ; ++t) {
+    const float* a = arow + kTile * t;
+    acc1[t] = mma6(split4(a[0], a[wrow], a[2 * wrow], a[3 * wrow]), b, acc1[t]);
+  }
+}
+
+template <int NTQ>
+__device__ __forceinline__ void sf_mode1(const f4* acc1, f4* acc2, const short* __restrict__ V1qT,
+                                         int ldq, int pstride, int lg, int li) {
+  // A[m = a][k = x'] = V1q[x'][a] = V1qT[a][x'];  B = split(acc1[t])
+#pragma unroll
+  for (int t = 0; t < NTQ; ++t) {
+    const Split4 b = split4(acc1[t][0], acc1[t][1], acc1[t][2], acc1[t][3]);
+#pragma unroll
+    for (int u = 0; u < NTQ; ++u) {
+      const Split4 a = load_split(V1qT + (kTile * u + li) * ldq + kTile * t + 4 * lg, pstride);
+      acc2[u] = mma6(a, b, acc2[u]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int NTQ>
+__device__ __forceinline__ void sf_store(const f4* acc2, float* __restrict__ Tzb, int p2, int lg) {
+#pragma unroll
+  for (int u = 0; u < NTQ; ++u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Tzb[(unsigned)(kTile * u + 4 * lg + r) * p2] = acc2[u][r];
+  }
+}
+
+// Workgroup layout as the FP32/FP64 forward pass (one wave per x parity q,
+// y parity p, 16-wide b strip; `slabs` z-slabs); staged folded rows in
+// chunks of kc (a multiple of 16).
+template <class S, int NT, bool OFULL, int MODE, int MT>
+__global__ void __launch_bounds__(MT)
+split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict__ items,
+              float* __restrict__ T, int slabs, int kc, int qsplit) {
+  float* lds = kx_split_lds;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nb = g.p2 / kTile, nbe = g.pe2 / kTile;
+  const int wps = (qsplit == 1 ? 2 : 1) * nb;
+  const int s = wave / wps;
+  const int w = wave - s * wps;
+  const int q = (qsplit == 1) ? (w / nb) : (int)blockIdx.z;
+  const int rem = w % nb;
+  const int p = rem < nbe ? 0 : 1;
+  const int b0 = (p == 0 ? rem : rem - nbe) * kTile;
+  const int z = blockIdx.x * slabs + s;
+  const bool zin = z < g.n3;
+  const int it = blockIdx.y;
+  const Item item = items[it];
+  const int q_lo = (qsplit == 1) ? 0 : (int)blockIdx.z;
+  const int q_hi = (qsplit == 1) ? 2 : q_lo + 1;
+  const int wrow = (qsplit == 1) ? g.p1 : (q_lo == 0 ? g.pe1 : g.po1);
+  auto qcol = [&](int qq) { return (qsplit == 1 && qq == 1) ? g.pe1 : 0; };
+  const int celems = 2 * kc * wrow;
+  float* __restrict__ sb = lds + (size_t)s * 2 * celems;
+
+  const int sthreads = wps * 64;
+  const int stid = tid - s * sthreads;
+  const long long zoff = (long long)(zin ? z : 0) * g.n1 * g.n2;
+  const S* __restrict__ s0 = src + (long long)item.i * g.N + zoff;
+  const S* __restrict__ s1 = src + (long long)(MODE == 1 ? item.j : item.i) * g.N + zoff;
+  const int npos = kc * g.pe1;
+  // one staged position: the four mirror images (y, x), (y, n1-1-x),
+  // (n2-1-y, x), (n2-1-y, n1-1-x) of the pair product
+  auto load_pos = [&](int pos, int y0, double* va, double* vb) {
+    const int yy = pos / g.pe1, xp = pos - yy * g.pe1;
+    const int y = y0 + yy, ym = g.n2 - 1 - y, xm = g.n1 - 1 - xp;
+    const bool in = zin && pos < npos && y < g.me2 && xp < g.me1;
+    const bool hx = in && xp < g.mo1, hy = in && y < g.mo2;
+    const int o[4] = {y * g.n1 + xp, y * g.n1 + xm, ym * g.n1 + xp, ym * g.n1 + xm};
+    const bool ok[4] = {in, hx, hy, hx && hy};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      va[m] = ok[m] ? (double)s0[o[m]] : 0.0;
+      if (MODE == 1) vb[m] = ok[m] ? (double)s1[o[m]] : 0.0;
+    }
+  };
+  auto store_pos = [&](float* buf, int pos, int ybase, const double* va, const double* vb) {
+    const int yy = pos / g.pe1, xp = pos - yy * g.pe1;
+    double v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = (MODE == 1) ? va[m] * vb[m] : va[m];
+    const double sx0 = v[0] + v[1], dx0 = v[0] - v[1];
+    const double sx1 = v[2] + v[3], dx1 = v[2] - v[3];
+    const int y = yy + ybase;
+    const bool xo = xp < g.mo1, yo = y < g.mo2;
+    for (int qq = q_lo; qq < q_hi; ++qq) {
+      const int wq = qq == 0 ? g.pe1 : g.po1;
+      if (xp >= wq) continue;
+      const bool live = qq == 0 || xo;
+      const double ve = !live ? 0.0 : (qq == 0 ? sx0 + sx1 : dx0 + dx1);
+      const double vo = !(live && yo) ? 0.0 : (qq == 0 ? sx0 - sx1 : dx0 - dx1);
+      buf[(0 * kc + yy) * wrow + qcol(qq) + xp] = (float)ve;
+      buf[(1 * kc + yy) * wrow + qcol(qq) + xp] = (float)vo;
+    }
+  };
+  double ra[kFwdPos][4], rb[kFwdPos][4];
+  auto fetch = [&](int y0) {
+#pragma unroll
+    for (int k = 0; k < kFwdPos; ++k) load_pos(stid + k * sthreads, y0, ra[k], rb[k]);
+  };
+  auto stash = [&](float* buf, int y0) {
+#pragma unroll
+    for (int k = 0; k < kFwdPos; ++k) {
+      const int pos = stid + k * sthreads;
+      if (pos < npos) store_pos(buf, pos, y0, ra[k], rb[k]);
+    }
+    // positions beyond the register budget (narrow y extents): direct
+    for (int pos = stid + kFwdPos * sthreads; pos < npos; pos += sthreads) {
+      double va[4], vb[4];
+      load_pos(pos, y0, va, vb);
+      store_pos(buf, pos, y0, va, vb);
+    }
+  };
+
+  constexpr int NTO = OFULL ? NT : NT - 1;
+  const bool qfull = q == 0 || OFULL;
+  // B[k = y'][n = b] = V2p[y'][b] = V2pT[b][y']: pre-split, k-contiguous rows
+  const short* __restrict__ V2pT = p == 0 ? e.ET[1] : e.OT[1];
+  const int ldp = p == 0 ? g.pe2 : g.po2;
+  const int pst2 = ldp * ldp;
+
+  f4 acc1[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc1[t] = kZ;
+  const int nchunks = (g.me2 + kc - 1) / kc;
+  fetch(0);
+  stash(sb, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const float* __restrict__ cur = sb + (c & 1) * celems;
+    if (c + 1 < nchunks) fetch((c + 1) * kc);
+    const int y0 = c * kc;
+    for (int kk = 0; kk < kc && y0 + kk < ldp; kk += kTile) {
+      // staged rows beyond the parity's length are zero; so are the padded V2 rows
+      const Split4 b = load_split(V2pT + (b0 + li) * ldp + y0 + kk + 4 * lg, pst2);
+      const float* __restrict__ arow = cur + (p * kc + kk + 4 * lg) * wrow + qcol(q) + li;
+      if (qfull)
+        sf_k_step<NT>(acc1, arow, wrow, b);
+      else
+        sf_k_step<NTO>(acc1, arow, wrow, b);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (c + 1 < nchunks) stash(sb + ((c + 1) & 1) * celems, (c + 1) * kc);
+    __syncthreads();
+  }
+
+  const short* __restrict__ V1qT = q == 0 ? e.ET[0] : e.OT[0];
+  const int ldq = q == 0 ? g.pe1 : g.po1;
+  f4 acc2[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) acc2[u] = kZ;
+  if (qfull)
+    sf_mode1<NT>(acc1, acc2, V1qT, ldq, ldq * ldq, lg, li);
+  else
+    sf_mode1<NTO>(acc1, acc2, V1qT, ldq, ldq * ldq, lg, li);
+  if (!zin) return;
+  const int aoff = q == 0 ? 0 : g.pe1, boff = p == 0 ? 0 : g.pe2;
+  float* __restrict__ Tzb =
+      T + (long long)it * g.slot + (long long)z * g.slab + (long long)aoff * g.p2 + boff + b0 + li;
+  if (qfull)
+    sf_store<NT>(acc2, Tzb, g.p2, lg);
+  else
+    sf_store<NTO>(acc2, Tzb, g.p2, lg);
+}
+
+// ================================================================ pencil
+template <int NT, bool OFULL, int MT>
+__global__ void __launch_bounds__(MT)
+split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T,
+             double* __restrict__ epart) {
+  constexpr int NTE = NT, NTO = OFULL ? NT : NT - 1;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nwaves = blockDim.x >> 6;
+  const int nstrips = (int)(g.slab / kTile);
+  const int qs = (int)blockIdx.x * nwaves + wave;
+  const bool qin = qs < nstrips;
+  const unsigned q0 = (unsigned)(qin ? qs : 0) * kTile;
+  const unsigned slab = (unsigned)g.slab;
+  const int it = blockIdx.y;
+  float* __restrict__ Tb = T + (long long)it * g.slot + q0;
+  const int pe = g.pe3, po = g.po3;
+
+  // folded column values, k-step t (z' = 16 t + 4 lg + e)
+  Split4 be[NT], bo[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    float ce[4], co[4];
+#pragma unroll
+    for (int ee = 0; ee < 4; ++ee) {
+      const int zp = kTile * t + 4 * lg + ee;
+      const bool ie = qin && zp < g.me3, io = qin && zp < g.mo3;
+      const float a = ie ? Tb[(unsigned)zp * slab + li] : 0.f;
+      const float m = io ? Tb[(unsigned)(g.n3 - 1 - zp) * slab + li] : 0.f;
+      ce[ee] = a + m;
+      co[ee] = io ? a - m : 0.f;
+    }
+    be[t] = split4(ce[0], ce[1], ce[2], ce[3]);
+    bo[t] = split4(co[0], co[1], co[2], co[3]);
+  }
+
+  // mode 3 (folded):  C[c][q] += A[c][z'] B[z'][q],  A[c][z'] = V3p[z'][c] = V3pT[c][z']
+  f4 accE[NT], accO[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    accE[t] = kZ;
+    accO[t] = kZ;
+  }
+#pragma unroll
+  for (int k = 0; k < NTE; ++k) {
+#pragma unroll
+    for (int t = 0; t < NTE; ++t) {
+      const Split4 a = load_split(e.ET[2] + (kTile * t + li) * pe + kTile * k + 4 * lg, pe * pe);
+      accE[t] = mma6(a, be[k], accE[t]);
+    }
+    if (k < NTO) {
+#pragma unroll
+      for (int t = 0; t < NTO; ++t) {
+        const Split4 a = load_split(e.OT[2] + (kTile * t + li) * po + kTile * k + 4 * lg, po * po);
+        accO[t] = mma6(a, bo[k], accO[t]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // Hadamard product with f(Lambda) (FP64) and the pair-energy partial sum
+  const double* __restrict__ Fq = F + q0;
+  double esum = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = kTile * t + 4 * lg + r;
+      {
+        const double f = qin ? Fq[(unsigned)c * slab + li] : 0.0;
+        const double v = accE[t][r];
+        esum += f * v * v;
+        accE[t][r] = (float)(f * v);
+      }
+      if (t < NTO) {
+        const double f = qin ? Fq[(unsigned)(pe + c) * slab + li] : 0.0;
+        const double v = accO[t][r];
+        esum += f * v * v;
+        accO[t][r] = (float)(f * v);
+      }
+    }
+  }
+
+  // inverse mode 3 (folded):  C[z'][q] += A[z'][c] B[c][q],  A = V3p (rows z', k = c)
+  f4 outE[NT], outO[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    outE[u] = kZ;
+    outO[u] = kZ;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    {
+      const Split4 b = split4(accE[t][0], accE[t][1], accE[t][2], accE[t][3]);
+#pragma unroll
+      for (int u = 0; u < NTE; ++u) {
+        const Split4 a = load_split(e.E[2] + (kTile * u + li) * pe + kTile * t + 4 * lg, pe * pe);
+        outE[u] = mma6(a, b, outE[u]);
+      }
+    }
+    if (t < NTO) {
+      const Split4 b = split4(accO[t][0], accO[t][1], accO[t][2], accO[t][3]);
+#pragma unroll
+      for (int u = 0; u < NTO; ++u) {
+        const Split4 a = load_split(e.O[2] + (kTile * u + li) * po + kTile * t + 4 * lg, po * po);
+        outO[u] = mma6(a, b, outO[u]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (qin) {
+#pragma unroll
+    for (int u = 0; u < NTE; ++u) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int zp = kTile * u + 4 * lg + r;
+        const float P = outE[u][r];
+        const float Q = (u < NTO) ? outO[u][r] : 0.f;
+        if (zp < g.me3) Tb[(unsigned)zp * slab + li] = P + Q;
+        if (zp < g.mo3) Tb[(unsigned)(g.n3 - 1 - zp) * slab + li] = P - Q;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o);
+  if (epart != nullptr && qin && lane == 0) epart[(long long)it * nstrips + qs] = esum;
+}
+
+// ================================================================ inverse
+// acc1 layout [q][p][t] flattened as acc1[(q * 2 + p) * NT + t]
+template <int NT, int NTO>
+__device__ __forceinline__ void si_k_step(f4* acc1q, const float* __restrict__ arow, int p2,
+                                          int pe2, const Split4& b) {
+  // A[m = b][k = a'] = T2[a'][b]: arow points at staged row k0 + 4 lg, column li
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const float* a = arow + kTile * t;
+    acc1q[t] = mma6(split4(a[0], a[p2], a[2 * p2], a[3 * p2]), b, acc1q[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < NTO; ++t) {
+    const float* a = arow + pe2 + kTile * t;
+    acc1q[NT + t] = mma6(split4(a[0], a[p2], a[2 * p2], a[3 * p2]), b, acc1q[NT + t]);
+  }
+}
+
+template <int NT, int NTO, bool HASO>
+__device__ __forceinline__ void si_mode2(const Split4* bs, f4* Q, int u, const short* __restrict__ VE2,
+                                         const short* __restrict__ VO2, int pe2, int po2, int lg,
+                                         int li) {
+  // bs[(q * 2 + p) * NT + t] = split(acc1 tile); A[m = y'][k = b] = V2p[y'][b]
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Q[k] = kZ;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const Split4 a = load_split(VE2 + (kTile * u + li) * pe2 + kTile * t + 4 * lg, pe2 * pe2);
+    Q[0] = mma6(a, bs[(0 * 2 + 0) * NT + t], Q[0]);
+    if (HASO) Q[1] = mma6(a, bs[(1 * 2 + 0) * NT + t], Q[1]);
+    if (t < NTO && u < NTO) {
+      const Split4 ao = load_split(VO2 + (kTile * u + li) * po2 + kTile * t + 4 * lg, po2 * po2);
+      Q[2] = mma6(ao, bs[(0 * 2 + 1) * NT + t], Q[2]);
+      if (HASO) Q[3] = mma6(ao, bs[(1 * 2 + 1) * NT + t], Q[3]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <class S, int NT, bool OFULL, int MODE, int MT>
+__global__ void __launch_bounds__(MT)
+split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restrict__ items,
+              const S* __restrict__ psi, const double* __restrict__ occ, S* __restrict__ dst,
+              int slabs, int kc) {
+  constexpr int NTO = OFULL ? NT : NT - 1;
+  float* lds = kx_split_lds;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nstr = g.pe1 / kTile;
+  const int s = wave / nstr;
+  const int x0 = (wave - s * nstr) * kTile;
+  const int z = blockIdx.x * slabs + s;
+  const bool zin = z < g.n3;
+  const int it = blockIdx.y;
+  const int pe2 = g.pe2, po2 = g.po2, p2 = g.p2;
+  const int celems = 2 * kc * p2;
+  float* __restrict__ sb = lds + (size_t)s * 2 * celems;
+  const int sthreads = nstr * 64;
+  const int stid = tid - s * sthreads;
+  const float* __restrict__ Tz = T + (long long)it * g.slot + (long long)(zin ? z : 0) * g.slab;
+  // staged chunk [q][kc][p2]: rows a0 + aa of the x-parity q blocks
+  auto load_el = [&](int idx, int a0) {
+    const int row = idx / p2, col = idx - row * p2;
+    const int qq = row / kc, aa = row - qq * kc;
+    const int mq = qq == 0 ? g.me1 : g.mo1;
+    const bool ok = zin && idx < celems && a0 + aa < mq;
+    const unsigned a = (qq == 0 ? 0 : g.pe1) + a0 + aa;
+    return ok ? Tz[a * (unsigned)p2 + col] : 0.f;
+  };
+  float pa[kSInvEl];
+  auto fetch = [&](int a0) {
+#pragma unroll
+    for (int k = 0; k < kSInvEl; ++k) pa[k] = load_el(stid + k * sthreads, a0);
+  };
+  auto stash = [&](float* buf, int a0) {
+#pragma unroll
+    for (int k = 0; k < kSInvEl; ++k) {
+      const int idx = stid + k * sthreads;
+      if (idx < celems) buf[idx] = pa[k];
+    }
+    // elements beyond the register budget (wide y extents): direct
+    for (int idx = stid + kSInvEl * sthreads; idx < celems; idx += sthreads) buf[idx] = load_el(idx, a0);
+  };
+
+  const int xp = x0 + li;
+  const bool has_o = x0 < g.po1;
+  f4 acc1[4 * NT];
+#pragma unroll
+  for (int k = 0; k < 4 * NT; ++k) acc1[k] = kZ;
+  const int nchunks = (g.me1 + kc - 1) / kc;
+  fetch(0);
+  stash(sb, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const float* __restrict__ cur = sb + (c & 1) * celems;
+    if (c + 1 < nchunks) fetch((c + 1) * kc);
+    const int a0 = c * kc;
+    for (int kk = 0; kk < kc && a0 + kk < g.pe1; kk += kTile) {
+      // B[k = a'][n = x'] = V1q[x'][a'] (rows x', k = a' contiguous); padded rows are zero
+      const Split4 be = load_split(e.E[0] + xp * g.pe1 + a0 + kk + 4 * lg, g.pe1 * g.pe1);
+      si_k_step<NT, NTO>(acc1, cur + (kk + 4 * lg) * p2 + li, p2, pe2, be);
+      if (has_o && a0 + kk < g.po1) {
+        const Split4 bo = load_split(e.O[0] + xp * g.po1 + a0 + kk + 4 * lg, g.po1 * g.po1);
+        si_k_step<NT, NTO>(acc1 + 2 * NT, cur + (kc + kk + 4 * lg) * p2 + li, p2, pe2, bo);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (c + 1 < nchunks) stash(sb + ((c + 1) & 1) * celems, (c + 1) * kc);
+    __syncthreads();
+  }
+  // split the W tiles once; they are the B operands of every y' tile
+  Split4 bs[4 * NT];
+#pragma unroll
+  for (int k = 0; k < 4 * NT; ++k) bs[k] = split4(acc1[k][0], acc1[k][1], acc1[k][2], acc1[k][3]);
+
+  const bool xin = zin && xp < g.me1;
+  const int xm = g.n1 - 1 - xp;
+  const long long zoff = (long long)(zin ? z : 0) * g.n1 * g.n2;
+  const Item item = items[it];
+  const S* __restrict__ pi = psi + (long long)item.i * g.N + zoff;
+  const S* __restrict__ pj = psi + (long long)(MODE == 1 ? item.j : item.i) * g.N + zoff;
+  S* __restrict__ vj = dst + (long long)(MODE == 1 ? item.j : item.i) * g.N + zoff;
+  S* __restrict__ vi = dst + (long long)item.i * g.N + zoff;
+  const bool offdiag = MODE == 1 && item.i != item.j;
+  const double oi = MODE == 1 ? occ[item.i] : 0.0;
+  const double oj = MODE == 1 ? occ[item.j] : 0.0;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    f4 Q[4];
+    if (has_o)
+      si_mode2<NT, NTO, true>(bs, Q, u, e.E[1], e.O[1], pe2, po2, lg, li);
+    else
+      si_mode2<NT, NTO, false>(bs, Q, u, e.E[1], e.O[1], pe2, po2, lg, li);
+    if (!xin) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int yp = kTile * u + 4 * lg + r;
+      if (yp >= g.me2) continue;
+      const double ee = Q[0][r], eo = has_o ? Q[1][r] : 0.0;
+      const double oe = u < NTO ? Q[2][r] : 0.0, oo = (has_o && u < NTO) ? Q[3][r] : 0.0;
+      const int ym = g.n2 - 1 - yp;
+      const bool hx = xp < g.mo1, hy = yp < g.mo2;
+      const double ph[4] = {ee + eo + oe + oo, ee - eo + oe - oo, ee + eo - oe - oo,
+                            ee - eo - oe + oo};
+      const unsigned o[4] = {(unsigned)(yp * g.n1 + xp), (unsigned)(yp * g.n1 + xm),
+                             (unsigned)(ym * g.n1 + xp), (unsigned)(ym * g.n1 + xm)};
+      const bool ok[4] = {true, hx, hy, hx && hy};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (!ok[m]) continue;
+        if (MODE == 0) {
+          vj[o[m]] = (S)ph[m];
+        } else {
+          vj[o[m]] = (S)((double)vj[o[m]] - (oi * ph[m]) * (double)pi[o[m]]);
+          if (offdiag) vi[o[m]] = (S)((double)vi[o[m]] - (oj * ph[m]) * (double)pj[o[m]]);
+        }
+      }
+    }
+  }
+}
+
+template <class K>
+void allow_lds(K kernel, size_t lds) {
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+}
+
+#define KX_NT_CASES(MACRO) MACRO(1) MACRO(2) MACRO(3) MACRO(4) MACRO(5)
+
+template <class S>
+hipError_t sfwd_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e, const S* src,
+                       const Item* items, int nitems, float* T, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 grid((g.n3 + p.slabs - 1) / p.slabs, nitems, p.qsplit);
+  const dim3 block(64 * p.waves);
+  const size_t lb = p.lds_bytes;
+  const bool of = g.po1 == g.pe1;
+  switch (g.pe1 / kTile) {
+#define KX_CASE(NT)                                                                          \
+  case NT: {                                                                                 \
+    constexpr int MT = fwd_mt(NT);                                                           \
+    auto k = mode == 1 ? (of ? split_forward<S, NT, true, 1, MT> : split_forward<S, NT, false, 1, MT>) \
+                       : (of ? split_forward<S, NT, true, 0, MT> : split_forward<S, NT, false, 0, MT>); \
+    allow_lds(k, lb);                                                                        \
+    hipLaunchKernelGGL(k, grid, block, lb, st, g, e, src, items, T, p.slabs, p.kc, p.qsplit); \
+    break;                                                                                   \
+  }
+    KX_NT_CASES(KX_CASE)
+#undef KX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t spen_launch(const Geom& g, const PencilPlan& p, const EigS& e, const double* F,
+                       int nitems, float* T, double* epart, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const long long nstrips = g.slab / kTile;
+  const int w = p.waves;
+  const dim3 grid((unsigned)((nstrips + w - 1) / w), nitems);
+  const dim3 block(64 * w);
+  const bool of = g.po3 == g.pe3;
+  switch (g.pe3 / kTile) {
+#define KX_CASE(NT)                                                                      \
+  case NT: {                                                                             \
+    constexpr int MT = pen_mt(NT);                                                       \
+    auto k = of ? split_pencil<NT, true, MT> : split_pencil<NT, false, MT>;              \
+    hipLaunchKernelGGL(k, grid, block, 0, st, g, e, F, T, epart);                        \
+    break;                                                                               \
+  }
+    KX_NT_CASES(KX_CASE)
+#undef KX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t sinv_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e, const float* T,
+                       const Item* items, int nitems, const S* psi, const double* occ, S* dst,
+                       hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 grid((g.n3 + p.slabs - 1) / p.slabs, nitems);
+  const dim3 block(64 * p.waves);
+  const size_t lb = p.lds_bytes;
+  const bool of = g.po2 == g.pe2;
+  switch (g.pe2 / kTile) {
+#define KX_CASE(NT)                                                                         \
+  case NT: {                                                                                \
+    constexpr int MT = inv_mt(NT);                                                          \
+    auto k = mode == 1 ? (of ? split_inverse<S, NT, true, 1, MT> : split_inverse<S, NT, false, 1, MT>) \
+                       : (of ? split_inverse<S, NT, true, 0, MT> : split_inverse<S, NT, false, 0, MT>); \
+    allow_lds(k, lb);                                                                       \
+    hipLaunchKernelGGL(k, grid, block, lb, st, g, e, T, items, psi, occ, dst, p.slabs, p.kc); \
+    break;                                                                                  \
+  }
+    KX_NT_CASES(KX_CASE)
+#undef KX_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+Plan make_split_plan(const Geom& g, size_t max_lds) {
+  // Same workgroup shapes as the FP32 path; chunks of exactly one k-step and
+  // no V blocks in LDS (the pre-split blocks are read through the caches).
+  Plan pl = make_plan(g, max_lds, sizeof(float));
+  // staging beyond the per-thread register budget falls back to direct
+  // loads in these kernels, so every shape is accepted
+  SlabPlan& f = pl.fwd;
+  f.kc = kSplitKc;
+  f.vlds = false;
+  f.ok = true;
+  const int wrow = f.qsplit == 1 ? g.p1 : g.pe1;
+  f.lds_bytes = (size_t)f.slabs * 2 * 2 * f.kc * wrow * sizeof(float);
+  SlabPlan& v = pl.inv;
+  v.kc = kSplitKc;
+  v.vlds = false;
+  v.ok = true;
+  v.lds_bytes = (size_t)v.slabs * 2 * 2 * v.kc * g.p2 * sizeof(float);
+  pl.pen.lds_bytes = 0;
+  return pl;
+}
+
+hipError_t launch_forward_s(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigS& e, const void* src, const Item* items, int nitems,
+                            float* T, hipStream_t s) {
+  return storage == KX_F64
+             ? sfwd_launch<double>(mode, g, p, e, (const double*)src, items, nitems, T, s)
+             : sfwd_launch<float>(mode, g, p, e, (const float*)src, items, nitems, T, s);
+}
+
+hipError_t launch_pencil_s(const Geom& g, const PencilPlan& p, const EigS& e, const double* F,
+                           int nitems, float* T, double* epart, hipStream_t s) {
+  return spen_launch(g, p, e, F, nitems, T, epart, s);
+}
+
+hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan& p,
+                            const EigS& e, const float* T, const Item* items, int nitems,
+                            const void* psi, const double* occ, void* dst, hipStream_t s) {
+  return storage == KX_F64
+             ? sinv_launch<double>(mode, g, p, e, T, items, nitems, (const double*)psi, occ,
+                                   (double*)dst, s)
+             : sinv_launch<float>(mode, g, p, e, T, items, nitems, (const float*)psi, occ,
+                                  (float*)dst, s);
+}
+
+}  // namespace kx

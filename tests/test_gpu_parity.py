@@ -15,6 +15,15 @@ from synth import WORKLOADS, make_workload, random_fields
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
+# FP32 mode products: unit roundoff 2^-24 ~ 6e-8, K <= 80 per product, six
+# products in sequence -> a few 1e-6 relative per element in the worst case;
+# the energy sums many independent roundings and is tighter.
+# Split BF16 x3: each FP32 operand is carried exactly by its three terms (24
+# significant bits), V_k to ~2^-25; the dropped terms (s + t >= 3) are
+# <= 3 * 2^-24 relative and the accumulation is FP32, so the same bounds hold.
+TOL32_FIELD = 1e-5
+TOL32_ENERGY = 1e-6
+REDUCED = ["fp32", "bf16x3"]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_energies.json")
 
 
@@ -207,6 +216,32 @@ def test_exchange_production_size_sampled(torch_cuda):
     g.close()
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", REDUCED)
+def test_exchange_production_size_reduced_precision(torch_cuda, prec):
+    """The 128-orbital 96^3 erfc workload in reduced precision: E_x and the
+    sampled pair energies against the stored oracle values, Vx psi of one
+    orbital against the oracle.  Prints |dE_x| in Hartree."""
+    torch = torch_cuda
+    name = "periodic96_erfc"
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)[name]
+    kx = _kx()
+    w, psi, occ = make_workload(name)
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    vx = g.apply_exchange(torch.from_numpy(psi).cuda(), occ, w.kernel, w.omega, prec=prec)
+    ex = g.exchange_energy()
+    pe = g.pair_energies(gold["pairs"])
+    print(f"{prec} E_x gpu={ex!r} oracle={gold['E_x']!r} |dE|={abs(ex - gold['E_x']):.3e} Ha", flush=True)
+    assert abs(ex - gold["E_x"]) <= TOL32_ENERGY * abs(gold["E_x"])
+    emax = max(abs(r) for r in gold["pair_energies"])
+    for e, r in zip(pe, gold["pair_energies"]):
+        assert abs(e - r) <= TOL32_ENERGY * emax
+    ref = orc.vx_orbital(psi, occ, 5, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
+    assert _rel(vx[5].cpu().numpy(), ref) <= TOL32_FIELD
+    g.close()
+
+
 # ------------------------------------------------------------------ error paths
 def test_error_statuses_on_device(torch_cuda):
     torch = torch_cuda
@@ -229,41 +264,69 @@ def test_error_statuses_on_device(torch_cuda):
 
 
 # ------------------------------------------------------------------ reduced precision
-# FP32 mode products: unit roundoff 2^-24 ~ 6e-8, K <= 80 per product, six
-# products in sequence -> a few 1e-6 relative per element in the worst case;
-# the energy sums many independent roundings and is tighter.
-TOL32_FIELD = 1e-5
-TOL32_ENERGY = 1e-6
 
 
-@pytest.mark.parametrize("n,h,order,bc,kernel,omega", FL_CASES[:5])
-def test_apply_fL_fp32_arithmetic(torch_cuda, n, h, order, bc, kernel, omega):
+@pytest.mark.parametrize("prec", REDUCED)
+@pytest.mark.parametrize("n,h,order,bc,kernel,omega", FL_CASES)
+def test_apply_fL_reduced_precision(torch_cuda, n, h, order, bc, kernel, omega, prec):
     torch = torch_cuda
     kx = _kx()
+    print(f"apply_fL {prec} n={n} bc={bc} kernel={kernel}", flush=True)
     rho = random_fields(n, 2, seed=sum(n) + 1)
     g = kx.Grid(n, h, order, bc)
-    phi = g.apply_fL(torch.from_numpy(rho).cuda(), kernel, omega, prec="fp32").cpu().numpy()
+    phi = g.apply_fL(torch.from_numpy(rho).cuda(), kernel, omega, prec=prec).cpu().numpy()
     g.close()
     ref = orc.apply_fL(rho, orc.make_grid(n, h, order, bc), kernel, omega)
     for b in range(2):
         assert _rel(phi[b], ref[b]) <= TOL32_FIELD
 
 
-@pytest.mark.parametrize("name", ["mixed40x36x44_erfc", "dirichlet32_coulomb"])
-def test_exchange_fp32_arithmetic(torch_cuda, name):
+@pytest.mark.parametrize("prec", REDUCED)
+@pytest.mark.parametrize("name", ["mixed40x36x44_erfc", "dirichlet32_coulomb", "dirichlet20x27x34_coulomb"])
+def test_exchange_reduced_precision(torch_cuda, name, prec):
     torch = torch_cuda
     kx = _kx()
+    print(f"exchange {prec} {name}", flush=True)
     w, psi, occ = make_workload(name)
     g = kx.Grid(w.n, w.h, w.order, w.bc)
-    vx = g.apply_exchange(torch.from_numpy(psi).cuda(), occ, w.kernel, w.omega, prec="fp32")
+    vx = g.apply_exchange(torch.from_numpy(psi).cuda(), occ, w.kernel, w.omega, prec=prec)
     ex = g.exchange_energy()
     vx = vx.cpu().numpy()
     g.close()
     vx_ref, ex_ref = orc.exchange(psi, occ, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
-    print(f"fp32 {name}: dE/E={abs(ex - ex_ref) / abs(ex_ref):.2e}", flush=True)
+    print(f"{prec} {name}: dE/E={abs(ex - ex_ref) / abs(ex_ref):.2e}", flush=True)
     assert abs(ex - ex_ref) <= TOL32_ENERGY * abs(ex_ref)
     for j in range(w.norb):
         assert _rel(vx[j], vx_ref[j]) <= TOL32_FIELD, j
+
+
+# Grids far from cubic: x much longer than y (forward staging beyond the
+# register budget) and y much longer than x (inverse staging).
+ANISO = [((70, 8, 12), ("dirichlet",) * 3), ((10, 70, 9), ("dirichlet",) * 3),
+         ((9, 66, 20), ("periodic", "periodic", "dirichlet"))]
+
+
+@pytest.mark.parametrize("n,bc", ANISO)
+@pytest.mark.parametrize("prec", ["fp64"] + REDUCED)
+def test_apply_fL_anisotropic_grids(torch_cuda, n, bc, prec):
+    torch = torch_cuda
+    kx = _kx()
+    print(f"apply_fL {prec} anisotropic n={n}", flush=True)
+    h = (0.3, 0.3, 0.3)
+    rho = random_fields(n, 2, seed=sum(n) + 7)
+    g = kx.Grid(n, h, 12, bc)
+    ref = orc.apply_fL(rho, orc.make_grid(n, h, 12, bc), "coulomb", 0.0)
+    try:
+        phi = g.apply_fL(torch.from_numpy(rho).cuda(), "coulomb", 0.0, prec=prec).cpu().numpy()
+    except kx.KxError as e:
+        # FP64 / FP32 inverse staging limit: documented, reported as unsupported
+        assert prec != "bf16x3" and e.status == 2 and n[1] > 4 * n[0]
+        return
+    finally:
+        g.close()
+    tol = TOL64 if prec == "fp64" else TOL32_FIELD
+    for b in range(2):
+        assert _rel(phi[b], ref[b]) <= tol
 
 
 def test_exchange_f32_storage_fp64_arithmetic(torch_cuda):
