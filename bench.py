@@ -6,8 +6,11 @@ energies, inverse transforms, Vx psi accumulation, E_x), inputs resident in
 HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64] [--workload periodic96_erfc]
+    python bench.py --calibrate-copy     # plain 1 GiB device copy, for counter scaling
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -37,7 +40,69 @@ def phase_flops(w):
     return {"forward": fw, "pencil": 2 * mode_flops(N, n3), "inverse": fw}
 
 
-def cpu_baseline(w, psi, occ, target_s=15.0):
+T_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "fp16x3": 4}
+
+
+def phase_bytes(w, prec):
+    """Algorithmic HBM bytes of each phase summed over all pairs of one step
+    (N values per field; s bytes per orbital value, t per intermediate value):
+      forward  reads psi_i, psi_j, writes T            (2s + t) N
+      pencil   reads and writes T                       2t N  (+ the f table once a launch)
+      inverse  reads T, psi_i, psi_j, read-modify-writes Vx psi_i, Vx psi_j   (t + 6s) N
+    A diagonal pair (i = i) touches one orbital: (s + t), 2t, (t + 3s) N."""
+    s = 8 if w.storage == "f64" else 4
+    t = T_BYTES[prec]
+    off, diag = w.norb * (w.norb - 1) // 2, w.norb
+    N = w.N
+    return {"forward": (off * (2 * s + t) + diag * (s + t)) * N,
+            "pencil": (off + diag) * 2 * t * N,
+            "inverse": (off * (t + 6 * s) + diag * (t + 3 * s)) * N}
+
+
+def kernel_sources_digest():
+    """Digest of the HIP sources and headers: counter figures recorded for
+    other sources no longer describe the kernels."""
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2406_16998_amd", "csrc", "*")) +
+                   [os.path.join(ROOT, "include", "kx.h")])
+    h = hashlib.sha256()
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, prec, phase):
+    """HBM bytes per launch from the committed counter summary (copy-scaled
+    FETCH_SIZE + WRITE_SIZE), or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    digest, val = None, None
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) >= 2 and f[0] == "sources_digest":
+                digest = f[1]
+            if len(f) >= 4 and f[0] == "bytes_per_launch" and f[1] == prec and f[2] == phase:
+                val = float(f[3])
+    return val if digest == kernel_sources_digest() else None
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 1 GiB, three times: what FETCH_SIZE and
+    WRITE_SIZE read for it scales the counters of the exchange kernels."""
+    import torch
+    n = 128 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": 8 * n, "launches": 3}))
+
+
+def cpu_baseline(w, psi, occ, target_s=20.0):
     """Time the FP64 oracle as it stands on a bounded sample of the same
     workload: exchange over the first k orbitals (k(k+1)/2 pairs)."""
     import numpy as np
@@ -48,10 +113,10 @@ def cpu_baseline(w, psi, occ, target_s=15.0):
     except Exception:
         threads = os.cpu_count()
     grid = orc.make_grid(w.n, w.h, w.order, w.bc)
-    # calibrate with 2 orbitals (3 pairs), then size the sample
+    # calibrate with 4 orbitals (10 pairs), then size the sample
     t0 = time.perf_counter()
-    orc.exchange(np.asarray(psi[:2], dtype=np.float64), occ[:2], grid, w.kernel, w.omega)
-    per_pair = (time.perf_counter() - t0) / 3
+    orc.exchange(np.asarray(psi[:4], dtype=np.float64), occ[:4], grid, w.kernel, w.omega)
+    per_pair = (time.perf_counter() - t0) / 10
     k = 2
     while k < w.norb and (k + 1) * (k + 2) / 2 * per_pair < target_s:
         k += 1
@@ -72,13 +137,17 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=sorted(PEAKS_TFLOPS))
     ap.add_argument("--workload", default="periodic96_erfc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the exchange path has no multi-GPU mode in this build",
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
     import torch
 
     from paper_2406_16998_amd import kx
@@ -122,14 +191,29 @@ def main():
 
     ms_step = ms_total / args.steps
     value = w.npairs * args.steps / (ms_total * 1e-3)
-    # dominant kernel: the transform phase with the largest summed time
+    # dominant kernel: the transform phase with the largest summed time; its
+    # bound is whichever of MFMA and HBM time at peak is larger
     pf = phase_flops(w)
+    pb = phase_bytes(w, args.prec)
     dom = max(pf, key=lambda p: phases[p]["ms"])
     avg_ms = phases[dom]["ms"] / max(phases[dom]["launches"], 1)
-    items_per_launch = w.npairs / max(phases[dom]["launches"] / args.steps, 1)
-    flops_launch = pf[dom] * items_per_launch
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    peak = PEAKS_TFLOPS[args.prec]
+    launches_per_step = max(phases[dom]["launches"] / args.steps, 1)
+    flops_launch = pf[dom] * w.npairs / launches_per_step
+    bytes_launch = pb[dom] / launches_per_step
+    peak_f = PEAKS_TFLOPS[args.prec]
+    hbm_bound = bytes_launch / (HBM_PEAK_GBS * 1e9) >= flops_launch / (peak_f * 1e12)
+    traffic = recorded_traffic(w.name, args.prec, dom)
+    if hbm_bound:
+        roof = {"bound": "hbm", "achieved": bytes_launch / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "algorithmic_bytes_per_launch": bytes_launch}
+    else:
+        roof = {"bound": "mfma", "achieved": flops_launch / (avg_ms * 1e-3) / 1e12, "peak": peak_f,
+                "unit": "TFLOP/s", "algorithmic_flops_per_launch": flops_launch}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof.update({"kernel": dom, "avg_launch_ms": avg_ms,
+                 "mfma_tflops": flops_launch / (avg_ms * 1e-3) / 1e12, "mfma_peak": peak_f,
+                 "hbm_gbs": bytes_launch / (avg_ms * 1e-3) / 1e9})
     total_flops = sum(pf.values()) * w.npairs
     result = {
         "metric": METRIC,
@@ -147,9 +231,7 @@ def main():
         "config": {"workload": w.name, "grid": list(w.n), "h": list(w.h), "fd_order": w.order,
                    "bc": list(w.bc), "kernel": w.kernel, "omega": w.omega, "norb": w.norb,
                    "pairs": w.npairs, "prec": args.prec, "storage": w.storage},
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch},
+        "roofline": roof,
         "vx_time_ms": ms_step,
         "tflops_whole_step": total_flops / (ms_step * 1e-3) / 1e12,
         "flops_per_pair": sum(pf.values()),
