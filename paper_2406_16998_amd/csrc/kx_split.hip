@@ -76,7 +76,6 @@ __device__ __forceinline__ f4 mma6(const Split4& a, const Split4& b, f4 c) {
 }
 
 constexpr f4 kZ = {0.f, 0.f, 0.f, 0.f};
-constexpr int kSInvEl = 16;  // inverse: staged elements per thread per chunk
 constexpr int kSplitKc = 16; // staged K rows per chunk: one MFMA k-step
 
 extern __shared__ __align__(16) float kx_split_lds[];
@@ -121,7 +120,9 @@ __device__ __forceinline__ void sf_store(const f4* acc2, float* __restrict__ Tzb
 // Workgroup layout as the FP32/FP64 forward pass (one wave per x parity q,
 // y parity p, 16-wide b strip; `slabs` z-slabs); staged folded rows in
 // chunks of kc (a multiple of 16).
-template <class S, int NT, bool OFULL, int MODE, int MT>
+// XST: some staged positions exceed the register budget (grids whose x
+// extent is large against y) and are loaded directly in the stash step.
+template <class S, int NT, bool OFULL, int MODE, bool XST, int MT>
 __global__ void __launch_bounds__(MT)
 split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict__ items,
               float* __restrict__ T, int slabs, int kc, int qsplit) {
@@ -199,11 +200,12 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
       const int pos = stid + k * sthreads;
       if (pos < npos) store_pos(buf, pos, y0, ra[k], rb[k]);
     }
-    // positions beyond the register budget (narrow y extents): direct
-    for (int pos = stid + kFwdPos * sthreads; pos < npos; pos += sthreads) {
-      double va[4], vb[4];
-      load_pos(pos, y0, va, vb);
-      store_pos(buf, pos, y0, va, vb);
+    if (XST) {
+      for (int pos = stid + kFwdPos * sthreads; pos < npos; pos += sthreads) {
+        double va[4], vb[4];
+        load_pos(pos, y0, va, vb);
+        store_pos(buf, pos, y0, va, vb);
+      }
     }
   };
 
@@ -445,57 +447,50 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
   const int pe2 = g.pe2, po2 = g.po2, p2 = g.p2;
   const int celems = 2 * kc * p2;
   float* __restrict__ sb = lds + (size_t)s * 2 * celems;
-  const int sthreads = nstr * 64;
-  const int stid = tid - s * sthreads;
   const float* __restrict__ Tz = T + (long long)it * g.slot + (long long)(zin ? z : 0) * g.slab;
-  // staged chunk [q][kc][p2]: rows a0 + aa of the x-parity q blocks
-  auto load_el = [&](int idx, int a0) {
-    const int row = idx / p2, col = idx - row * p2;
-    const int qq = row / kc, aa = row - qq * kc;
-    const int mq = qq == 0 ? g.me1 : g.mo1;
-    const bool ok = zin && idx < celems && a0 + aa < mq;
-    const unsigned a = (qq == 0 ? 0 : g.pe1) + a0 + aa;
-    return ok ? Tz[a * (unsigned)p2 + col] : 0.f;
-  };
-  float pa[kSInvEl];
-  auto fetch = [&](int a0) {
-#pragma unroll
-    for (int k = 0; k < kSInvEl; ++k) pa[k] = load_el(stid + k * sthreads, a0);
-  };
-  auto stash = [&](float* buf, int a0) {
-#pragma unroll
-    for (int k = 0; k < kSInvEl; ++k) {
-      const int idx = stid + k * sthreads;
-      if (idx < celems) buf[idx] = pa[k];
+  // Staged chunk [q][kc][p2]: rows a0 .. a0 + kc of the even (q = 0) and odd
+  // (q = 1) x-parity blocks of this slab, contiguous in T.  Copied global ->
+  // LDS without registers, 1 KB per wave instruction (16 bytes a lane); the
+  // padded rows of T hold zeros, and odd rows past po1 are never multiplied.
+  const int segs = p2 / kTile;  // 1 KB segments per block of kc = 16 rows
+  const int wv = wave - s * nstr;
+  auto issue = [&](float* buf, int a0) {
+    for (int sg = wv; sg < 2 * segs; sg += nstr) {
+      const int qq = sg >= segs ? 1 : 0, k = sg - qq * segs;
+      if (qq == 1 && a0 >= g.po1) break;
+      const float* src = Tz + (size_t)((qq ? g.pe1 : 0) + a0) * p2 + k * 256 + lane * 4;
+      __builtin_amdgcn_global_load_lds(src, buf + qq * kc * p2 + k * 256, 16, 0, 0);
     }
-    // elements beyond the register budget (wide y extents): direct
-    for (int idx = stid + kSInvEl * sthreads; idx < celems; idx += sthreads) buf[idx] = load_el(idx, a0);
   };
-
   const int xp = x0 + li;
   const bool has_o = x0 < g.po1;
   f4 acc1[4 * NT];
 #pragma unroll
   for (int k = 0; k < 4 * NT; ++k) acc1[k] = kZ;
   const int nchunks = (g.me1 + kc - 1) / kc;
-  fetch(0);
-  stash(sb, 0);
+  // B[k = a'][n = x'] = V1q[x'][a'] (rows x', k = a' contiguous; padded rows
+  // are zero), loaded one chunk ahead so that the only wait on global memory
+  // in the loop is the end-of-chunk wait for the staging copies
+  Split4 be_n, bo_n = {};
+  auto load_b = [&](int a0) {
+    be_n = load_split(e.E[0] + xp * g.pe1 + a0 + 4 * lg, g.pe1 * g.pe1);
+    if (has_o && a0 < g.po1) bo_n = load_split(e.O[0] + xp * g.po1 + a0 + 4 * lg, g.po1 * g.po1);
+  };
+  load_b(0);
+  issue(sb, 0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
     const float* __restrict__ cur = sb + (c & 1) * celems;
-    if (c + 1 < nchunks) fetch((c + 1) * kc);
     const int a0 = c * kc;
-    for (int kk = 0; kk < kc && a0 + kk < g.pe1; kk += kTile) {
-      // B[k = a'][n = x'] = V1q[x'][a'] (rows x', k = a' contiguous); padded rows are zero
-      const Split4 be = load_split(e.E[0] + xp * g.pe1 + a0 + kk + 4 * lg, g.pe1 * g.pe1);
-      si_k_step<NT, NTO>(acc1, cur + (kk + 4 * lg) * p2 + li, p2, pe2, be);
-      if (has_o && a0 + kk < g.po1) {
-        const Split4 bo = load_split(e.O[0] + xp * g.po1 + a0 + kk + 4 * lg, g.po1 * g.po1);
-        si_k_step<NT, NTO>(acc1 + 2 * NT, cur + (kc + kk + 4 * lg) * p2 + li, p2, pe2, bo);
-      }
-      __builtin_amdgcn_sched_barrier(0);
+    const Split4 be = be_n, bo = bo_n;
+    if (c + 1 < nchunks) {
+      load_b(a0 + kc);
+      issue(sb + ((c + 1) & 1) * celems, a0 + kc);
     }
-    if (c + 1 < nchunks) stash(sb + ((c + 1) & 1) * celems, (c + 1) * kc);
+    si_k_step<NT, NTO>(acc1, cur + 4 * lg * p2 + li, p2, pe2, be);
+    if (has_o && a0 < g.po1) si_k_step<NT, NTO>(acc1 + 2 * NT, cur + (kc + 4 * lg) * p2 + li, p2, pe2, bo);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
   // split the W tiles once; they are the B operands of every y' tile
@@ -566,12 +561,20 @@ hipError_t sfwd_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e
   const dim3 block(64 * p.waves);
   const size_t lb = p.lds_bytes;
   const bool of = g.po1 == g.pe1;
+  const int wps = (p.qsplit == 1 ? 2 : 1) * (g.p2 / kTile);
+  const bool xst = p.kc * g.pe1 > kFwdPos * wps * 64;
   switch (g.pe1 / kTile) {
 #define KX_CASE(NT)                                                                          \
   case NT: {                                                                                 \
     constexpr int MT = fwd_mt(NT);                                                           \
-    auto k = mode == 1 ? (of ? split_forward<S, NT, true, 1, MT> : split_forward<S, NT, false, 1, MT>) \
-                       : (of ? split_forward<S, NT, true, 0, MT> : split_forward<S, NT, false, 0, MT>); \
+    auto k = xst ? (mode == 1 ? (of ? split_forward<S, NT, true, 1, true, MT>                  \
+                                    : split_forward<S, NT, false, 1, true, MT>)                \
+                              : (of ? split_forward<S, NT, true, 0, true, MT>                  \
+                                    : split_forward<S, NT, false, 0, true, MT>))               \
+                 : (mode == 1 ? (of ? split_forward<S, NT, true, 1, false, MT>                 \
+                                    : split_forward<S, NT, false, 1, false, MT>)               \
+                              : (of ? split_forward<S, NT, true, 0, false, MT>                 \
+                                    : split_forward<S, NT, false, 0, false, MT>));             \
     allow_lds(k, lb);                                                                        \
     hipLaunchKernelGGL(k, grid, block, lb, st, g, e, src, items, T, p.slabs, p.kc, p.qsplit); \
     break;                                                                                   \
@@ -613,6 +616,7 @@ hipError_t sinv_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e
                        const Item* items, int nitems, const S* psi, const double* occ, S* dst,
                        hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
+  if (p.kc != kTile) return hipErrorInvalidValue;  // chunks are exactly one k-step
   const dim3 grid((g.n3 + p.slabs - 1) / p.slabs, nitems);
   const dim3 block(64 * p.waves);
   const size_t lb = p.lds_bytes;
