@@ -104,7 +104,10 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
  * updates orbital j and, if i != j, orbital i.  occ_host[norb] are the
  * spin-summed occupations used as literal weights (a closed shell with
  * occ = 2 gives twice the per-spin operator of Eq. (3)).
- *   dtype, prec  as for kx_apply_fL
+ *   dtype, prec  as for kx_apply_fL.  With KX_PREC_FP32 or KX_PREC_BF16X3 on
+ *              KX_F64 storage the orbitals are rounded to FP32 once and
+ *              Vx psi is accumulated in FP32 before it is widened into
+ *              vxpsi_dev (the handle keeps 8*norb*N bytes of FP32 copies).
  *   psi_dev    norb*N orbitals (read only)
  *   vxpsi_dev  norb*N outputs, overwritten (not accumulated into)
  * Also prepares E_x = -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h with

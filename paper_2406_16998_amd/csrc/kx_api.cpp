@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -149,6 +150,11 @@ struct kx_grid {
   double* hOcc = nullptr;  // pinned staging
   hipEvent_t occ_done = nullptr;
   double* dPairE = nullptr;
+  // FP32 working copies of psi and Vx psi for reduced-precision exchange on
+  // FP64 storage (elements each)
+  float* dPsi32 = nullptr;
+  float* dVx32 = nullptr;
+  size_t work32_cap = 0;
   long long pairE_cap = 0;
   double* dEx = nullptr;
   int last_norb = -1;
@@ -763,6 +769,8 @@ kx_status kx_destroy(kx_grid* g) {
   dev_free(g->dOcc);
   dev_free(g->dPairE);
   dev_free(g->dEx);
+  dev_free(g->dPsi32);
+  dev_free(g->dVx32);
   if (g->hOcc) (void)hipHostFree(g->hOcc);
   if (g->occ_done) (void)hipEventDestroy(g->occ_done);
   for (hipEvent_t ev : g->prof_ev) (void)hipEventDestroy(ev);
@@ -867,15 +875,44 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
   std::memcpy(g->hOcc, occ_host, sizeof(double) * norb);
   KX_HIP(hipMemcpyAsync(g->dOcc, g->hOcc, sizeof(double) * norb, hipMemcpyHostToDevice, g->stream));
   KX_HIP(hipEventRecord(g->occ_done, g->stream));
-  KX_HIP(hipMemsetAsync(vxpsi_dev, 0, elem_size(dtype) * (size_t)norb * g->geom.N, g->stream));
+  // Reduced precision on FP64 storage: the orbitals are rounded to FP32 once
+  // and Vx psi is accumulated in FP32, then widened into the output; the
+  // per-pair passes then move half the bytes.
+  const size_t nel = (size_t)norb * g->geom.N;
+  const bool narrow = prec != KX_PREC_FP64 && dtype == KX_F64 &&
+                      (reinterpret_cast<uintptr_t>(psi_dev) % 16) == 0 &&
+                      (reinterpret_cast<uintptr_t>(vxpsi_dev) % 16) == 0;
+  const void* psi_w = psi_dev;
+  void* vx_w = vxpsi_dev;
+  int dtype_w = dtype;
+  if (narrow) {
+    if (nel > g->work32_cap) {
+      KX_HIP(hipStreamSynchronize(g->stream));
+      dev_free(g->dPsi32);
+      dev_free(g->dVx32);
+      g->dPsi32 = g->dVx32 = nullptr;
+      g->work32_cap = 0;
+      st = dev_alloc((void**)&g->dPsi32, sizeof(float) * nel);
+      if (st != KX_OK) return st;
+      st = dev_alloc((void**)&g->dVx32, sizeof(float) * nel);
+      if (st != KX_OK) return st;
+      g->work32_cap = nel;
+    }
+    KX_HIP(launch_narrow((const double*)psi_dev, g->dPsi32, (long long)nel, g->stream));
+    psi_w = g->dPsi32;
+    vx_w = g->dVx32;
+    dtype_w = KX_F32;
+  }
+  KX_HIP(hipMemsetAsync(vx_w, 0, elem_size(dtype_w) * nel, g->stream));
 
   const double dV = g->h[0] * g->h[1] * g->h[2];
   for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
     const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
     if (nb <= 0) continue;
-    KX_HIP(run_batch(g, 1, prec, dtype, psi_dev, g->dItems + o0, nb, psi_dev, g->dOcc, vxpsi_dev,
-                     norb, dV));
+    KX_HIP(run_batch(g, 1, prec, dtype_w, psi_w, g->dItems + o0, nb, psi_w, g->dOcc, vx_w, norb,
+                     dV));
   }
+  if (narrow) KX_HIP(launch_widen(g->dVx32, (double*)vxpsi_dev, (long long)nel, g->stream));
   KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
     return launch_exchange_energy(g->dPairE, g->dOcc, norb, g->dEx, g->stream);
   }));

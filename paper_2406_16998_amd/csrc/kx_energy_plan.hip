@@ -60,7 +60,50 @@ exchange_energy_kernel(const double* __restrict__ pair_e, const double* __restri
   if (threadIdx.x == 0) ex[0] = -0.25 * tot;
 }
 
+// elementwise precision conversion, 4 elements a thread per step
+__global__ void __launch_bounds__(256) narrow_kernel(const double* __restrict__ a, float* __restrict__ b,
+                                                     long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x * 4;
+  for (long long k = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4; k < n; k += stride) {
+    if (k + 3 < n) {
+      const double2 u = *reinterpret_cast<const double2*>(a + k);
+      const double2 v = *reinterpret_cast<const double2*>(a + k + 2);
+      *reinterpret_cast<float4*>(b + k) = make_float4((float)u.x, (float)u.y, (float)v.x, (float)v.y);
+    } else {
+      for (long long m = k; m < n; ++m) b[m] = (float)a[m];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ a, double* __restrict__ b,
+                                                    long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x * 4;
+  for (long long k = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4; k < n; k += stride) {
+    if (k + 3 < n) {
+      const float4 u = *reinterpret_cast<const float4*>(a + k);
+      *reinterpret_cast<double2*>(b + k) = make_double2(u.x, u.y);
+      *reinterpret_cast<double2*>(b + k + 2) = make_double2(u.z, u.w);
+    } else {
+      for (long long m = k; m < n; ++m) b[m] = a[m];
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_narrow(const double* a, float* b, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 1023) / 1024, 8192);
+  hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen(const float* a, double* b, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 1023) / 1024, 8192);
+  hipLaunchKernelGGL(widen_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
 
 // ================================================================ planning
 Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {

@@ -144,6 +144,9 @@ hipError_t launch_pencil_s(const Geom& g, const PencilPlan& p, const EigS& e, co
 hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigS& e, const float* T, const Item* items, int nitems,
                             const void* psi, const double* occ, void* dst, hipStream_t s);
+// b[k] = (float)a[k] and a[k] = b[k] widened, k < n (16-byte aligned arrays)
+hipError_t launch_narrow(const double* a, float* b, long long n, hipStream_t s);
+hipError_t launch_widen(const float* a, double* b, long long n, hipStream_t s);
 // per-item energies: pair_e[index(i, j)] = dV * sum_s epart[k*nstrips + s]
 hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* items, int nitems,
                               int norb, double dV, double* pair_e, hipStream_t s);

@@ -157,7 +157,9 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
   const int npos = kc * g.pe1;
   // one staged position: the four mirror images (y, x), (y, n1-1-x),
   // (n2-1-y, x), (n2-1-y, n1-1-x) of the pair product
-  auto load_pos = [&](int pos, int y0, double* va, double* vb) {
+  // raw loads stay in storage precision until the stash step, so the
+  // prefetch does not wait on them
+  auto load_pos = [&](int pos, int y0, S* va, S* vb) {
     const int yy = pos / g.pe1, xp = pos - yy * g.pe1;
     const int y = y0 + yy, ym = g.n2 - 1 - y, xm = g.n1 - 1 - xp;
     const bool in = zin && pos < npos && y < g.me2 && xp < g.me1;
@@ -166,15 +168,15 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
     const bool ok[4] = {in, hx, hy, hx && hy};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      va[m] = ok[m] ? (double)s0[o[m]] : 0.0;
-      if (MODE == 1) vb[m] = ok[m] ? (double)s1[o[m]] : 0.0;
+      va[m] = ok[m] ? s0[o[m]] : S(0);
+      if (MODE == 1) vb[m] = ok[m] ? s1[o[m]] : S(0);
     }
   };
-  auto store_pos = [&](float* buf, int pos, int ybase, const double* va, const double* vb) {
+  auto store_pos = [&](float* buf, int pos, int ybase, const S* va, const S* vb) {
     const int yy = pos / g.pe1, xp = pos - yy * g.pe1;
     double v[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = (MODE == 1) ? va[m] * vb[m] : va[m];
+    for (int m = 0; m < 4; ++m) v[m] = (MODE == 1) ? (double)va[m] * (double)vb[m] : (double)va[m];
     const double sx0 = v[0] + v[1], dx0 = v[0] - v[1];
     const double sx1 = v[2] + v[3], dx1 = v[2] - v[3];
     const int y = yy + ybase;
@@ -189,7 +191,7 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
       buf[(1 * kc + yy) * wrow + qcol(qq) + xp] = (float)vo;
     }
   };
-  double ra[kFwdPos][4], rb[kFwdPos][4];
+  S ra[kFwdPos][4], rb[kFwdPos][4];
   auto fetch = [&](int y0) {
 #pragma unroll
     for (int k = 0; k < kFwdPos; ++k) load_pos(stid + k * sthreads, y0, ra[k], rb[k]);
@@ -202,7 +204,7 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
     }
     if (XST) {
       for (int pos = stid + kFwdPos * sthreads; pos < npos; pos += sthreads) {
-        double va[4], vb[4];
+        S va[4], vb[4];
         load_pos(pos, y0, va, vb);
         store_pos(buf, pos, y0, va, vb);
       }
