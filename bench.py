@@ -49,8 +49,9 @@ def phase_bytes(w, prec):
       forward  reads psi_i, psi_j, writes T            (2s + t) N
       pencil   reads and writes T                       2t N  (+ the f table once a launch)
       inverse  reads T, psi_i, psi_j, read-modify-writes Vx psi_i, Vx psi_j   (t + 6s) N
-    A diagonal pair (i = i) touches one orbital: (s + t), 2t, (t + 3s) N."""
-    s = 8 if w.storage == "f64" else 4
+    A diagonal pair (i = i) touches one orbital: (s + t), 2t, (t + 3s) N.
+    Reduced precision on FP64 storage runs on FP32 working copies (s = 4)."""
+    s = 8 if (w.storage == "f64" and prec == "fp64") else 4
     t = T_BYTES[prec]
     off, diag = w.norb * (w.norb - 1) // 2, w.norb
     N = w.N
