@@ -1,0 +1,70 @@
+"""The large periodic workload: 256 orbitals on 144^3, FP32 orbital storage,
+erfc kernel, 32896 pair solves per application.
+
+The oracle cannot run every pair at this size, so the checks are:
+  * the FP64 GPU path against oracle pair energies on a seeded sample of
+    pairs (the oracle reads the FP32 orbitals promoted exactly to FP64, so the
+    difference is compute error only): 1e-10 relative;
+  * each reduced precision against the same oracle sample at its energy
+    tolerance, and against the full FP64 GPU path for E_x and Vx psi.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import make_workload
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TOL64 = 1e-10
+TOL32_FIELD = 1e-5
+TOL32_ENERGY = 1e-6
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def test_periodic144_f32_storage_sampled():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_16998_amd import kx
+
+    name = "periodic144_erfc_f32"
+    print(f"generating {name}", flush=True)
+    w, psi, occ = make_workload(name)
+    assert psi.dtype == np.float32
+    psi_d = torch.from_numpy(psi).cuda()
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+
+    rng = np.random.default_rng(5)
+    sample = [(0, 0), (255, 255)] + [tuple(sorted(rng.choice(w.norb, 2, replace=False)))
+                                     for _ in range(8)]
+    grid = orc.make_grid(w.n, w.h, w.order, w.bc)
+    F = orc.kernel_values(grid.lam_sum(), w.kernel, w.omega)
+    ref = np.array([orc.pair_energy(psi[i].astype(np.float64), psi[j].astype(np.float64), grid,
+                                    w.kernel, w.omega, F) for i, j in sample])
+    emax = float(np.max(np.abs(ref)))
+    print("oracle sample done", flush=True)
+
+    vx64 = g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec="fp64")
+    ex64 = g.exchange_energy()
+    pe64 = g.pair_energies(sample)
+    print(f"fp64 E_x={ex64!r}", flush=True)
+    for e, r in zip(pe64, ref):
+        assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * emax
+    vx64 = vx64.cpu().numpy()
+
+    for prec in ("fp32", "bf16x3"):
+        vx = g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec=prec)
+        ex = g.exchange_energy()
+        pe = g.pair_energies(sample)
+        print(f"{prec} E_x={ex!r} |dE| vs fp64 = {abs(ex - ex64):.3e} Ha", flush=True)
+        assert abs(ex - ex64) <= TOL32_ENERGY * abs(ex64)
+        for e, r in zip(pe, ref):
+            assert abs(e - r) <= TOL32_ENERGY * emax
+        vx = vx.cpu().numpy()
+        for j in (0, 131, 255):
+            assert _rel(vx[j], vx64[j]) <= TOL32_FIELD, (prec, j)
+        del vx
+    g.close()
