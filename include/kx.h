@@ -118,6 +118,26 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
                             const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                             int prec);
 
+/* Ragged batch: the exact-exchange application of nsys independent systems
+ * (each its own handle, grid, boundary conditions, kernel, omega, orbital
+ * count), recorded once into one HIP graph with one branch per system and
+ * replayed by a single graph launch while the handles, their buffers and
+ * the arguments below are unchanged (recorded again otherwise).
+ *   grids[nsys]      distinct handles (each owns its workspace)
+ *   kernels, omegas, norbs   per system, as for kx_apply_exchange
+ *   dtype, prec      shared by all systems
+ *   psi_dev, occ_host, vxpsi_dev  per system, as for kx_apply_exchange
+ *   ex_out           NULL or nsys doubles: E_x per system
+ * Synchronises before returning; afterwards kx_exchange_energy and
+ * kx_pair_energies on each handle report that system.  Validation and all
+ * allocation happen before any recorded work; on error no system is
+ * partially updated except through a device failure (KX_ERR_DEVICE).
+ * The recorded graph lives with grids[0] and is released by kx_destroy. */
+kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* kernels,
+                                  const double* omegas, const int* norbs, int dtype,
+                                  const void* const* psi_dev, const double* const* occ_host,
+                                  void* const* vxpsi_dev, int prec, double* ex_out);
+
 /* E_x of the last kx_apply_exchange on this handle.  Synchronises the stream.
  * KX_ERR_STATE if there was none. */
 kx_status kx_exchange_energy(kx_grid* g, double* ex_out);

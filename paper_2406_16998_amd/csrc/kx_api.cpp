@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -160,6 +161,21 @@ struct kx_grid {
   int last_norb = -1;
   // optional per-launch timing (hipEvents on the handle's stream)
   bool prof_on = false;
+  bool capturing = false;  // work is being recorded into a graph: no timing events
+  // identity and buffer generation: a recorded graph bakes in device
+  // addresses, so any reallocation invalidates it
+  unsigned long long id = 0;
+  unsigned long long gen = 0;
+  // the recorded multi-system exchange whose origin stream is this handle's
+  struct BatchGraph {
+    std::vector<unsigned long long> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t origin = nullptr;        // capture and replay stream
+    std::vector<hipStream_t> branch;     // one per system
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+  } batch;
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_kind;
 };
@@ -283,6 +299,7 @@ kx_status ensure_ftable(kx_grid* g, int kernel, double omega) {
   const double om = (kernel == KX_KERNEL_ERFC) ? omega : 0.0;
   if (g->dF && g->f_kernel == kernel && g->f_omega == om) return KX_OK;
   if (!g->dF) {
+    ++g->gen;
     kx_status st = dev_alloc((void**)&g->dF, sizeof(double) * g->geom.fsize);
     if (st != KX_OK) return st;
   }
@@ -303,6 +320,7 @@ kx_status ensure_workspace(kx_grid* g, int slots) {
   g->dT = nullptr;
   g->dEpart = nullptr;
   g->slots = 0;
+  ++g->gen;
   kx_status st = dev_alloc((void**)&g->dT, sizeof(double) * (size_t)g->geom.slot * slots);
   if (st != KX_OK) return st;
   // padded rows are never written by the kernels; keep them zero
@@ -316,26 +334,26 @@ kx_status ensure_workspace(kx_grid* g, int slots) {
 
 // Bracket one kernel launch with timing events when profiling is on.
 template <class F>
-hipError_t timed(kx_grid* g, int kind, F&& launch) {
-  if (!g->prof_on) return launch();
+hipError_t timed(kx_grid* g, hipStream_t s, int kind, F&& launch) {
+  if (!g->prof_on || g->capturing) return launch();
   const size_t k = g->prof_kind.size();
   while (g->prof_ev.size() < 2 * (k + 1)) {
     hipEvent_t ev;
     if (hipEventCreate(&ev) != hipSuccess) return hipErrorOutOfMemory;
     g->prof_ev.push_back(ev);
   }
-  hipError_t e = hipEventRecord(g->prof_ev[2 * k], g->stream);
+  hipError_t e = hipEventRecord(g->prof_ev[2 * k], s);
   if (e != hipSuccess) return e;
   e = launch();
   if (e != hipSuccess) return e;
-  e = hipEventRecord(g->prof_ev[2 * k + 1], g->stream);
+  e = hipEventRecord(g->prof_ev[2 * k + 1], s);
   g->prof_kind.push_back(kind);
   return e;
 }
 
 // One batch of nb items through the three transform passes (and, for the
 // exchange, the per-pair energy reduction), in the arithmetic of prec.
-hipError_t run_batch(kx_grid* g, int mode, int prec, int dtype, const void* src, const Item* it,
+hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int dtype, const void* src, const Item* it,
                      int nb, const void* psi, const double* occ, void* dst, int norb, double dV) {
   const Geom& G = g->geom;
   double* epart = mode == 1 ? g->dEpart : nullptr;
@@ -344,63 +362,63 @@ hipError_t run_batch(kx_grid* g, int mode, int prec, int dtype, const void* src,
   if (prec == KX_PREC_FP64) {
     const EigR<double> E = eig_of(g);
     double* T = (double*)g->dT;
-    e = timed(g, KX_PHASE_FORWARD, [&] {
-      return launch_forward_d(dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, g->stream);
+    e = timed(g, st, KX_PHASE_FORWARD, [&] {
+      return launch_forward_d(dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, st);
     });
     if (e != hipSuccess) return e;
-    e = timed(g, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, epart, g->stream);
+    e = timed(g, st, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, epart, st);
     });
     if (e != hipSuccess) return e;
     if (mode == 1) {
-      e = timed(g, KX_PHASE_ENERGY, [&] {
-        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
+      e = timed(g, st, KX_PHASE_ENERGY, [&] {
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
       });
       if (e != hipSuccess) return e;
     }
-    return timed(g, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_d(dtype, mode, G, g->plan_d.inv, E, T, it, nb, psi, occ, dst, g->stream);
+    return timed(g, st, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_d(dtype, mode, G, g->plan_d.inv, E, T, it, nb, psi, occ, dst, st);
     });
   }
   if (prec == KX_PREC_BF16X3) {
     const EigS E = eigs_of(g);
     float* T = (float*)g->dT;
-    e = timed(g, KX_PHASE_FORWARD, [&] {
-      return launch_forward_s(dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, g->stream);
+    e = timed(g, st, KX_PHASE_FORWARD, [&] {
+      return launch_forward_s(dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, st);
     });
     if (e != hipSuccess) return e;
-    e = timed(g, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_s(G, g->plan_s.pen, E, g->dF, nb, T, epart, g->stream);
+    e = timed(g, st, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_s(G, g->plan_s.pen, E, g->dF, nb, T, epart, st);
     });
     if (e != hipSuccess) return e;
     if (mode == 1) {
-      e = timed(g, KX_PHASE_ENERGY, [&] {
-        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
+      e = timed(g, st, KX_PHASE_ENERGY, [&] {
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
       });
       if (e != hipSuccess) return e;
     }
-    return timed(g, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, E, T, it, nb, psi, occ, dst, g->stream);
+    return timed(g, st, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, E, T, it, nb, psi, occ, dst, st);
     });
   }
   const EigR<float> E = eigf_of(g);
   float* T = (float*)g->dT;
-  e = timed(g, KX_PHASE_FORWARD, [&] {
-    return launch_forward_f(dtype, mode, G, g->plan_f.fwd, E, src, it, nb, T, g->stream);
+  e = timed(g, st, KX_PHASE_FORWARD, [&] {
+    return launch_forward_f(dtype, mode, G, g->plan_f.fwd, E, src, it, nb, T, st);
   });
   if (e != hipSuccess) return e;
-  e = timed(g, KX_PHASE_PENCIL, [&] {
-    return launch_pencil_f(G, g->plan_f.pen, E, g->dF, nb, T, epart, g->stream);
+  e = timed(g, st, KX_PHASE_PENCIL, [&] {
+    return launch_pencil_f(G, g->plan_f.pen, E, g->dF, nb, T, epart, st);
   });
   if (e != hipSuccess) return e;
   if (mode == 1) {
-    e = timed(g, KX_PHASE_ENERGY, [&] {
-      return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, g->stream);
+    e = timed(g, st, KX_PHASE_ENERGY, [&] {
+      return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
     });
     if (e != hipSuccess) return e;
   }
-  return timed(g, KX_PHASE_INVERSE, [&] {
-    return launch_inverse_f(dtype, mode, G, g->plan_f.inv, E, T, it, nb, psi, occ, dst, g->stream);
+  return timed(g, st, KX_PHASE_INVERSE, [&] {
+    return launch_inverse_f(dtype, mode, G, g->plan_f.inv, E, T, it, nb, psi, occ, dst, st);
   });
 }
 
@@ -408,6 +426,7 @@ kx_status upload_items(kx_grid* g, int kind, int key, int maxb, const std::vecto
   if (g->items_key_kind == kind && g->items_key == key && g->items_maxb == maxb) return KX_OK;
   KX_HIP(hipStreamSynchronize(g->stream));
   if (items.size() > g->items_cap) {
+    ++g->gen;
     dev_free(g->dItems);
     g->dItems = nullptr;
     g->items_cap = 0;
@@ -421,6 +440,171 @@ kx_status upload_items(kx_grid* g, int kind, int key, int maxb, const std::vecto
   g->items_key = key;
   g->items_maxb = maxb;
   return KX_OK;
+}
+
+// One exchange application, resolved against the handle's buffers.
+struct XPlan {
+  int kernel = 0, norb = 0, prec = 0, dtype = 0, dtype_w = 0;
+  double omega = 0.0, dV = 0.0;
+  bool narrow = false;  // reduced precision on FP64 storage: FP32 working copies
+  const void* psi = nullptr;
+  void* vx = nullptr;
+  const void* psi_w = nullptr;
+  void* vx_w = nullptr;
+  size_t nel = 0;
+};
+
+// Validate the arguments, make every buffer the application needs (workspace,
+// schedule, f table, results, working copies) and upload the occupations on
+// the handle's stream.  May synchronise the stream (allocation).
+kx_status prepare_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
+                           const void* psi_dev, const double* occ_host, void* vxpsi_dev, int prec,
+                           XPlan& xp) {
+  if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
+  kx_status st = check_kernel_args(g, kernel, omega);
+  if (st != KX_OK) return st;
+  st = check_types(g, dtype, prec);
+  if (st != KX_OK) return st;
+  if (norb > 0 && (!psi_dev || !vxpsi_dev || !occ_host)) return KX_ERR_INVALID_ARG;
+  if (psi_dev && psi_dev == vxpsi_dev) return KX_ERR_INVALID_ARG;
+  if ((double)norb * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
+  for (int i = 0; i < norb; ++i)
+    if (!std::isfinite(occ_host[i])) return KX_ERR_INVALID_ARG;
+
+  const long long npairs = (long long)norb * (norb + 1) / 2;
+  // results buffers
+  if (npairs > g->pairE_cap) {
+    KX_HIP(hipStreamSynchronize(g->stream));
+    ++g->gen;
+    dev_free(g->dPairE);
+    g->dPairE = nullptr;
+    g->pairE_cap = 0;
+    st = dev_alloc((void**)&g->dPairE, sizeof(double) * std::max<long long>(npairs, 1));
+    if (st != KX_OK) return st;
+    g->pairE_cap = npairs;
+  }
+  if (norb > g->occ_cap) {
+    KX_HIP(hipStreamSynchronize(g->stream));
+    ++g->gen;
+    dev_free(g->dOcc);
+    if (g->hOcc) (void)hipHostFree(g->hOcc);
+    g->dOcc = nullptr;
+    g->hOcc = nullptr;
+    g->occ_cap = 0;
+    st = dev_alloc((void**)&g->dOcc, sizeof(double) * norb);
+    if (st != KX_OK) return st;
+    if (hipHostMalloc((void**)&g->hOcc, sizeof(double) * norb, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      g->hOcc = nullptr;
+      return KX_ERR_OUT_OF_MEMORY;
+    }
+    g->occ_cap = norb;
+  }
+  xp = XPlan();
+  xp.kernel = kernel;
+  xp.omega = omega;
+  xp.norb = norb;
+  xp.prec = prec;
+  xp.dtype = xp.dtype_w = dtype;
+  xp.psi = xp.psi_w = psi_dev;
+  xp.vx = xp.vx_w = vxpsi_dev;
+  xp.dV = g->h[0] * g->h[1] * g->h[2];
+  if (norb == 0) return KX_OK;
+
+  // schedule (cached per norb and batch cap)
+  const int cap = g->max_slots;
+  if (!(g->items_key_kind == 1 && g->items_key == norb && g->items_maxb == cap)) {
+    build_schedule(norb, cap, g->sched_pairs, g->sched_offsets);
+  }
+  int maxb = 0;
+  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b)
+    maxb = std::max(maxb, g->sched_offsets[b + 1] - g->sched_offsets[b]);
+  st = ensure_workspace(g, maxb);
+  if (st != KX_OK) return st;
+  st = ensure_ftable(g, kernel, omega);
+  if (st != KX_OK) return st;
+  st = upload_items(g, 1, norb, cap, g->sched_pairs);
+  if (st != KX_OK) return st;
+
+  // occupations: pinned staging, reused once the previous upload finished
+  KX_HIP(hipEventSynchronize(g->occ_done));
+  std::memcpy(g->hOcc, occ_host, sizeof(double) * norb);
+  KX_HIP(hipMemcpyAsync(g->dOcc, g->hOcc, sizeof(double) * norb, hipMemcpyHostToDevice, g->stream));
+  KX_HIP(hipEventRecord(g->occ_done, g->stream));
+
+  // Reduced precision on FP64 storage: the orbitals are rounded to FP32 once
+  // and Vx psi is accumulated in FP32, then widened into the output; the
+  // per-pair passes then move half the bytes.
+  xp.nel = (size_t)norb * g->geom.N;
+  xp.narrow = prec != KX_PREC_FP64 && dtype == KX_F64 &&
+              (reinterpret_cast<uintptr_t>(psi_dev) % 16) == 0 &&
+              (reinterpret_cast<uintptr_t>(vxpsi_dev) % 16) == 0;
+  if (xp.narrow) {
+    if (xp.nel > g->work32_cap) {
+      KX_HIP(hipStreamSynchronize(g->stream));
+      ++g->gen;
+      dev_free(g->dPsi32);
+      dev_free(g->dVx32);
+      g->dPsi32 = g->dVx32 = nullptr;
+      g->work32_cap = 0;
+      st = dev_alloc((void**)&g->dPsi32, sizeof(float) * xp.nel);
+      if (st != KX_OK) return st;
+      st = dev_alloc((void**)&g->dVx32, sizeof(float) * xp.nel);
+      if (st != KX_OK) return st;
+      g->work32_cap = xp.nel;
+    }
+    xp.psi_w = g->dPsi32;
+    xp.vx_w = g->dVx32;
+    xp.dtype_w = KX_F32;
+  }
+  return KX_OK;
+}
+
+// The device work of one prepared exchange application, on stream s: kernels
+// only (no memset or host transfer), so it can be recorded into a graph.
+hipError_t enqueue_exchange(kx_grid* g, const XPlan& xp, hipStream_t s) {
+  if (xp.norb == 0) return launch_zero(g->dEx, sizeof(double), s);
+  hipError_t e;
+  if (xp.narrow) {
+    e = launch_narrow((const double*)xp.psi, g->dPsi32, (long long)xp.nel, s);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_zero(xp.vx_w, elem_size(xp.dtype_w) * xp.nel, s);
+  if (e != hipSuccess) return e;
+  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
+    const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
+    if (nb <= 0) continue;
+    e = run_batch(g, s, 1, xp.prec, xp.dtype_w, xp.psi_w, g->dItems + o0, nb, xp.psi_w, g->dOcc,
+                  xp.vx_w, xp.norb, xp.dV);
+    if (e != hipSuccess) return e;
+  }
+  if (xp.narrow) {
+    e = launch_widen(g->dVx32, (double*)xp.vx, (long long)xp.nel, s);
+    if (e != hipSuccess) return e;
+  }
+  return timed(g, s, KX_PHASE_ENERGY, [&] {
+    return launch_exchange_energy(g->dPairE, g->dOcc, xp.norb, g->dEx, s);
+  });
+}
+
+// Drop the recorded multi-system graph (and, with all, its streams/events).
+void release_batch_graph(kx_grid* g, bool all) {
+  auto& b = g->batch;
+  if (b.origin) (void)hipStreamSynchronize(b.origin);
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+  b.key.clear();
+  if (!all) return;
+  for (hipStream_t s : b.branch) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b.join) (void)hipEventDestroy(e);
+  if (b.fork) (void)hipEventDestroy(b.fork);
+  if (b.origin) (void)hipStreamDestroy(b.origin);
+  b.branch.clear();
+  b.join.clear();
+  b.fork = nullptr;
+  b.origin = nullptr;
 }
 
 }  // namespace
@@ -492,6 +676,10 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
 
   kx_grid* g = new (std::nothrow) kx_grid();
   if (!g) return KX_ERR_OUT_OF_MEMORY;
+  {
+    static std::atomic<unsigned long long> next_id{1};
+    g->id = next_id++;
+  }
   for (int k = 0; k < 3; ++k) {
     g->n[k] = n[k];
     g->h[k] = h[k];
@@ -746,6 +934,7 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
 kx_status kx_destroy(kx_grid* g) {
   if (!g) return KX_OK;
   (void)hipStreamSynchronize(g->stream);
+  release_batch_graph(g, true);
   for (int k = 0; k < 3; ++k) {
     dev_free(g->dVE[k]);
     dev_free(g->dVO[k]);
@@ -802,8 +991,8 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   if (st != KX_OK) return st;
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
-    KX_HIP(run_batch(g, 0, prec, dtype, rho_dev, g->dItems + b0, nb, nullptr, nullptr, phi_dev, 0,
-                     0.0));
+    KX_HIP(run_batch(g, g->stream, 0, prec, dtype, rho_dev, g->dItems + b0, nb, nullptr, nullptr,
+                     phi_dev, 0, 0.0));
   }
   return KX_OK;
 }
@@ -811,112 +1000,95 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
                             const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                             int prec) {
-  if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
-  kx_status st = check_kernel_args(g, kernel, omega);
+  if (!g) return KX_ERR_INVALID_ARG;
+  XPlan xp;
+  kx_status st = prepare_exchange(g, kernel, omega, norb, dtype, psi_dev, occ_host, vxpsi_dev, prec,
+                                  xp);
   if (st != KX_OK) return st;
-  st = check_types(g, dtype, prec);
-  if (st != KX_OK) return st;
-  if (norb > 0 && (!psi_dev || !vxpsi_dev || !occ_host)) return KX_ERR_INVALID_ARG;
-  if (psi_dev && psi_dev == vxpsi_dev) return KX_ERR_INVALID_ARG;
-  if ((double)norb * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
-  for (int i = 0; i < norb; ++i)
-    if (!std::isfinite(occ_host[i])) return KX_ERR_INVALID_ARG;
-
-  const long long npairs = (long long)norb * (norb + 1) / 2;
-  // results buffers
-  if (npairs > g->pairE_cap) {
-    KX_HIP(hipStreamSynchronize(g->stream));
-    dev_free(g->dPairE);
-    g->dPairE = nullptr;
-    g->pairE_cap = 0;
-    st = dev_alloc((void**)&g->dPairE, sizeof(double) * std::max<long long>(npairs, 1));
-    if (st != KX_OK) return st;
-    g->pairE_cap = npairs;
-  }
-  if (norb > g->occ_cap) {
-    KX_HIP(hipStreamSynchronize(g->stream));
-    dev_free(g->dOcc);
-    if (g->hOcc) (void)hipHostFree(g->hOcc);
-    g->dOcc = nullptr;
-    g->hOcc = nullptr;
-    g->occ_cap = 0;
-    st = dev_alloc((void**)&g->dOcc, sizeof(double) * norb);
-    if (st != KX_OK) return st;
-    if (hipHostMalloc((void**)&g->hOcc, sizeof(double) * norb, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      g->hOcc = nullptr;
-      return KX_ERR_OUT_OF_MEMORY;
-    }
-    g->occ_cap = norb;
-  }
-  if (norb == 0) {
-    KX_HIP(hipMemsetAsync(g->dEx, 0, sizeof(double), g->stream));
-    g->last_norb = 0;
-    return KX_OK;
-  }
-
-  // schedule (cached per norb and batch cap)
-  const int cap = g->max_slots;
-  if (!(g->items_key_kind == 1 && g->items_key == norb && g->items_maxb == cap)) {
-    build_schedule(norb, cap, g->sched_pairs, g->sched_offsets);
-  }
-  int maxb = 0;
-  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b)
-    maxb = std::max(maxb, g->sched_offsets[b + 1] - g->sched_offsets[b]);
-  st = ensure_workspace(g, maxb);
-  if (st != KX_OK) return st;
-  st = ensure_ftable(g, kernel, omega);
-  if (st != KX_OK) return st;
-  st = upload_items(g, 1, norb, cap, g->sched_pairs);
-  if (st != KX_OK) return st;
-
-  // occupations: pinned staging, reused once the previous upload finished
-  KX_HIP(hipEventSynchronize(g->occ_done));
-  std::memcpy(g->hOcc, occ_host, sizeof(double) * norb);
-  KX_HIP(hipMemcpyAsync(g->dOcc, g->hOcc, sizeof(double) * norb, hipMemcpyHostToDevice, g->stream));
-  KX_HIP(hipEventRecord(g->occ_done, g->stream));
-  // Reduced precision on FP64 storage: the orbitals are rounded to FP32 once
-  // and Vx psi is accumulated in FP32, then widened into the output; the
-  // per-pair passes then move half the bytes.
-  const size_t nel = (size_t)norb * g->geom.N;
-  const bool narrow = prec != KX_PREC_FP64 && dtype == KX_F64 &&
-                      (reinterpret_cast<uintptr_t>(psi_dev) % 16) == 0 &&
-                      (reinterpret_cast<uintptr_t>(vxpsi_dev) % 16) == 0;
-  const void* psi_w = psi_dev;
-  void* vx_w = vxpsi_dev;
-  int dtype_w = dtype;
-  if (narrow) {
-    if (nel > g->work32_cap) {
-      KX_HIP(hipStreamSynchronize(g->stream));
-      dev_free(g->dPsi32);
-      dev_free(g->dVx32);
-      g->dPsi32 = g->dVx32 = nullptr;
-      g->work32_cap = 0;
-      st = dev_alloc((void**)&g->dPsi32, sizeof(float) * nel);
-      if (st != KX_OK) return st;
-      st = dev_alloc((void**)&g->dVx32, sizeof(float) * nel);
-      if (st != KX_OK) return st;
-      g->work32_cap = nel;
-    }
-    KX_HIP(launch_narrow((const double*)psi_dev, g->dPsi32, (long long)nel, g->stream));
-    psi_w = g->dPsi32;
-    vx_w = g->dVx32;
-    dtype_w = KX_F32;
-  }
-  KX_HIP(hipMemsetAsync(vx_w, 0, elem_size(dtype_w) * nel, g->stream));
-
-  const double dV = g->h[0] * g->h[1] * g->h[2];
-  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
-    const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
-    if (nb <= 0) continue;
-    KX_HIP(run_batch(g, 1, prec, dtype_w, psi_w, g->dItems + o0, nb, psi_w, g->dOcc, vx_w, norb,
-                     dV));
-  }
-  if (narrow) KX_HIP(launch_widen(g->dVx32, (double*)vxpsi_dev, (long long)nel, g->stream));
-  KX_HIP(timed(g, KX_PHASE_ENERGY, [&] {
-    return launch_exchange_energy(g->dPairE, g->dOcc, norb, g->dEx, g->stream);
-  }));
+  KX_HIP(enqueue_exchange(g, xp, g->stream));
   g->last_norb = norb;
+  return KX_OK;
+}
+
+kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* kernels,
+                                  const double* omegas, const int* norbs, int dtype,
+                                  const void* const* psi_dev, const double* const* occ_host,
+                                  void* const* vxpsi_dev, int prec, double* ex_out) {
+  if (nsys < 1 || nsys > 256 || !grids || !kernels || !omegas || !norbs || !psi_dev || !occ_host ||
+      !vxpsi_dev)
+    return KX_ERR_INVALID_ARG;
+  for (int k = 0; k < nsys; ++k) {
+    if (!grids[k]) return KX_ERR_INVALID_ARG;
+    for (int m = 0; m < k; ++m)
+      if (grids[m] == grids[k]) return KX_ERR_INVALID_ARG;  // one workspace per system
+  }
+  std::vector<XPlan> xps(nsys);
+  for (int k = 0; k < nsys; ++k) {
+    kx_status st = prepare_exchange(grids[k], kernels[k], omegas[k], norbs[k], dtype, psi_dev[k],
+                                    occ_host[k], vxpsi_dev[k], prec, xps[k]);
+    if (st != KX_OK) return st;
+  }
+  // uploads and any earlier work on the systems' own streams come first
+  for (int k = 0; k < nsys; ++k) KX_HIP(hipStreamSynchronize(grids[k]->stream));
+
+  kx_grid* o = grids[0];
+  auto& b = o->batch;
+  std::vector<unsigned long long> key;
+  for (int k = 0; k < nsys; ++k) {
+    unsigned long long om;
+    std::memcpy(&om, &omegas[k], sizeof om);
+    key.insert(key.end(), {grids[k]->id, grids[k]->gen, (unsigned long long)kernels[k], om,
+                           (unsigned long long)norbs[k], (unsigned long long)prec,
+                           (unsigned long long)dtype, (unsigned long long)(uintptr_t)psi_dev[k],
+                           (unsigned long long)(uintptr_t)vxpsi_dev[k]});
+  }
+  if (!(b.exec && b.key == key)) {
+    release_batch_graph(o, false);
+    if (!b.origin) KX_HIP(hipStreamCreateWithFlags(&b.origin, hipStreamNonBlocking));
+    if (!b.fork) KX_HIP(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+    while ((int)b.branch.size() < nsys) {
+      hipStream_t s;
+      KX_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      b.branch.push_back(s);
+      hipEvent_t e;
+      KX_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b.join.push_back(e);
+    }
+    // record: fork from the origin stream, one branch per system, join back
+    KX_HIP(hipStreamBeginCapture(b.origin, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipEventRecord(b.fork, b.origin);
+    for (int k = 0; k < nsys && e == hipSuccess; ++k) {
+      e = hipStreamWaitEvent(b.branch[k], b.fork, 0);
+      if (e != hipSuccess) break;
+      grids[k]->capturing = true;
+      e = enqueue_exchange(grids[k], xps[k], b.branch[k]);
+      grids[k]->capturing = false;
+      if (e != hipSuccess) break;
+      e = hipEventRecord(b.join[k], b.branch[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b.origin, b.join[k], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b.origin, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return KX_ERR_DEVICE;
+    }
+    b.graph = graph;
+    if (hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      release_batch_graph(o, false);
+      return KX_ERR_DEVICE;
+    }
+    b.key = key;
+  }
+  KX_HIP(hipGraphLaunch(b.exec, b.origin));
+  KX_HIP(hipStreamSynchronize(b.origin));
+  for (int k = 0; k < nsys; ++k) {
+    grids[k]->last_norb = norbs[k];
+    if (ex_out)
+      KX_HIP(hipMemcpy(&ex_out[k], grids[k]->dEx, sizeof(double), hipMemcpyDeviceToHost));
+  }
   return KX_OK;
 }
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 
 #include "kx_internal.h"
 
@@ -89,7 +90,31 @@ __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ a,
   }
 }
 
+__global__ void __launch_bounds__(256) zero_kernel(unsigned* __restrict__ p, long long words,
+                                                   int vec) {
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nthr = (long long)gridDim.x * blockDim.x;
+  long long done = 0;
+  if (vec) {
+    const long long quads = words / 4;
+    uint4* q = reinterpret_cast<uint4*>(p);
+    for (long long k = tid; k < quads; k += nthr) q[k] = make_uint4(0u, 0u, 0u, 0u);
+    done = quads * 4;
+  }
+  for (long long k = done + tid; k < words; k += nthr) p[k] = 0u;
+}
+
 }  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 4 != 0 || (reinterpret_cast<uintptr_t>(p) % 4) != 0) return hipErrorInvalidValue;
+  const long long words = (long long)(bytes / 4);
+  const int vec = (reinterpret_cast<uintptr_t>(p) % 16) == 0;
+  const long long blocks = std::max<long long>(1, std::min<long long>((words + 1023) / 1024, 8192));
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned*)p, words, vec);
+  return hipGetLastError();
+}
 
 hipError_t launch_narrow(const double* a, float* b, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -144,6 +144,9 @@ hipError_t launch_pencil_s(const Geom& g, const PencilPlan& p, const EigS& e, co
 hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigS& e, const float* T, const Item* items, int nitems,
                             const void* psi, const double* occ, void* dst, hipStream_t s);
+// zero `bytes` (a multiple of 4, 4-byte aligned) with a kernel, so that the
+// clearing can be recorded into a graph
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // b[k] = (float)a[k] and a[k] = b[k] widened, k < n (16-byte aligned arrays)
 hipError_t launch_narrow(const double* a, float* b, long long n, hipStream_t s);
 hipError_t launch_widen(const float* a, double* b, long long n, hipStream_t s);

@@ -27,6 +27,7 @@ EXPORTS = (
     "kx_setup_laplacian", "kx_apply_fL", "kx_apply_exchange", "kx_exchange_energy",
     "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
+    "kx_batch_apply_exchange",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -65,6 +66,9 @@ def lib():
             "kx_fd_weights": [c_int, dp],
             "kx_laplacian_1d": [c_int, c_double, c_int, c_int, dp],
             "kx_pair_schedule": [c_int, c_int, ip, ip, ip, ip],
+            "kx_batch_apply_exchange": [c_int, ctypes.POINTER(vp), ip, dp, ip, c_int,
+                                        ctypes.POINTER(vp), ctypes.POINTER(dp),
+                                        ctypes.POINTER(vp), c_int, dp],
             "kx_profile": [vp, c_int],
             "kx_profile_read": [vp, c_int, dp, ctypes.POINTER(ctypes.c_longlong)],
         }
@@ -118,6 +122,35 @@ def pair_schedule(norb, max_batch=0):
     _check(lib().kx_pair_schedule(norb, max_batch, ctypes.byref(npairs), ctypes.byref(nb),
                                   _iptr(pairs), _iptr(offs)), "kx_pair_schedule")
     return pairs[:npairs.value], offs
+
+
+def batch_apply_exchange(grids, psis, occs, kernels, omegas, prec="fp64", outs=None):
+    """Exchange of several systems through kx_batch_apply_exchange (one
+    recorded graph, replayed while nothing changes).  Returns (vx list, E_x
+    list)."""
+    import numpy as np
+    import torch
+    n = len(grids)
+    if outs is None:
+        outs = [torch.empty_like(p) for p in psis]
+    dts = {p.dtype for p in psis} | {o.dtype for o in outs}
+    if len(dts) != 1 or not all(p.is_cuda and p.is_contiguous() for p in list(psis) + list(outs)):
+        raise ValueError("psis and outs: contiguous device tensors of one dtype")
+    dtype = DTYPE["f64" if psis[0].dtype == torch.float64 else "f32"]
+    occ_arrays = [np.ascontiguousarray(np.asarray(o, dtype=np.float64)) for o in occs]
+    norbs = (ctypes.c_int * n)(*[int(p.shape[0]) for p in psis])
+    ks = (ctypes.c_int * n)(*[KERNEL[k] for k in kernels])
+    oms = (ctypes.c_double * n)(*[float(w) for w in omegas])
+    hs = (ctypes.c_void_p * n)(*[g._h.value for g in grids])
+    ps = (ctypes.c_void_p * n)(*[p.data_ptr() for p in psis])
+    vs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    occ_ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(a) for a in occ_arrays])
+    ex = (ctypes.c_double * n)()
+    for g in grids:
+        g.stream.synchronize()
+    _check(lib().kx_batch_apply_exchange(n, hs, ks, oms, norbs, dtype, ps, occ_ptrs, vs, PREC[prec],
+                                         ex), "kx_batch_apply_exchange")
+    return outs, list(ex)
 
 
 # ---------------------------------------------------------------- device

@@ -6,6 +6,7 @@ names the workloads.  Both sides of every parity comparison read the arrays
 it returns.
 """
 from .orbitals import (  # noqa: F401
+    RAGGED_BATCH,
     WORKLOADS,
     Workload,
     gaussian_orbitals,

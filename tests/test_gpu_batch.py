@@ -1,0 +1,123 @@
+"""Ragged multi-system batches through kx_batch_apply_exchange (one recorded
+HIP graph, one branch per system): against the oracle, against the
+one-system entry point, and across replays with other work in between."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import Workload, make_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+# small systems with different shapes, boundary conditions, kernels and
+# orbital counts (the oracle finishes each in seconds)
+SMALL = [
+    "dirichlet20x27x34_coulomb",
+    "mixed40x36x44_erfc",
+    Workload("periodic24x20x28_erfc", (24, 20, 28), (0.35, 0.3, 0.33), 12,
+             ("periodic",) * 3, "erfc", 0.106, 4, 2.0, 11, 8, True),
+    Workload("slab30x26x18_coulomb", (30, 26, 18), (0.3, 0.3, 0.3), 12,
+             ("periodic", "periodic", "dirichlet"), "coulomb", 0.0, 3, 2.0, 12, 12, False),
+]
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def systems():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_16998_amd import kx
+    out = []
+    for spec in SMALL:
+        w, psi, occ = make_workload(spec)
+        occ = occ * np.linspace(1.0, 0.5, w.norb)  # distinct occupations
+        g = kx.Grid(w.n, w.h, w.order, w.bc)
+        out.append((w, psi, occ, g, torch.from_numpy(psi).cuda()))
+    yield out
+    for s in out:
+        s[3].close()
+
+
+def _batch(systems, prec, outs=None):
+    from paper_2406_16998_amd import kx
+    return kx.batch_apply_exchange([s[3] for s in systems], [s[4] for s in systems],
+                                   [s[2] for s in systems], [s[0].kernel for s in systems],
+                                   [s[0].omega for s in systems], prec=prec, outs=outs)
+
+
+def test_batch_matches_oracle_fp64(systems):
+    print("batch fp64 vs oracle", flush=True)
+    vxs, exs = _batch(systems, "fp64")
+    for (w, psi, occ, g, _), vx, ex in zip(systems, vxs, exs):
+        grid = orc.make_grid(w.n, w.h, w.order, w.bc)
+        vx_ref, ex_ref = orc.exchange(psi, occ, grid, w.kernel, w.omega)
+        assert abs(ex - ex_ref) <= TOL64 * abs(ex_ref), w.name
+        assert abs(g.exchange_energy() - ex) == 0.0
+        vx = vx.cpu().numpy()
+        for j in range(w.norb):
+            assert _rel(vx[j], vx_ref[j]) <= TOL64, (w.name, j)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_batch_replays_match_single_system_calls(systems, prec):
+    """Three replays of the recorded graph, each after eager single-system work
+    that reuses the same handles, must equal the eager results bitwise."""
+    import torch
+    print(f"batch replays {prec}", flush=True)
+    eager = []
+    for w, psi, occ, g, psi_d in systems:
+        vx = g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec=prec)
+        eager.append((vx.clone(), g.exchange_energy()))
+    outs = [torch.empty_like(s[4]) for s in systems]
+    for rep in range(3):
+        for k, s in enumerate(systems):  # other work on the same handles in between
+            if (rep + k) % 2 == 0:
+                s[3].apply_exchange(s[4], s[2], s[0].kernel, s[0].omega,
+                                    prec="fp32" if prec == "fp64" else "fp64")
+        torch.cuda.synchronize()
+        for o in outs:
+            o.fill_(float("nan"))
+        vxs, exs = _batch(systems, prec, outs=outs)
+        for (vx_e, ex_e), vx, ex in zip(eager, vxs, exs):
+            assert ex == ex_e, rep
+            assert torch.equal(vx, vx_e), rep
+
+
+def test_batch_rejects_bad_arguments(systems):
+    from paper_2406_16998_amd import kx
+    s = systems[0]
+    with pytest.raises(kx.KxError) as e:
+        kx.batch_apply_exchange([s[3], s[3]], [s[4], s[4]], [s[2], s[2]], [s[0].kernel] * 2,
+                                [s[0].omega] * 2)
+    assert e.value.status == 1
+    L = kx.lib()
+    assert L.kx_batch_apply_exchange(0, None, None, None, None, 0, None, None, None, 0, None) == 1
+
+
+@pytest.mark.slow
+def test_ragged_six_systems_bf16_against_fp64():
+    """The six-system ragged workload (48^3 .. 120x120x60, 16 .. 128 orbitals):
+    split-BF16 batch against the FP64 batch (E_x per system, Vx psi of the
+    first and last orbital)."""
+    import torch
+    from paper_2406_16998_amd import kx
+    from synth import RAGGED_BATCH
+    sys_ = []
+    for name in RAGGED_BATCH:
+        print(f"generating {name}", flush=True)
+        w, psi, occ = make_workload(name)
+        sys_.append((w, psi, occ, kx.Grid(w.n, w.h, w.order, w.bc), torch.from_numpy(psi).cuda()))
+    vx64, ex64 = _batch(sys_, "fp64")
+    vx16, ex16 = _batch(sys_, "bf16x3")
+    for (w, *_), a, b, ea, eb in zip(sys_, vx64, vx16, ex64, ex16):
+        print(f"{w.name}: E_x fp64={ea!r} bf16x3={eb!r}", flush=True)
+        assert abs(ea - eb) <= 1e-6 * abs(ea), w.name
+        for j in (0, w.norb - 1):
+            assert _rel(b[j].cpu().numpy(), a[j].cpu().numpy()) <= 1e-5, (w.name, j)
+    for s in sys_:
+        s[3].close()
