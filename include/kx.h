@@ -138,6 +138,27 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
                                   const void* const* psi_dev, const double* const* occ_host,
                                   void* const* vxpsi_dev, int prec, double* ex_out);
 
+/* Autotuner: time every launch shape the transform kernels accept for this
+ * grid (workgroup z-slabs, staging chunk rows, V blocks in LDS or not,
+ * parity split, pencil waves) for precision prec on storage dtype, on
+ * synthetic data in batches of `items` pairs (<= 0: the handle's batch size),
+ * and keep the fastest per pass for later calls on this handle.
+ *   verify      non-zero: also check that every shape gives bitwise the same
+ *               intermediate and Vx psi as the current one (KX_ERR_NUMERIC
+ *               otherwise; the plan is then left unchanged); no cache use
+ *   cache_path  NULL, or a text file: a line for this grid shape, precision
+ *               and device is read instead of timing (accepted only if the
+ *               shape is one this build proposes); a new result is appended
+ * Allocates temporary device buffers (2*items orbitals in and out) and
+ * synchronises the stream. */
+kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
+                      const char* cache_path);
+
+/* The launch shapes in use for prec (a test and reporting hook):
+ * fwd_out[6] = {parity split, z-slabs, waves, chunk rows, V in LDS, LDS bytes},
+ * pen_out[2] = {waves, LDS bytes}, inv_out[6] like fwd_out (parity split 1). */
+kx_status kx_get_plan(kx_grid* g, int prec, int* fwd_out, int* pen_out, int* inv_out);
+
 /* E_x of the last kx_apply_exchange on this handle.  Synchronises the stream.
  * KX_ERR_STATE if there was none. */
 kx_status kx_exchange_energy(kx_grid* g, double* ex_out);

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -1089,6 +1090,285 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
     if (ex_out)
       KX_HIP(hipMemcpy(&ex_out[k], grids[k]->dEx, sizeof(double), hipMemcpyDeviceToHost));
   }
+  return KX_OK;
+}
+
+kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
+                      const char* cache_path) {
+  if (!g || dtype < KX_F64 || dtype > KX_F32) return KX_ERR_INVALID_ARG;
+  if (prec != KX_PREC_FP64 && prec != KX_PREC_FP32 && prec != KX_PREC_BF16X3)
+    return prec == KX_PREC_FP16X3 ? KX_ERR_UNSUPPORTED : KX_ERR_INVALID_ARG;
+  const Geom& G = g->geom;
+  // the storage the transform kernels see (reduced precision on FP64 storage
+  // runs on FP32 working copies)
+  const int dtype_w = (prec != KX_PREC_FP64 && dtype == KX_F64) ? KX_F32 : dtype;
+  const int kind = prec == KX_PREC_FP64 ? 0 : (prec == KX_PREC_FP32 ? 1 : 2);
+  Plan& plan = kind == 0 ? g->plan_d : (kind == 1 ? g->plan_f : g->plan_s);
+  int dev = 0, lds = 64 * 1024;
+  hipDeviceProp_t prop;
+  KX_HIP(hipGetDevice(&dev));
+  KX_HIP(hipGetDeviceProperties(&prop, dev));
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    lds = 64 * 1024;
+  }
+  char key[256];
+  std::snprintf(key, sizeof key, "kx-tune-v1 %d %d %d %d %d %d %d %d %s %d", G.n1, G.n2, G.n3,
+                g->bc[0], g->bc[1], g->bc[2], kind, dtype_w, prop.gcnArchName,
+                prop.multiProcessorCount);
+  // cached result: "<key> | fwd qsplit slabs waves kc vlds lds | pen waves lds | inv slabs waves kc vlds lds"
+  if (cache_path && !verify) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[512];
+      bool found = false;
+      while (std::fgets(line, sizeof line, f)) {
+        const size_t kl = std::strlen(key);
+        if (std::strncmp(line, key, kl) != 0 || line[kl] != ' ') continue;
+        SlabPlan fw, iv;
+        PencilPlan pn;
+        int fv = 0, ivv = 0;
+        unsigned long long fl = 0, pl = 0, il = 0;
+        if (std::sscanf(line + kl, " | fwd %d %d %d %d %d %llu | pen %d %llu | inv %d %d %d %d %llu",
+                        &fw.qsplit, &fw.slabs, &fw.waves, &fw.kc, &fv, &fl, &pn.waves, &pl,
+                        &iv.slabs, &iv.waves, &iv.kc, &ivv, &il) == 13) {
+          fw.vlds = fv != 0;
+          fw.lds_bytes = fl;
+          pn.lds_bytes = pl;
+          iv.vlds = ivv != 0;
+          iv.lds_bytes = il;
+          // accept only a shape this build would itself propose
+          std::vector<SlabPlan> cf, ci;
+          std::vector<PencilPlan> cp;
+          plan_candidates(G, (size_t)lds, kind, cf, cp, ci);
+          auto same = [](const SlabPlan& a, const SlabPlan& b) {
+            return a.qsplit == b.qsplit && a.slabs == b.slabs && a.waves == b.waves &&
+                   a.kc == b.kc && a.vlds == b.vlds && a.lds_bytes == b.lds_bytes;
+          };
+          bool okf = false, okp = false, oki = false;
+          for (auto& c : cf) okf = okf || same(c, fw);
+          for (auto& c : ci) oki = oki || same(c, iv);
+          for (auto& c : cp) okp = okp || (c.waves == pn.waves && c.lds_bytes == pn.lds_bytes);
+          if (okf && okp && oki) {
+            plan.fwd = fw;
+            plan.pen = pn;
+            plan.inv = iv;
+            ++g->gen;
+            found = true;
+          }
+        }
+      }
+      std::fclose(f);
+      if (found) return KX_OK;
+    }
+  }
+
+  const int nb = std::max(1, std::min(items > 0 ? items : g->max_slots, g->max_slots));
+  const int norb_t = 2 * nb;
+  const size_t esw = elem_size(dtype_w);
+  const size_t fbytes = esw * (size_t)norb_t * G.N;
+  const size_t tbytes = (kind == 0 ? sizeof(double) : sizeof(float)) * (size_t)nb * G.slot;
+  kx_status st = ensure_workspace(g, nb);
+  if (st != KX_OK) return st;
+  st = ensure_ftable(g, KX_KERNEL_ERFC, 0.106);
+  if (st != KX_OK) return st;
+  std::vector<Item> its(nb);
+  for (int k = 0; k < nb; ++k) its[k] = {2 * k, 2 * k + 1};
+  st = upload_items(g, 3, nb, nb, its);
+  if (st != KX_OK) return st;
+  void *psi = nullptr, *vx = nullptr, *tsave = nullptr, *ref = nullptr;
+  double* occ = nullptr;
+  unsigned long long* cnt = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(g->stream);
+    dev_free(psi);
+    dev_free(vx);
+    dev_free(tsave);
+    dev_free(ref);
+    dev_free(occ);
+    dev_free(cnt);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (dev_alloc(&psi, fbytes) != KX_OK || dev_alloc(&vx, fbytes) != KX_OK ||
+      dev_alloc(&tsave, tbytes) != KX_OK || dev_alloc(&ref, std::max(tbytes, fbytes)) != KX_OK ||
+      dev_alloc((void**)&occ, sizeof(double) * norb_t) != KX_OK ||
+      dev_alloc((void**)&cnt, sizeof(unsigned long long)) != KX_OK) {
+    release();
+    return KX_ERR_OUT_OF_MEMORY;
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return KX_ERR_DEVICE;
+  }
+  hipStream_t s = g->stream;
+  const std::vector<double> ones(norb_t, 1.0);
+  hipError_t he = hipMemcpy(occ, ones.data(), sizeof(double) * norb_t, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = launch_pattern(psi, (long long)norb_t * G.N, dtype_w == KX_F64, s);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return KX_ERR_DEVICE;
+  }
+  const Item* dit = g->dItems;
+  auto fwd = [&](const SlabPlan& p) -> hipError_t {
+    if (kind == 0)
+      return launch_forward_d(dtype_w, 1, G, p, eig_of(g), psi, dit, nb, (double*)g->dT, s);
+    if (kind == 1)
+      return launch_forward_f(dtype_w, 1, G, p, eigf_of(g), psi, dit, nb, (float*)g->dT, s);
+    return launch_forward_s(dtype_w, 1, G, p, eigs_of(g), psi, dit, nb, (float*)g->dT, s);
+  };
+  auto pen = [&](const PencilPlan& p) -> hipError_t {
+    if (kind == 0)
+      return launch_pencil_d(G, p, eig_of(g), g->dF, nb, (double*)g->dT, g->dEpart, s);
+    if (kind == 1)
+      return launch_pencil_f(G, p, eigf_of(g), g->dF, nb, (float*)g->dT, g->dEpart, s);
+    return launch_pencil_s(G, p, eigs_of(g), g->dF, nb, (float*)g->dT, g->dEpart, s);
+  };
+  auto inv = [&](const SlabPlan& p) -> hipError_t {
+    if (kind == 0)
+      return launch_inverse_d(dtype_w, 1, G, p, eig_of(g), (const double*)g->dT, dit, nb, psi, occ,
+                              vx, s);
+    if (kind == 1)
+      return launch_inverse_f(dtype_w, 1, G, p, eigf_of(g), (const float*)g->dT, dit, nb, psi,
+                              occ, vx, s);
+    return launch_inverse_s(dtype_w, 1, G, p, eigs_of(g), (const float*)g->dT, dit, nb, psi, occ,
+                            vx, s);
+  };
+  // mean time of three launches after one warm-up
+  auto timeit = [&](auto&& launch, auto&& reset, float& ms) -> hipError_t {
+    hipError_t e = reset();
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = reset();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    ms /= 3.0f;
+    return e;
+  };
+  // bitwise agreement of buf with the reference copy
+  auto same_as_ref = [&](const void* buf, size_t bytes, bool& same) -> hipError_t {
+    unsigned long long c = 0;
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof c, s);
+    if (e == hipSuccess) e = launch_diff(buf, ref, bytes, cnt, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&c, cnt, sizeof c, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    same = c == 0;
+    return e;
+  };
+  auto none = [&]() -> hipError_t { return hipSuccess; };
+  auto fail_dev = [&]() {
+    (void)hipGetLastError();
+    release();
+    return KX_ERR_DEVICE;
+  };
+
+  std::vector<SlabPlan> cf, ci;
+  std::vector<PencilPlan> cp;
+  plan_candidates(G, (size_t)lds, kind, cf, cp, ci);
+  if (cf.empty() || cp.empty() || ci.empty()) {
+    release();
+    return KX_ERR_UNSUPPORTED;
+  }
+  bool all_same = true;
+  // forward: reference with the current shape, then every candidate
+  if (fwd(plan.fwd) != hipSuccess ||
+      hipMemcpyAsync(ref, g->dT, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail_dev();
+  float best = 1e30f;
+  SlabPlan bf = plan.fwd;
+  for (const SlabPlan& c : cf) {
+    float ms = 0;
+    if (timeit([&] { return fwd(c); }, none, ms) != hipSuccess) return fail_dev();
+    if (verify) {
+      bool same = false;
+      if (same_as_ref(g->dT, tbytes, same) != hipSuccess) return fail_dev();
+      all_same = all_same && same;
+    }
+    if (ms < best) {
+      best = ms;
+      bf = c;
+    }
+  }
+  // pencil: each run starts from the forward output
+  if (fwd(bf) != hipSuccess ||
+      hipMemcpyAsync(tsave, g->dT, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      pen(plan.pen) != hipSuccess ||
+      hipMemcpyAsync(ref, g->dT, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail_dev();
+  auto restore_t = [&]() { return hipMemcpyAsync(g->dT, tsave, tbytes, hipMemcpyDeviceToDevice, s); };
+  best = 1e30f;
+  PencilPlan bp = plan.pen;
+  for (const PencilPlan& c : cp) {
+    float ms = 0;
+    if (timeit([&] { return pen(c); }, restore_t, ms) != hipSuccess) return fail_dev();
+    if (verify) {
+      bool same = false;
+      if (restore_t() != hipSuccess || pen(c) != hipSuccess ||
+          same_as_ref(g->dT, tbytes, same) != hipSuccess)
+        return fail_dev();
+      all_same = all_same && same;
+    }
+    if (ms < best) {
+      best = ms;
+      bp = c;
+    }
+  }
+  // inverse: from the pencil output, into a cleared Vx psi
+  if (restore_t() != hipSuccess || pen(bp) != hipSuccess) return fail_dev();
+  auto clear_vx = [&]() { return launch_zero(vx, fbytes, s); };
+  if (clear_vx() != hipSuccess || inv(plan.inv) != hipSuccess ||
+      hipMemcpyAsync(ref, vx, fbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail_dev();
+  best = 1e30f;
+  SlabPlan bi = plan.inv;
+  for (const SlabPlan& c : ci) {
+    float ms = 0;
+    if (timeit([&] { return inv(c); }, clear_vx, ms) != hipSuccess) return fail_dev();
+    if (verify) {
+      bool same = false;
+      if (clear_vx() != hipSuccess || inv(c) != hipSuccess ||
+          same_as_ref(vx, fbytes, same) != hipSuccess)
+        return fail_dev();
+      all_same = all_same && same;
+    }
+    if (ms < best) {
+      best = ms;
+      bi = c;
+    }
+  }
+  release();
+  if (!all_same) return KX_ERR_NUMERIC;
+  plan.fwd = bf;
+  plan.pen = bp;
+  plan.inv = bi;
+  ++g->gen;  // recorded graphs carry the old launch shapes
+  if (cache_path && !verify) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s | fwd %d %d %d %d %d %llu | pen %d %llu | inv %d %d %d %d %llu\n", key,
+                   bf.qsplit, bf.slabs, bf.waves, bf.kc, bf.vlds ? 1 : 0,
+                   (unsigned long long)bf.lds_bytes, bp.waves, (unsigned long long)bp.lds_bytes,
+                   bi.slabs, bi.waves, bi.kc, bi.vlds ? 1 : 0, (unsigned long long)bi.lds_bytes);
+      std::fclose(f);
+    }
+  }
+  return KX_OK;
+}
+
+kx_status kx_get_plan(kx_grid* g, int prec, int* fwd_out, int* pen_out, int* inv_out) {
+  if (!g || !fwd_out || !pen_out || !inv_out) return KX_ERR_INVALID_ARG;
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_BF16X3) return KX_ERR_INVALID_ARG;
+  const Plan& p = prec == KX_PREC_FP64 ? g->plan_d : (prec == KX_PREC_FP32 ? g->plan_f : g->plan_s);
+  const int f[6] = {p.fwd.qsplit, p.fwd.slabs, p.fwd.waves, p.fwd.kc, p.fwd.vlds ? 1 : 0,
+                    (int)p.fwd.lds_bytes};
+  const int q[2] = {p.pen.waves, (int)p.pen.lds_bytes};
+  const int v[6] = {1, p.inv.slabs, p.inv.waves, p.inv.kc, p.inv.vlds ? 1 : 0,
+                    (int)p.inv.lds_bytes};
+  std::copy(f, f + 6, fwd_out);
+  std::copy(q, q + 2, pen_out);
+  std::copy(v, v + 6, inv_out);
   return KX_OK;
 }
 

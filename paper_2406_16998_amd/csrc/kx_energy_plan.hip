@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <vector>
 
 #include "kx_internal.h"
 
@@ -104,7 +105,53 @@ __global__ void __launch_bounds__(256) zero_kernel(unsigned* __restrict__ p, lon
   for (long long k = done + tid; k < words; k += nthr) p[k] = 0u;
 }
 
+// deterministic values in [-1, 1) from the element index (tuning inputs)
+__global__ void __launch_bounds__(256) pattern_kernel(void* __restrict__ p, long long n, int dbl) {
+  const long long nthr = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += nthr) {
+    unsigned long long x = (unsigned long long)k * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    x ^= x >> 29;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 32;
+    const double v = (double)(x >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    if (dbl)
+      static_cast<double*>(p)[k] = v;
+    else
+      static_cast<float*>(p)[k] = (float)v;
+  }
+}
+
+// number of 32-bit words that differ between a and b
+__global__ void __launch_bounds__(256) diff_kernel(const unsigned* __restrict__ a,
+                                                   const unsigned* __restrict__ b, long long words,
+                                                   unsigned long long* __restrict__ count) {
+  const long long nthr = (long long)gridDim.x * blockDim.x;
+  unsigned long long c = 0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += nthr)
+    c += a[k] != b[k];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 }  // namespace
+
+hipError_t launch_pattern(void* p, long long n, bool dbl, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192));
+  hipLaunchKernelGGL(pattern_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, dbl ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_diff(const void* a, const void* b, size_t bytes, unsigned long long* count,
+                       hipStream_t s) {
+  if (bytes % 4 != 0) return hipErrorInvalidValue;
+  const long long words = (long long)(bytes / 4);
+  if (words == 0) return hipSuccess;
+  const long long blocks = std::max<long long>(1, std::min<long long>((words + 255) / 256, 8192));
+  hipLaunchKernelGGL(diff_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const unsigned*)a,
+                     (const unsigned*)b, words, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
@@ -202,6 +249,87 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     p.lds_bytes = vb <= max_lds ? vb : 0;
   }
   return pl;
+}
+
+// ---------------------------------------------------------------- tuning
+// Every launch shape the transform kernels accept for this grid (kind 0:
+// double operands, 1: float operands, 2: split-BF16), each within the
+// kernels' launch bounds, register staging budgets and the LDS size.
+void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPlan>& fwd,
+                     std::vector<PencilPlan>& pen, std::vector<SlabPlan>& inv) {
+  fwd.clear();
+  pen.clear();
+  inv.clear();
+  const size_t esize = kind == 0 ? sizeof(double) : sizeof(float);
+  const bool split = kind == 2;
+  const int ntx = g.pe1 / kTile, nty = g.pe2 / kTile, ntz = g.pe3 / kTile;
+  {
+    const int maxw = fwd_mt(ntx) / 64;
+    for (int qsplit : {1, 2}) {
+      const int wps = (qsplit == 1 ? 2 : 1) * (g.p2 / kTile);
+      if (wps > maxw) continue;
+      const int wrow = qsplit == 1 ? g.p1 : g.pe1;
+      const size_t vb =
+          (size_t)(qsplit == 1 ? g.pe1 * g.pe1 + g.po1 * g.po1 : g.pe1 * g.pe1) * esize;
+      for (int slabs : {1, 2, 4, 8}) {
+        if (slabs * wps > maxw) continue;
+        for (int kc : {4, 8, 16, 32}) {
+          if (split && kc != 16) continue;
+          if (!split && (size_t)kc * g.pe1 > (size_t)kFwdPos * wps * 64) continue;
+          for (int vl : {0, 1}) {
+            if (split && vl) continue;
+            const size_t lds = (size_t)slabs * 2 * 2 * kc * wrow * esize + (vl ? vb : 0);
+            if (lds > max_lds) continue;
+            SlabPlan p;
+            p.qsplit = qsplit;
+            p.slabs = slabs;
+            p.waves = slabs * wps;
+            p.kc = kc;
+            p.vlds = vl != 0;
+            p.lds_bytes = lds;
+            fwd.push_back(p);
+          }
+        }
+      }
+    }
+  }
+  {
+    const int maxw = pen_mt(ntz) / 64;
+    const size_t vb = (size_t)(g.pe3 * (g.pe3 + 1) + g.po3 * (g.po3 + 1)) * esize;
+    for (int w : {2, 4, 8, 16}) {
+      if (w > maxw) continue;
+      for (int vl : {0, 1}) {
+        if ((split && vl) || (vl && vb > max_lds)) continue;
+        PencilPlan p;
+        p.waves = w;
+        p.lds_bytes = vl ? vb : 0;
+        pen.push_back(p);
+      }
+    }
+  }
+  {
+    const int maxw = inv_mt(nty) / 64;
+    const int wps = g.pe1 / kTile;
+    const size_t vb = (size_t)(g.pe2 * g.pe2 + g.po2 * g.po2) * esize;
+    for (int slabs = 1; slabs * wps <= maxw; ++slabs) {
+      for (int kc : {4, 8, 16}) {
+        if (split && kc != 16) continue;
+        if (!split && (size_t)2 * kc * g.p2 > (size_t)kInvEl * wps * 64) continue;
+        for (int vl : {0, 1}) {
+          if (split && vl) continue;
+          const size_t lds = (size_t)slabs * 2 * 2 * kc * g.p2 * esize + (vl ? vb : 0);
+          if (lds > max_lds) continue;
+          SlabPlan p;
+          p.slabs = slabs;
+          p.waves = slabs * wps;
+          p.kc = kc;
+          p.vlds = vl != 0;
+          p.lds_bytes = lds;
+          inv.push_back(p);
+        }
+      }
+    }
+  }
 }
 
 hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* items, int nitems,

@@ -101,6 +101,9 @@ struct Plan {
 };
 // esize: bytes per element of the mode-product operands (8 or 4)
 Plan make_plan(const Geom& g, size_t max_lds, size_t esize);
+// every valid launch shape (kind 0: double operands, 1: float, 2: split-BF16)
+void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPlan>& fwd,
+                     std::vector<PencilPlan>& pen, std::vector<SlabPlan>& inv);
 
 // ---- set-up kernels (kx_setup.hip) ----
 // Jacobi eigensolver of the symmetric n x n matrix A (global memory); writes
@@ -147,6 +150,10 @@ hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan
 // zero `bytes` (a multiple of 4, 4-byte aligned) with a kernel, so that the
 // clearing can be recorded into a graph
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// tuning helpers: index-hash values in [-1, 1); count of differing words
+hipError_t launch_pattern(void* p, long long n, bool dbl, hipStream_t s);
+hipError_t launch_diff(const void* a, const void* b, size_t bytes, unsigned long long* count,
+                       hipStream_t s);
 // b[k] = (float)a[k] and a[k] = b[k] widened, k < n (16-byte aligned arrays)
 hipError_t launch_narrow(const double* a, float* b, long long n, hipStream_t s);
 hipError_t launch_widen(const float* a, double* b, long long n, hipStream_t s);

@@ -27,7 +27,7 @@ EXPORTS = (
     "kx_setup_laplacian", "kx_apply_fL", "kx_apply_exchange", "kx_exchange_energy",
     "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
-    "kx_batch_apply_exchange",
+    "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -66,6 +66,8 @@ def lib():
             "kx_fd_weights": [c_int, dp],
             "kx_laplacian_1d": [c_int, c_double, c_int, c_int, dp],
             "kx_pair_schedule": [c_int, c_int, ip, ip, ip, ip],
+            "kx_autotune": [vp, c_int, c_int, c_int, c_int, ctypes.c_char_p],
+            "kx_get_plan": [vp, c_int, ip, ip, ip],
             "kx_batch_apply_exchange": [c_int, ctypes.POINTER(vp), ip, dp, ip, c_int,
                                         ctypes.POINTER(vp), ctypes.POINTER(dp),
                                         ctypes.POINTER(vp), c_int, dp],
@@ -226,6 +228,19 @@ class Grid:
         e = np.zeros(len(p))
         _check(lib().kx_pair_energies(self._h, len(p), _iptr(p), _dptr(e)), "kx_pair_energies")
         return e
+
+    def autotune(self, prec="fp64", dtype="f64", items=0, verify=False, cache_path=None):
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().kx_autotune(self._h, PREC[prec], DTYPE[dtype], int(items), 1 if verify else 0,
+                                 path), "kx_autotune")
+
+    def plan(self, prec="fp64"):
+        """Launch shapes in use: dicts for the forward, pencil and inverse passes."""
+        f, p, v = (ctypes.c_int * 6)(), (ctypes.c_int * 2)(), (ctypes.c_int * 6)()
+        _check(lib().kx_get_plan(self._h, PREC[prec], f, p, v), "kx_get_plan")
+        keys = ("qsplit", "slabs", "waves", "kc", "vlds", "lds_bytes")
+        return (dict(zip(keys, list(f))), {"waves": p[0], "lds_bytes": p[1]},
+                dict(zip(keys, list(v))))
 
     def profile(self, enable=True):
         _check(lib().kx_profile(self._h, 1 if enable else 0), "kx_profile")
