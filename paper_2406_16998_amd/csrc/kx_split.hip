@@ -21,6 +21,11 @@
 
 #include "kx_internal.h"
 
+// The FP32 staging and update arithmetic below must round the same way in
+// every launch shape (results are reproducible bit for bit across plans):
+// no contraction of products and sums into fused operations.
+#pragma clang fp contract(off)
+
 namespace kx {
 namespace {
 
@@ -159,8 +164,7 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
   // (n2-1-y, x), (n2-1-y, n1-1-x) of the pair product
   // raw loads stay in storage precision until the stash step, so the
   // prefetch does not wait on them
-  auto load_pos = [&](int pos, int y0, S* va, S* vb) {
-    const int yy = pos / g.pe1, xp = pos - yy * g.pe1;
+  auto load_pos = [&](int pos, int yy, int xp, int y0, S* va, S* vb) {
     const int y = y0 + yy, ym = g.n2 - 1 - y, xm = g.n1 - 1 - xp;
     const bool in = zin && pos < npos && y < g.me2 && xp < g.me1;
     const bool hx = in && xp < g.mo1, hy = in && y < g.mo2;
@@ -172,41 +176,50 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
       if (MODE == 1) vb[m] = ok[m] ? s1[o[m]] : S(0);
     }
   };
-  auto store_pos = [&](float* buf, int pos, int ybase, const S* va, const S* vb) {
-    const int yy = pos / g.pe1, xp = pos - yy * g.pe1;
-    double v[4];
+  // FP32 arithmetic: the operands are split from FP32 values anyway
+  auto store_pos = [&](float* buf, int yy, int xp, int ybase, const S* va, const S* vb) {
+    float v[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = (MODE == 1) ? (double)va[m] * (double)vb[m] : (double)va[m];
-    const double sx0 = v[0] + v[1], dx0 = v[0] - v[1];
-    const double sx1 = v[2] + v[3], dx1 = v[2] - v[3];
+    for (int m = 0; m < 4; ++m) v[m] = (MODE == 1) ? (float)va[m] * (float)vb[m] : (float)va[m];
+    const float sx0 = v[0] + v[1], dx0 = v[0] - v[1];
+    const float sx1 = v[2] + v[3], dx1 = v[2] - v[3];
     const int y = yy + ybase;
     const bool xo = xp < g.mo1, yo = y < g.mo2;
     for (int qq = q_lo; qq < q_hi; ++qq) {
       const int wq = qq == 0 ? g.pe1 : g.po1;
       if (xp >= wq) continue;
       const bool live = qq == 0 || xo;
-      const double ve = !live ? 0.0 : (qq == 0 ? sx0 + sx1 : dx0 + dx1);
-      const double vo = !(live && yo) ? 0.0 : (qq == 0 ? sx0 - sx1 : dx0 - dx1);
-      buf[(0 * kc + yy) * wrow + qcol(qq) + xp] = (float)ve;
-      buf[(1 * kc + yy) * wrow + qcol(qq) + xp] = (float)vo;
+      const float ve = !live ? 0.f : (qq == 0 ? sx0 + sx1 : dx0 + dx1);
+      const float vo = !(live && yo) ? 0.f : (qq == 0 ? sx0 - sx1 : dx0 - dx1);
+      buf[(0 * kc + yy) * wrow + qcol(qq) + xp] = ve;
+      buf[(1 * kc + yy) * wrow + qcol(qq) + xp] = vo;
     }
   };
+  // this thread's staged positions are the same in every chunk
+  int pyy[kFwdPos], pxp[kFwdPos];
+#pragma unroll
+  for (int k = 0; k < kFwdPos; ++k) {
+    const int pos = stid + k * sthreads;
+    pyy[k] = pos / g.pe1;
+    pxp[k] = pos - pyy[k] * g.pe1;
+  }
   S ra[kFwdPos][4], rb[kFwdPos][4];
   auto fetch = [&](int y0) {
 #pragma unroll
-    for (int k = 0; k < kFwdPos; ++k) load_pos(stid + k * sthreads, y0, ra[k], rb[k]);
+    for (int k = 0; k < kFwdPos; ++k) load_pos(stid + k * sthreads, pyy[k], pxp[k], y0, ra[k], rb[k]);
   };
   auto stash = [&](float* buf, int y0) {
 #pragma unroll
     for (int k = 0; k < kFwdPos; ++k) {
       const int pos = stid + k * sthreads;
-      if (pos < npos) store_pos(buf, pos, y0, ra[k], rb[k]);
+      if (pos < npos) store_pos(buf, pyy[k], pxp[k], y0, ra[k], rb[k]);
     }
     if (XST) {
       for (int pos = stid + kFwdPos * sthreads; pos < npos; pos += sthreads) {
         S va[4], vb[4];
-        load_pos(pos, y0, va, vb);
-        store_pos(buf, pos, y0, va, vb);
+        const int yy = pos / g.pe1, xp = pos - yy * g.pe1;
+        load_pos(pos, yy, xp, y0, va, vb);
+        store_pos(buf, yy, xp, y0, va, vb);
       }
     }
   };
@@ -509,8 +522,8 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
   S* __restrict__ vj = dst + (long long)(MODE == 1 ? item.j : item.i) * g.N + zoff;
   S* __restrict__ vi = dst + (long long)item.i * g.N + zoff;
   const bool offdiag = MODE == 1 && item.i != item.j;
-  const double oi = MODE == 1 ? occ[item.i] : 0.0;
-  const double oj = MODE == 1 ? occ[item.j] : 0.0;
+  const float oi = MODE == 1 ? (float)occ[item.i] : 0.f;
+  const float oj = MODE == 1 ? (float)occ[item.j] : 0.f;
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     f4 Q[4];
@@ -523,12 +536,12 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
     for (int r = 0; r < 4; ++r) {
       const int yp = kTile * u + 4 * lg + r;
       if (yp >= g.me2) continue;
-      const double ee = Q[0][r], eo = has_o ? Q[1][r] : 0.0;
-      const double oe = u < NTO ? Q[2][r] : 0.0, oo = (has_o && u < NTO) ? Q[3][r] : 0.0;
+      const float ee = Q[0][r], eo = has_o ? Q[1][r] : 0.f;
+      const float oe = u < NTO ? Q[2][r] : 0.f, oo = (has_o && u < NTO) ? Q[3][r] : 0.f;
       const int ym = g.n2 - 1 - yp;
       const bool hx = xp < g.mo1, hy = yp < g.mo2;
-      const double ph[4] = {ee + eo + oe + oo, ee - eo + oe - oo, ee + eo - oe - oo,
-                            ee - eo - oe + oo};
+      const float ph[4] = {ee + eo + oe + oo, ee - eo + oe - oo, ee + eo - oe - oo,
+                           ee - eo - oe + oo};
       const unsigned o[4] = {(unsigned)(yp * g.n1 + xp), (unsigned)(yp * g.n1 + xm),
                              (unsigned)(ym * g.n1 + xp), (unsigned)(ym * g.n1 + xm)};
       const bool ok[4] = {true, hx, hy, hx && hy};
@@ -538,8 +551,9 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
         if (MODE == 0) {
           vj[o[m]] = (S)ph[m];
         } else {
-          vj[o[m]] = (S)((double)vj[o[m]] - (oi * ph[m]) * (double)pi[o[m]]);
-          if (offdiag) vi[o[m]] = (S)((double)vi[o[m]] - (oj * ph[m]) * (double)pj[o[m]]);
+          // FP32 update (Vx psi is accumulated in FP32 on this path)
+          vj[o[m]] = (S)((float)vj[o[m]] - (oi * ph[m]) * (float)pi[o[m]]);
+          if (offdiag) vi[o[m]] = (S)((float)vi[o[m]] - (oj * ph[m]) * (float)pj[o[m]]);
         }
       }
     }
