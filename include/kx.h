@@ -61,7 +61,10 @@ typedef enum {
   KX_PREC_FP64 = 0,    /* FP64 MFMA                                          */
   KX_PREC_FP32 = 1,    /* FP32 MFMA, FP32 intermediates                      */
   KX_PREC_BF16X3 = 2,  /* three-term BF16 split of both operands, FP32 accumulate */
-  KX_PREC_FP16X3 = 3   /* three-term FP16 split, FP32 accumulate             */
+  KX_PREC_FP16X3 = 3,  /* three-term FP16 split, FP32 accumulate             */
+  KX_PREC_MIXED = 4    /* FP64 forward transform, f scaling and energies (E_x
+                        * as in FP64); the potential's back-transform and the
+                        * Vx psi update in split BF16 with FP32 intermediates */
 } kx_prec;
 /* Storage type of psi / rho / phi / vxpsi. */
 typedef enum { KX_F64 = 0, KX_F32 = 1 } kx_dtype;
@@ -88,8 +91,9 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
  *   kernel, omega  see above; omega > 0 required for KX_KERNEL_ERFC
  *   batch          number of fields, >= 0 (0 is a no-op)
  *   dtype          storage of rho / phi: KX_F64 or KX_F32
- *   prec           arithmetic of the mode products: KX_PREC_FP64, KX_PREC_FP32
- *                  or KX_PREC_BF16X3 (KX_PREC_FP16X3: KX_ERR_UNSUPPORTED).
+ *   prec           arithmetic of the mode products: KX_PREC_FP64, KX_PREC_FP32,
+ *                  KX_PREC_BF16X3 or KX_PREC_MIXED (KX_PREC_FP16X3:
+ *                  KX_ERR_UNSUPPORTED).
  *                  FP64 and FP32 also return KX_ERR_UNSUPPORTED on grids whose
  *                  y extent exceeds about four times the x extent (staging
  *                  limit of their inverse pass); BF16X3 has no shape limit.
@@ -104,10 +108,12 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
  * updates orbital j and, if i != j, orbital i.  occ_host[norb] are the
  * spin-summed occupations used as literal weights (a closed shell with
  * occ = 2 gives twice the per-spin operator of Eq. (3)).
- *   dtype, prec  as for kx_apply_fL.  With KX_PREC_FP32 or KX_PREC_BF16X3 on
- *              KX_F64 storage the orbitals are rounded to FP32 once and
- *              Vx psi is accumulated in FP32 before it is widened into
- *              vxpsi_dev (the handle keeps 8*norb*N bytes of FP32 copies).
+ *   dtype, prec  as for kx_apply_fL.  With KX_PREC_FP32, KX_PREC_BF16X3 or
+ *              KX_PREC_MIXED on KX_F64 storage the orbitals are rounded to
+ *              FP32 once for the inverse pass and Vx psi is accumulated in
+ *              FP32 before it is widened into vxpsi_dev (the handle keeps
+ *              8*norb*N bytes of FP32 copies).  KX_PREC_MIXED forms the pair
+ *              products and all energies from the FP64 orbitals in FP64.
  *   psi_dev    norb*N orbitals (read only)
  *   vxpsi_dev  norb*N outputs, overwritten (not accumulated into)
  * Also prepares E_x = -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h with

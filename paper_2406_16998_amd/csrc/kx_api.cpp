@@ -134,6 +134,8 @@ struct kx_grid {
   double f_omega = 0.0;
   // workspace
   double* dT = nullptr;
+  float* dT2 = nullptr;  // FP32 intermediate of the mixed path (slots2 slots)
+  int slots2 = 0;
   int slots = 0;
   double* dEpart = nullptr;
   int epart_slots = 0;
@@ -289,8 +291,10 @@ kx_status check_kernel_args(const kx_grid* g, int kernel, double omega) {
 
 kx_status check_types(const kx_grid* g, int dtype, int prec) {
   if (dtype != KX_F64 && dtype != KX_F32) return KX_ERR_INVALID_ARG;
-  if (prec < KX_PREC_FP64 || prec > KX_PREC_FP16X3) return KX_ERR_INVALID_ARG;
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED) return KX_ERR_INVALID_ARG;
   if (prec == KX_PREC_FP16X3) return KX_ERR_UNSUPPORTED;
+  if (prec == KX_PREC_MIXED)  // FP64 forward pass, split inverse pass
+    return g->plan_d.fwd.ok && g->plan_s.inv.ok ? KX_OK : KX_ERR_UNSUPPORTED;
   const Plan& p = prec == KX_PREC_FP64 ? g->plan_d : (prec == KX_PREC_FP32 ? g->plan_f : g->plan_s);
   if (!p.fwd.ok || !p.inv.ok) return KX_ERR_UNSUPPORTED;
   return KX_OK;
@@ -333,6 +337,22 @@ kx_status ensure_workspace(kx_grid* g, int slots) {
   return KX_OK;
 }
 
+// The FP32 copy of the intermediate that the mixed path's inverse pass reads.
+kx_status ensure_t2(kx_grid* g, int slots) {
+  if (slots <= g->slots2) return KX_OK;
+  KX_HIP(hipStreamSynchronize(g->stream));
+  dev_free(g->dT2);
+  g->dT2 = nullptr;
+  g->slots2 = 0;
+  ++g->gen;
+  kx_status st = dev_alloc((void**)&g->dT2, sizeof(float) * (size_t)g->geom.slot * slots);
+  if (st != KX_OK) return st;
+  // padded rows are never written by the kernels; keep them zero
+  KX_HIP(hipMemsetAsync(g->dT2, 0, sizeof(float) * (size_t)g->geom.slot * slots, g->stream));
+  g->slots2 = slots;
+  return KX_OK;
+}
+
 // Bracket one kernel launch with timing events when profiling is on.
 template <class F>
 hipError_t timed(kx_grid* g, hipStream_t s, int kind, F&& launch) {
@@ -354,17 +374,44 @@ hipError_t timed(kx_grid* g, hipStream_t s, int kind, F&& launch) {
 
 // One batch of nb items through the three transform passes (and, for the
 // exchange, the per-pair energy reduction), in the arithmetic of prec.
-hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int dtype, const void* src, const Item* it,
-                     int nb, const void* psi, const double* occ, void* dst, int norb, double dV) {
+// src (the forward pass input) has storage src_dtype; psi and dst (the
+// inverse pass) have storage dtype.
+hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dtype,
+                     const void* src, const Item* it, int nb, int dtype, const void* psi,
+                     const double* occ, void* dst, int norb, double dV) {
   const Geom& G = g->geom;
   double* epart = mode == 1 ? g->dEpart : nullptr;
   const int nstrips = (int)(G.slab / kTile);
   hipError_t e;
+  if (prec == KX_PREC_MIXED) {
+    // forward, f scaling and energies in FP64; the pencil's result rounded
+    // into the FP32 intermediate; split-BF16 inverse pass
+    const EigR<double> E = eig_of(g);
+    double* T = (double*)g->dT;
+    e = timed(g, st, KX_PHASE_FORWARD, [&] {
+      return launch_forward_d(src_dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, st);
+    });
+    if (e != hipSuccess) return e;
+    e = timed(g, st, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, epart, st, g->dT2);
+    });
+    if (e != hipSuccess) return e;
+    if (mode == 1) {
+      e = timed(g, st, KX_PHASE_ENERGY, [&] {
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
+      });
+      if (e != hipSuccess) return e;
+    }
+    return timed(g, st, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, eigs_of(g), g->dT2, it, nb, psi, occ,
+                              dst, st);
+    });
+  }
   if (prec == KX_PREC_FP64) {
     const EigR<double> E = eig_of(g);
     double* T = (double*)g->dT;
     e = timed(g, st, KX_PHASE_FORWARD, [&] {
-      return launch_forward_d(dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, st);
+      return launch_forward_d(src_dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, st);
     });
     if (e != hipSuccess) return e;
     e = timed(g, st, KX_PHASE_PENCIL, [&] {
@@ -385,7 +432,7 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int dtype, 
     const EigS E = eigs_of(g);
     float* T = (float*)g->dT;
     e = timed(g, st, KX_PHASE_FORWARD, [&] {
-      return launch_forward_s(dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, st);
+      return launch_forward_s(src_dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, st);
     });
     if (e != hipSuccess) return e;
     e = timed(g, st, KX_PHASE_PENCIL, [&] {
@@ -405,7 +452,7 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int dtype, 
   const EigR<float> E = eigf_of(g);
   float* T = (float*)g->dT;
   e = timed(g, st, KX_PHASE_FORWARD, [&] {
-    return launch_forward_f(dtype, mode, G, g->plan_f.fwd, E, src, it, nb, T, st);
+    return launch_forward_f(src_dtype, mode, G, g->plan_f.fwd, E, src, it, nb, T, st);
   });
   if (e != hipSuccess) return e;
   e = timed(g, st, KX_PHASE_PENCIL, [&] {
@@ -522,6 +569,10 @@ kx_status prepare_exchange(kx_grid* g, int kernel, double omega, int norb, int d
     maxb = std::max(maxb, g->sched_offsets[b + 1] - g->sched_offsets[b]);
   st = ensure_workspace(g, maxb);
   if (st != KX_OK) return st;
+  if (prec == KX_PREC_MIXED) {
+    st = ensure_t2(g, maxb);
+    if (st != KX_OK) return st;
+  }
   st = ensure_ftable(g, kernel, omega);
   if (st != KX_OK) return st;
   st = upload_items(g, 1, norb, cap, g->sched_pairs);
@@ -575,8 +626,10 @@ hipError_t enqueue_exchange(kx_grid* g, const XPlan& xp, hipStream_t s) {
   for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
     const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
     if (nb <= 0) continue;
-    e = run_batch(g, s, 1, xp.prec, xp.dtype_w, xp.psi_w, g->dItems + o0, nb, xp.psi_w, g->dOcc,
-                  xp.vx_w, xp.norb, xp.dV);
+    // the mixed path's FP64 forward pass reads the caller's orbitals
+    const bool mixed = xp.prec == KX_PREC_MIXED;
+    e = run_batch(g, s, 1, xp.prec, mixed ? xp.dtype : xp.dtype_w, mixed ? xp.psi : xp.psi_w,
+                  g->dItems + o0, nb, xp.dtype_w, xp.psi_w, g->dOcc, xp.vx_w, xp.norb, xp.dV);
     if (e != hipSuccess) return e;
   }
   if (xp.narrow) {
@@ -954,6 +1007,7 @@ kx_status kx_destroy(kx_grid* g) {
   }
   dev_free(g->dF);
   dev_free(g->dT);
+  dev_free(g->dT2);
   dev_free(g->dEpart);
   dev_free(g->dItems);
   dev_free(g->dOcc);
@@ -984,6 +1038,10 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   const int chunk = std::min(batch, g->max_slots);
   st = ensure_workspace(g, chunk);
   if (st != KX_OK) return st;
+  if (prec == KX_PREC_MIXED) {
+    st = ensure_t2(g, chunk);
+    if (st != KX_OK) return st;
+  }
   st = ensure_ftable(g, kernel, omega);
   if (st != KX_OK) return st;
   std::vector<Item> items(batch);
@@ -992,8 +1050,8 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   if (st != KX_OK) return st;
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
-    KX_HIP(run_batch(g, g->stream, 0, prec, dtype, rho_dev, g->dItems + b0, nb, nullptr, nullptr,
-                     phi_dev, 0, 0.0));
+    KX_HIP(run_batch(g, g->stream, 0, prec, dtype, rho_dev, g->dItems + b0, nb, dtype, nullptr,
+                     nullptr, phi_dev, 0, 0.0));
   }
   return KX_OK;
 }
@@ -1096,6 +1154,10 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
 kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
                       const char* cache_path) {
   if (!g || dtype < KX_F64 || dtype > KX_F32) return KX_ERR_INVALID_ARG;
+  if (prec == KX_PREC_MIXED) {  // its forward and pencil passes are FP64's, its inverse BF16X3's
+    const kx_status st = kx_autotune(g, KX_PREC_FP64, dtype, items, verify, cache_path);
+    return st != KX_OK ? st : kx_autotune(g, KX_PREC_BF16X3, dtype, items, verify, cache_path);
+  }
   if (prec != KX_PREC_FP64 && prec != KX_PREC_FP32 && prec != KX_PREC_BF16X3)
     return prec == KX_PREC_FP16X3 ? KX_ERR_UNSUPPORTED : KX_ERR_INVALID_ARG;
   const Geom& G = g->geom;
@@ -1359,8 +1421,10 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
 
 kx_status kx_get_plan(kx_grid* g, int prec, int* fwd_out, int* pen_out, int* inv_out) {
   if (!g || !fwd_out || !pen_out || !inv_out) return KX_ERR_INVALID_ARG;
-  if (prec < KX_PREC_FP64 || prec > KX_PREC_BF16X3) return KX_ERR_INVALID_ARG;
-  const Plan& p = prec == KX_PREC_FP64 ? g->plan_d : (prec == KX_PREC_FP32 ? g->plan_f : g->plan_s);
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED || prec == KX_PREC_FP16X3)
+    return KX_ERR_INVALID_ARG;
+  Plan p = prec == KX_PREC_FP32 ? g->plan_f : (prec == KX_PREC_BF16X3 ? g->plan_s : g->plan_d);
+  if (prec == KX_PREC_MIXED) p.inv = g->plan_s.inv;
   const int f[6] = {p.fwd.qsplit, p.fwd.slabs, p.fwd.waves, p.fwd.kc, p.fwd.vlds ? 1 : 0,
                     (int)p.fwd.lds_bytes};
   const int q[2] = {p.pen.waves, (int)p.pen.lds_bytes};

@@ -13,8 +13,10 @@ hipError_t launch_forward_d(int storage, int mode, const Geom& g, const SlabPlan
 }
 
 hipError_t launch_pencil_d(const Geom& g, const PencilPlan& p, const EigR<double>& e,
-                              const double* F, int nitems, double* T, double* epart, hipStream_t s) {
-  return pen_launch<double>(g, p, e, F, nitems, T, epart, s);
+                              const double* F, int nitems, double* T, double* epart, hipStream_t s,
+                              float* out_f) {
+  return out_f ? pen_launch<double, float>(g, p, e, F, nitems, T, out_f, epart, s)
+               : pen_launch<double, double>(g, p, e, F, nitems, T, T, epart, s);
 }
 
 hipError_t launch_inverse_d(int storage, int mode, const Geom& g, const SlabPlan& p,

@@ -14,7 +14,7 @@ hipError_t launch_forward_f(int storage, int mode, const Geom& g, const SlabPlan
 
 hipError_t launch_pencil_f(const Geom& g, const PencilPlan& p, const EigR<float>& e,
                               const double* F, int nitems, float* T, double* epart, hipStream_t s) {
-  return pen_launch<float>(g, p, e, F, nitems, T, epart, s);
+  return pen_launch<float, float>(g, p, e, F, nitems, T, T, epart, s);
 }
 
 hipError_t launch_inverse_f(int storage, int mode, const Geom& g, const SlabPlan& p,

@@ -124,8 +124,10 @@ hipError_t launch_ftable(const double* const lamE[3], const double* const lamO[3
 hipError_t launch_forward_d(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigR<double>& e, const void* src, const Item* items, int nitems,
                             double* T, hipStream_t s);
+// out_f: NULL = in place; else the result rounded to float into out_f (same layout)
 hipError_t launch_pencil_d(const Geom& g, const PencilPlan& p, const EigR<double>& e,
-                           const double* F, int nitems, double* T, double* epart, hipStream_t s);
+                           const double* F, int nitems, double* T, double* epart, hipStream_t s,
+                           float* out_f = nullptr);
 hipError_t launch_inverse_d(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigR<double>& e, const double* T, const Item* items, int nitems,
                             const void* psi, const double* occ, void* dst, hipStream_t s);

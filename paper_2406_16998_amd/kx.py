@@ -19,7 +19,7 @@ STATUS = {
 }
 BC = {"dirichlet": 0, "periodic": 1}
 KERNEL = {"coulomb": 0, "erfc": 1}
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3, "mixed": 4}
 DTYPE = {"f64": 0, "f32": 1}
 
 # every symbol include/kx.h declares

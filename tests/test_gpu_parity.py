@@ -24,6 +24,8 @@ TOL64 = 1e-10
 TOL32_FIELD = 1e-5
 TOL32_ENERGY = 1e-6
 REDUCED = ["fp32", "bf16x3"]
+# mixed: FP64 forward pass, f scaling and energies (energies at the FP64
+# tolerance), split-BF16 back-transform and Vx psi update (FP32 tolerances)
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_energies.json")
 
 
@@ -217,7 +219,7 @@ def test_exchange_production_size_sampled(torch_cuda):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("prec", REDUCED)
+@pytest.mark.parametrize("prec", REDUCED + ["mixed"])
 def test_exchange_production_size_reduced_precision(torch_cuda, prec):
     """The 128-orbital 96^3 erfc workload in reduced precision: E_x and the
     sampled pair energies against the stored oracle values, Vx psi of one
@@ -233,10 +235,11 @@ def test_exchange_production_size_reduced_precision(torch_cuda, prec):
     ex = g.exchange_energy()
     pe = g.pair_energies(gold["pairs"])
     print(f"{prec} E_x gpu={ex!r} oracle={gold['E_x']!r} |dE|={abs(ex - gold['E_x']):.3e} Ha", flush=True)
-    assert abs(ex - gold["E_x"]) <= TOL32_ENERGY * abs(gold["E_x"])
+    tol_e = TOL64 if prec == "mixed" else TOL32_ENERGY
+    assert abs(ex - gold["E_x"]) <= tol_e * abs(gold["E_x"])
     emax = max(abs(r) for r in gold["pair_energies"])
     for e, r in zip(pe, gold["pair_energies"]):
-        assert abs(e - r) <= TOL32_ENERGY * emax
+        assert abs(e - r) <= tol_e * emax
     ref = orc.vx_orbital(psi, occ, 5, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
     assert _rel(vx[5].cpu().numpy(), ref) <= TOL32_FIELD
     g.close()
@@ -266,7 +269,7 @@ def test_error_statuses_on_device(torch_cuda):
 # ------------------------------------------------------------------ reduced precision
 
 
-@pytest.mark.parametrize("prec", REDUCED)
+@pytest.mark.parametrize("prec", REDUCED + ["mixed"])
 @pytest.mark.parametrize("n,h,order,bc,kernel,omega", FL_CASES)
 def test_apply_fL_reduced_precision(torch_cuda, n, h, order, bc, kernel, omega, prec):
     torch = torch_cuda
@@ -296,6 +299,32 @@ def test_exchange_reduced_precision(torch_cuda, name, prec):
     vx_ref, ex_ref = orc.exchange(psi, occ, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
     print(f"{prec} {name}: dE/E={abs(ex - ex_ref) / abs(ex_ref):.2e}", flush=True)
     assert abs(ex - ex_ref) <= TOL32_ENERGY * abs(ex_ref)
+    for j in range(w.norb):
+        assert _rel(vx[j], vx_ref[j]) <= TOL32_FIELD, j
+
+
+@pytest.mark.parametrize("name", ["mixed40x36x44_erfc", "dirichlet32_coulomb", "dirichlet20x27x34_coulomb"])
+def test_exchange_mixed_precision(torch_cuda, name):
+    """Energies (total and per pair) at the FP64 tolerance, Vx psi at the FP32
+    tolerance; non-uniform occupations."""
+    torch = torch_cuda
+    kx = _kx()
+    print(f"exchange mixed {name}", flush=True)
+    w, psi, occ = make_workload(name)
+    occ = occ * np.linspace(1.0, 0.25, w.norb)
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    vx = g.apply_exchange(torch.from_numpy(psi).cuda(), occ, w.kernel, w.omega, prec="mixed")
+    ex = g.exchange_energy()
+    pairs = [(i, j) for i in range(w.norb) for j in range(i, w.norb)]
+    pe = g.pair_energies(pairs)
+    vx = vx.cpu().numpy()
+    g.close()
+    grid = orc.make_grid(w.n, w.h, w.order, w.bc)
+    vx_ref, ex_ref, pe_ref = orc.exchange(psi, occ, grid, w.kernel, w.omega, pair_energies=True)
+    print(f"mixed {name}: dE/E={abs(ex - ex_ref) / abs(ex_ref):.2e}", flush=True)
+    assert abs(ex - ex_ref) <= TOL64 * abs(ex_ref)
+    for p, e in zip(pairs, pe):
+        assert abs(e - pe_ref[p]) <= TOL64 * abs(pe_ref[p]) + 1e-14 * abs(ex_ref), p
     for j in range(w.norb):
         assert _rel(vx[j], vx_ref[j]) <= TOL32_FIELD, j
 
