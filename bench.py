@@ -170,13 +170,14 @@ def roofline(w, prec, phases, steps):
     return roof
 
 
-def measure(g, w, psi_d, occ, vx, prec, steps, warmup, tune):
+def measure(g, w, psi_d, occ, vx, prec, steps, warmup, tune, tune_cache=None):
     """Warm-up, then `steps` timed exchange applications (HIP events on the
     stream the library runs on); per-phase times from the library's events."""
     import torch
     t0 = time.perf_counter()
     if tune:
-        g.autotune(prec=prec, dtype="f64" if psi_d.dtype == torch.float64 else "f32")
+        g.autotune(prec=prec, dtype="f64" if psi_d.dtype == torch.float64 else "f32",
+                   cache_path=tune_cache)
     tune_s = time.perf_counter() - t0
     for k in range(warmup):
         g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec=prec, out=vx)
@@ -274,6 +275,8 @@ def main():
     ap.add_argument("--workload", default="periodic96_erfc", help="a synth workload, or 'ragged'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the planner's launch shapes")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner result file: read if it holds this grid, else appended")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -303,8 +306,8 @@ def main():
     precs = ["fp64", "fp32", "bf16x3", "mixed"] if args.prec == "all" else [args.prec]
     print(f"# workload {w.name}: {w.n} {w.bc} norb={w.norb} pairs={w.npairs} prec={precs}",
           file=sys.stderr, flush=True)
-    runs = {p: measure(g, w, psi_d, occ, vx, p, args.steps, args.warmup, not args.no_tune)
-            for p in precs}
+    runs = {p: measure(g, w, psi_d, occ, vx, p, args.steps, args.warmup, not args.no_tune,
+                       args.tune_cache) for p in precs}
     # the headline: the fastest variant whose E_x is within 1e-8 Ha of FP64
     # (FP64 itself when it ran; else the single variant asked for)
     ref_ex = runs["fp64"]["E_x"] if "fp64" in runs else None
