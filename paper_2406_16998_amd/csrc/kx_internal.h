@@ -72,8 +72,13 @@ struct EigS {
 constexpr int kFwdPos = 2;  // folded positions staged per thread per chunk (forward)
 constexpr int kInvEl = 8;   // elements staged per thread per chunk (inverse)
 constexpr int fwd_mt(int nt) { return nt <= 3 ? 1024 : (nt == 4 ? 768 : 640); }
+// waves per SIMD the forward pass keeps its registers for: six lets two
+// 12-wave workgroups share a CU, so one workgroup's loads overlap the
+// other's products
+constexpr int fwd_min_waves(int nt) { return nt <= 3 ? 6 : 1; }
 constexpr int inv_mt(int nt) { return nt <= 2 ? 1024 : (nt == 3 ? 768 : 512); }
 constexpr int pen_mt(int nt) { return nt <= 2 ? 1024 : 512; }
+constexpr int pen_min_waves(int nt) { return nt <= 3 ? 3 : 1; }
 
 // One item of a transform batch: an orbital pair (i, j) for the exchange,
 // (b, -1) with b the field index for apply_fL.

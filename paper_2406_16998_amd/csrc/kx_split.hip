@@ -128,7 +128,7 @@ __device__ __forceinline__ void sf_store(const f4* acc2, float* __restrict__ Tzb
 // XST: some staged positions exceed the register budget (grids whose x
 // extent is large against y) and are loaded directly in the stash step.
 template <class S, int NT, bool OFULL, int MODE, bool XST, int MT>
-__global__ void __launch_bounds__(MT)
+__global__ void __launch_bounds__(MT, fwd_min_waves(NT))
 split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict__ items,
               float* __restrict__ T, int slabs, int kc, int qsplit) {
   float* lds = kx_split_lds;
