@@ -217,7 +217,7 @@ def bench_ragged(args):
 
     from paper_2406_16998_amd import kx
     from synth import RAGGED_BATCH, make_workload
-    precs = ["fp64", "bf16x3"] if args.prec == "all" else [args.prec]
+    precs = ["fp64", "bf16x3", "mixed"] if args.prec == "all" else [args.prec]
     systems = []
     for name in RAGGED_BATCH:
         w, psi, occ = make_workload(name)
