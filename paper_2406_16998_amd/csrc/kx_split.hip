@@ -26,6 +26,8 @@
 // no contraction of products and sums into fused operations.
 #pragma clang fp contract(off)
 
+#include "kx_epilogue.inc"
+
 namespace kx {
 namespace {
 
@@ -514,7 +516,6 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
   for (int k = 0; k < 4 * NT; ++k) bs[k] = split4(acc1[k][0], acc1[k][1], acc1[k][2], acc1[k][3]);
 
   const bool xin = zin && xp < g.me1;
-  const int xm = g.n1 - 1 - xp;
   const long long zoff = (long long)(zin ? z : 0) * g.n1 * g.n2;
   const Item item = items[it];
   const S* __restrict__ pi = psi + (long long)item.i * g.N + zoff;
@@ -524,6 +525,10 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
   const bool offdiag = MODE == 1 && item.i != item.j;
   const float oi = MODE == 1 ? (float)occ[item.i] : 0.f;
   const float oj = MODE == 1 ? (float)occ[item.j] : 0.f;
+  // output groups (u, r): the next group's loads go out before this one's stores
+  EpiGroup<S> cur, nxt;
+  epi_addr(cur, g, xin, xp, 4 * lg);
+  if (MODE == 1) epi_load(cur, pi, pj, vj, vi);
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     f4 Q[4];
@@ -531,31 +536,20 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
       si_mode2<NT, NTO, true>(bs, Q, u, e.E[1], e.O[1], pe2, po2, lg, li);
     else
       si_mode2<NT, NTO, false>(bs, Q, u, e.E[1], e.O[1], pe2, po2, lg, li);
-    if (!xin) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int yp = kTile * u + 4 * lg + r;
-      if (yp >= g.me2) continue;
+      const int gn = 4 * u + r + 1;
+      if (gn < 4 * NT) {
+        epi_addr(nxt, g, xin, xp, kTile * (gn / 4) + 4 * lg + gn % 4);
+        if (MODE == 1) epi_load(nxt, pi, pj, vj, vi);
+      }
       const float ee = Q[0][r], eo = has_o ? Q[1][r] : 0.f;
       const float oe = u < NTO ? Q[2][r] : 0.f, oo = (has_o && u < NTO) ? Q[3][r] : 0.f;
-      const int ym = g.n2 - 1 - yp;
-      const bool hx = xp < g.mo1, hy = yp < g.mo2;
       const float ph[4] = {ee + eo + oe + oo, ee - eo + oe - oo, ee + eo - oe - oo,
                            ee - eo - oe + oo};
-      const unsigned o[4] = {(unsigned)(yp * g.n1 + xp), (unsigned)(yp * g.n1 + xm),
-                             (unsigned)(ym * g.n1 + xp), (unsigned)(ym * g.n1 + xm)};
-      const bool ok[4] = {true, hx, hy, hx && hy};
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if (!ok[m]) continue;
-        if (MODE == 0) {
-          vj[o[m]] = (S)ph[m];
-        } else {
-          // FP32 update (Vx psi is accumulated in FP32 on this path)
-          vj[o[m]] = (S)((float)vj[o[m]] - (oi * ph[m]) * (float)pi[o[m]]);
-          if (offdiag) vi[o[m]] = (S)((float)vi[o[m]] - (oj * ph[m]) * (float)pj[o[m]]);
-        }
-      }
+      // FP32 update (Vx psi is accumulated in FP32 on this path)
+      epi_store<float, S, MODE>(cur, ph, vj, vi, oi, oj, offdiag);
+      if (gn < 4 * NT) cur = nxt;
     }
   }
 }
