@@ -229,7 +229,7 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     for (size_t extra : {vb, (size_t)0}) {
       for (int c : {16, 8, 4}) {
         if ((size_t)2 * c * g.p2 <= (size_t)kInvEl * wps * 64 &&
-            (size_t)v.slabs * 2 * 2 * c * g.p2 * esize + extra <= max_lds) {
+            (size_t)v.slabs * inv_slab_elems(g, c, inv_band(esize)) * esize + extra <= max_lds) {
           v.kc = c;
           break;
         }
@@ -238,7 +238,7 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     }
     v.ok = v.kc != 0;
     if (!v.ok) v.kc = 4;
-    const size_t chunk = (size_t)v.slabs * 2 * 2 * v.kc * g.p2 * esize;
+    const size_t chunk = (size_t)v.slabs * inv_slab_elems(g, v.kc, inv_band(esize)) * esize;
     v.vlds = chunk + vb <= max_lds;
     v.lds_bytes = chunk + (v.vlds ? vb : 0);
   }
@@ -316,8 +316,9 @@ void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPl
         if (split && kc != 16) continue;
         if (!split && (size_t)2 * kc * g.p2 > (size_t)kInvEl * wps * 64) continue;
         for (int vl : {0, 1}) {
-          if (split && vl) continue;
-          const size_t lds = (size_t)slabs * 2 * 2 * kc * g.p2 * esize + (vl ? vb : 0);
+          // split: the pre-split V2 blocks (three bf16 planes, padded rows)
+          const size_t lds = split ? split_inv_lds(g, slabs, vl != 0)
+                                   : (size_t)slabs * inv_slab_elems(g, kc, inv_band(esize)) * esize + (vl ? vb : 0);
           if (lds > max_lds) continue;
           SlabPlan p;
           p.slabs = slabs;

@@ -80,6 +80,30 @@ constexpr int inv_mt(int nt) { return nt <= 2 ? 1024 : (nt == 3 ? 768 : 512); }
 constexpr int pen_mt(int nt) { return nt <= 2 ? 1024 : 512; }
 constexpr int pen_min_waves(int nt) { return nt <= 3 ? 3 : 1; }
 
+// Split inverse pass with its V2 blocks in LDS: row stride (bf16 elements) of
+// a staged block, padded by 4 so that the 16 rows of an operand read start in
+// different banks, and the bytes of the three planes of both blocks.
+__host__ __device__ inline int sinv_ld(int n) { return n + 4; }
+__host__ __device__ inline size_t sinv_vbytes(const Geom& g) {
+  const size_t b = 2 * 3 * ((size_t)g.pe2 * sinv_ld(g.pe2) + (size_t)g.po2 * sinv_ld(g.po2));
+  return (b + 15) / 16 * 16;
+}
+// Elements (of the operand type) of LDS per z-slab of an inverse launch: two
+// staged chunks of kc rows, reused afterwards for the output: the slab's phi
+// plane (n1 x n2), or one output band (2 kTile rows of n1) at a time.
+__host__ __device__ inline size_t inv_slab_elems(const Geom& g, int kc, bool band) {
+  const size_t stage = (size_t)2 * 2 * kc * g.p2;
+  const size_t out = band ? (size_t)2 * kTile * g.n1 : (size_t)g.n1 * g.n2;
+  return ((stage > out ? stage : out) + 3) / 4 * 4;
+}
+// Inverse kernels with FP64 operands stream bands, the others whole planes.
+__host__ __device__ inline bool inv_band(size_t esize) { return esize == 8; }
+// LDS of a split inverse launch, plus the V2 blocks when they are resident.
+inline size_t split_inv_lds(const Geom& g, int slabs, bool vlds) {
+  return (size_t)slabs * inv_slab_elems(g, kTile, false) * sizeof(float) +
+         (vlds ? sinv_vbytes(g) : 0);
+}
+
 // One item of a transform batch: an orbital pair (i, j) for the exchange,
 // (b, -1) with b the field index for apply_fL.
 struct Item {

@@ -424,20 +424,22 @@ __device__ __forceinline__ void si_k_step(f4* acc1q, const float* __restrict__ a
   }
 }
 
+// lde / ldo: row strides of the even / odd V2 blocks (in global memory or
+// LDS), pse / pso: their plane strides.
 template <int NT, int NTO, bool HASO>
 __device__ __forceinline__ void si_mode2(const Split4* bs, f4* Q, int u, const short* __restrict__ VE2,
-                                         const short* __restrict__ VO2, int pe2, int po2, int lg,
-                                         int li) {
+                                         const short* __restrict__ VO2, int lde, int ldo, int pse,
+                                         int pso, int lg, int li) {
   // bs[(q * 2 + p) * NT + t] = split(acc1 tile); A[m = y'][k = b] = V2p[y'][b]
 #pragma unroll
   for (int k = 0; k < 4; ++k) Q[k] = kZ;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const Split4 a = load_split(VE2 + (kTile * u + li) * pe2 + kTile * t + 4 * lg, pe2 * pe2);
+    const Split4 a = load_split(VE2 + (kTile * u + li) * lde + kTile * t + 4 * lg, pse);
     Q[0] = mma6(a, bs[(0 * 2 + 0) * NT + t], Q[0]);
     if (HASO) Q[1] = mma6(a, bs[(1 * 2 + 0) * NT + t], Q[1]);
     if (t < NTO && u < NTO) {
-      const Split4 ao = load_split(VO2 + (kTile * u + li) * po2 + kTile * t + 4 * lg, po2 * po2);
+      const Split4 ao = load_split(VO2 + (kTile * u + li) * ldo + kTile * t + 4 * lg, pso);
       Q[2] = mma6(ao, bs[(0 * 2 + 1) * NT + t], Q[2]);
       if (HASO) Q[3] = mma6(ao, bs[(1 * 2 + 1) * NT + t], Q[3]);
     }
@@ -445,13 +447,16 @@ __device__ __forceinline__ void si_mode2(const Split4* bs, f4* Q, int u, const s
   }
 }
 
-template <class S, int NT, bool OFULL, int MODE, int MT>
+template <class S, int NT, bool OFULL, int MODE, bool VL, int MT>
 __global__ void __launch_bounds__(MT)
 split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restrict__ items,
               const S* __restrict__ psi, const double* __restrict__ occ, S* __restrict__ dst,
               int slabs, int kc) {
   constexpr int NTO = OFULL ? NT : NT - 1;
-  float* lds = kx_split_lds;
+  // LDS: [pre-split V2 blocks, rows padded (VL)] [slabs][staged chunks / phi plane]
+  short* __restrict__ vE = reinterpret_cast<short*>(kx_split_lds);
+  short* __restrict__ vO = vE + 3 * g.pe2 * sinv_ld(g.pe2);
+  float* lds = kx_split_lds + (VL ? sinv_vbytes(g) / sizeof(float) : 0);
   const int tid = threadIdx.x;
   const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -463,8 +468,20 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
   const int it = blockIdx.y;
   const int pe2 = g.pe2, po2 = g.po2, p2 = g.p2;
   const int celems = 2 * kc * p2;
-  float* __restrict__ sb = lds + (size_t)s * 2 * celems;
+  // this slab's LDS: the staged chunks, then the phi plane
+  float* __restrict__ sb = lds + (size_t)s * inv_slab_elems(g, kTile, false);
   const float* __restrict__ Tz = T + (long long)it * g.slot + (long long)(zin ? z : 0) * g.slab;
+  if (VL) {  // 8-byte pieces of the three planes of each block (visible after the first barrier)
+    const int lde = sinv_ld(pe2), ldo = sinv_ld(po2);
+    const int ne = 3 * pe2 * (pe2 / 4), no = 3 * po2 * (po2 / 4);
+    for (int idx = tid; idx < ne + no; idx += blockDim.x) {
+      const bool od = idx >= ne;
+      const int k = od ? idx - ne : idx, w = od ? po2 : pe2, ld = od ? ldo : lde;
+      const int row = k / (w / 4), c = k - row * (w / 4);  // row over planes x rows
+      const s4 v = *reinterpret_cast<const s4*>((od ? e.O[1] : e.E[1]) + row * w + 4 * c);
+      *reinterpret_cast<s4*>((od ? vO : vE) + row * ld + 4 * c) = v;
+    }
+  }
   // Staged chunk [q][kc][p2]: rows a0 .. a0 + kc of the even (q = 0) and odd
   // (q = 1) x-parity blocks of this slab, contiguous in T.  Copied global ->
   // LDS without registers, 1 KB per wave instruction (16 bytes a lane); the
@@ -525,33 +542,33 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
   const bool offdiag = MODE == 1 && item.i != item.j;
   const float oi = MODE == 1 ? (float)occ[item.i] : 0.f;
   const float oj = MODE == 1 ? (float)occ[item.j] : 0.f;
-  // output groups (u, r): the next group's loads go out before this one's stores
-  EpiGroup<S> cur, nxt;
-  epi_addr(cur, g, xin, xp, 4 * lg);
-  if (MODE == 1) epi_load(cur, pi, pj, vj, vi);
+  // phi of this slab into LDS (the staged chunks are no longer read), then
+  // the plane's rows through the update
+  float* __restrict__ plane = sb;
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     f4 Q[4];
+    const short* VE2 = VL ? vE : e.E[1];
+    const short* VO2 = VL ? vO : e.O[1];
+    const int lde = VL ? sinv_ld(pe2) : pe2, ldo = VL ? sinv_ld(po2) : po2;
     if (has_o)
-      si_mode2<NT, NTO, true>(bs, Q, u, e.E[1], e.O[1], pe2, po2, lg, li);
+      si_mode2<NT, NTO, true>(bs, Q, u, VE2, VO2, lde, ldo, pe2 * lde, po2 * ldo, lg, li);
     else
-      si_mode2<NT, NTO, false>(bs, Q, u, e.E[1], e.O[1], pe2, po2, lg, li);
+      si_mode2<NT, NTO, false>(bs, Q, u, VE2, VO2, lde, ldo, pe2 * lde, po2 * ldo, lg, li);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int gn = 4 * u + r + 1;
-      if (gn < 4 * NT) {
-        epi_addr(nxt, g, xin, xp, kTile * (gn / 4) + 4 * lg + gn % 4);
-        if (MODE == 1) epi_load(nxt, pi, pj, vj, vi);
-      }
       const float ee = Q[0][r], eo = has_o ? Q[1][r] : 0.f;
       const float oe = u < NTO ? Q[2][r] : 0.f, oo = (has_o && u < NTO) ? Q[3][r] : 0.f;
       const float ph[4] = {ee + eo + oe + oo, ee - eo + oe - oo, ee + eo - oe - oo,
                            ee - eo - oe + oo};
-      // FP32 update (Vx psi is accumulated in FP32 on this path)
-      epi_store<float, S, MODE>(cur, ph, vj, vi, oi, oj, offdiag);
-      if (gn < 4 * NT) cur = nxt;
+      plane_put(plane, g, xin, xp, kTile * u + 4 * lg + r, ph);
     }
   }
+  __syncthreads();
+  if (!zin) return;
+  // FP32 update (Vx psi is accumulated in FP32 on this path)
+  rows_apply<float, S, MODE, 4>(plane, g, plane_rows(g), tid - s * nstr * 64, nstr * 64, pi, pj,
+                                vj, vi, oi, oj, offdiag);
 }
 
 template <class K>
@@ -635,8 +652,11 @@ hipError_t sinv_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e
 #define KX_CASE(NT)                                                                         \
   case NT: {                                                                                \
     constexpr int MT = inv_mt(NT);                                                          \
-    auto k = mode == 1 ? (of ? split_inverse<S, NT, true, 1, MT> : split_inverse<S, NT, false, 1, MT>) \
-                       : (of ? split_inverse<S, NT, true, 0, MT> : split_inverse<S, NT, false, 0, MT>); \
+    auto k = mode == 1 ? (of ? split_inverse<S, NT, true, 1, false, MT> : split_inverse<S, NT, false, 1, false, MT>) \
+                       : (of ? split_inverse<S, NT, true, 0, false, MT> : split_inverse<S, NT, false, 0, false, MT>); \
+    if (p.vlds)                                                                             \
+      k = mode == 1 ? (of ? split_inverse<S, NT, true, 1, true, MT> : split_inverse<S, NT, false, 1, true, MT>) \
+                    : (of ? split_inverse<S, NT, true, 0, true, MT> : split_inverse<S, NT, false, 0, true, MT>); \
     allow_lds(k, lb);                                                                       \
     hipLaunchKernelGGL(k, grid, block, lb, st, g, e, T, items, psi, occ, dst, p.slabs, p.kc); \
     break;                                                                                  \
@@ -667,7 +687,7 @@ Plan make_split_plan(const Geom& g, size_t max_lds) {
   v.kc = kSplitKc;
   v.vlds = false;
   v.ok = true;
-  v.lds_bytes = (size_t)v.slabs * 2 * 2 * v.kc * g.p2 * sizeof(float);
+  v.lds_bytes = split_inv_lds(g, v.slabs, false);
   pl.pen.lds_bytes = 0;
   return pl;
 }
