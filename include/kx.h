@@ -94,9 +94,6 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
  *   prec           arithmetic of the mode products: KX_PREC_FP64, KX_PREC_FP32,
  *                  KX_PREC_BF16X3 or KX_PREC_MIXED (KX_PREC_FP16X3:
  *                  KX_ERR_UNSUPPORTED).
- *                  FP64 and FP32 also return KX_ERR_UNSUPPORTED on grids whose
- *                  y extent exceeds about four times the x extent (staging
- *                  limit of their inverse pass); BF16X3 has no shape limit.
  *   rho_dev        batch*N input values;  phi_dev  batch*N outputs (overwritten)
  * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic. */
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,

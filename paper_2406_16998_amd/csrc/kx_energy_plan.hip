@@ -224,23 +224,13 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     while ((v.slabs + 1) * wps <= maxw && (v.slabs * wps) % 4 != 0) ++v.slabs;
     v.waves = v.slabs * wps;
     const size_t vb = (size_t)(g.pe2 * g.pe2 + g.po2 * g.po2) * esize;
-    // every staged element of a chunk must have a register slot
-    v.kc = 0;
-    for (size_t extra : {vb, (size_t)0}) {
-      for (int c : {16, 8, 4}) {
-        if ((size_t)2 * c * g.p2 <= (size_t)kInvEl * wps * 64 &&
-            (size_t)v.slabs * inv_slab_elems(g, c, inv_band(esize)) * esize + extra <= max_lds) {
-          v.kc = c;
-          break;
-        }
-      }
-      if (v.kc) break;
-    }
-    v.ok = v.kc != 0;
-    if (!v.ok) v.kc = 4;
-    const size_t chunk = (size_t)v.slabs * inv_slab_elems(g, v.kc, inv_band(esize)) * esize;
-    v.vlds = chunk + vb <= max_lds;
-    v.lds_bytes = chunk + (v.vlds ? vb : 0);
+    v.kc = inv_kc(esize);
+    auto chunks = [&](int sl) { return (size_t)sl * inv_slab_elems(g, v.kc, inv_band(esize)) * esize; };
+    while (v.slabs > 1 && chunks(v.slabs) > max_lds) --v.slabs;
+    v.waves = v.slabs * wps;
+    v.ok = chunks(v.slabs) <= max_lds;
+    v.vlds = chunks(v.slabs) + vb <= max_lds;
+    v.lds_bytes = chunks(v.slabs) + (v.vlds ? vb : 0);
   }
   {
     PencilPlan& p = pl.pen;
@@ -313,8 +303,7 @@ void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPl
     const size_t vb = (size_t)(g.pe2 * g.pe2 + g.po2 * g.po2) * esize;
     for (int slabs = 1; slabs * wps <= maxw; ++slabs) {
       for (int kc : {4, 8, 16}) {
-        if (split && kc != 16) continue;
-        if (!split && (size_t)2 * kc * g.p2 > (size_t)kInvEl * wps * 64) continue;
+        if (kc != inv_kc(esize)) continue;  // chunks are copied in 1 KB segments
         for (int vl : {0, 1}) {
           // split: the pre-split V2 blocks (three bf16 planes, padded rows)
           const size_t lds = split ? split_inv_lds(g, slabs, vl != 0)

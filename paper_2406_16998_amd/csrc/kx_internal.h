@@ -70,7 +70,6 @@ struct EigS {
 // Staging budgets of the slab kernels and their launch bounds (threads per
 // workgroup) by register tile count NT, shared by kernels and planner.
 constexpr int kFwdPos = 2;  // folded positions staged per thread per chunk (forward)
-constexpr int kInvEl = 8;   // elements staged per thread per chunk (inverse)
 constexpr int fwd_mt(int nt) { return nt <= 3 ? 1024 : (nt == 4 ? 768 : 640); }
 // waves per SIMD the forward pass keeps its registers for: six lets two
 // 12-wave workgroups share a CU, so one workgroup's loads overlap the
@@ -96,6 +95,9 @@ __host__ __device__ inline size_t inv_slab_elems(const Geom& g, int kc, bool ban
   const size_t out = band ? (size_t)2 * kTile * g.n1 : (size_t)g.n1 * g.n2;
   return ((stage > out ? stage : out) + 3) / 4 * 4;
 }
+// Staged rows per chunk of the inverse pass (the chunks are copied to LDS in
+// 1 KB segments: 64 bytes per column).
+constexpr int inv_kc(size_t esize) { return (int)(64 / esize); }
 // Inverse kernels with FP64 operands stream bands, the others whole planes.
 __host__ __device__ inline bool inv_band(size_t esize) { return esize == 8; }
 // LDS of a split inverse launch, plus the V2 blocks when they are resident.

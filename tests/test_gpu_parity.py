@@ -330,8 +330,9 @@ def test_exchange_mixed_precision(torch_cuda, name):
 
 
 # Grids far from cubic: x much longer than y (forward staging beyond the
-# register budget) and y much longer than x (inverse staging); and axes with
-# four and five 16-row tiles per parity (n_k up to 160).
+# register budget) and y much longer than x (long staged rows in the inverse
+# pass); and axes with four and five 16-row tiles per parity (n_k up to 160).
+# Every precision accepts every shape.
 ANISO = [((70, 8, 12), ("dirichlet",) * 3), ((10, 70, 9), ("dirichlet",) * 3),
          ((9, 66, 20), ("periodic", "periodic", "dirichlet")),
          ((150, 36, 40), ("periodic", "dirichlet", "periodic")),
@@ -352,14 +353,6 @@ def test_apply_fL_anisotropic_grids(torch_cuda, n, bc, prec):
     ref = orc.apply_fL(rho, orc.make_grid(n, h, 12, bc), "coulomb", 0.0)
     try:
         phi = g.apply_fL(torch.from_numpy(rho).cuda(), "coulomb", 0.0, prec=prec).cpu().numpy()
-    except kx.KxError as e:
-        # FP64 / FP32 inverse staging limit (padded folded y extent above four
-        # times the padded even x extent): documented, reported as unsupported
-        def pad16(v):
-            return (v + 15) // 16 * 16
-        p2 = pad16(n[1] - n[1] // 2) + pad16(n[1] // 2)
-        assert prec != "bf16x3" and e.status == 2 and p2 > 4 * pad16(n[0] - n[0] // 2)
-        return
     finally:
         g.close()
     tol = TOL64 if prec == "fp64" else TOL32_FIELD
