@@ -197,12 +197,14 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     f.waves = f.slabs * wps;
     const int wrow = f.qsplit == 1 ? g.p1 : g.pe1;
     const size_t vb = (size_t)(f.qsplit == 1 ? g.pe1 * g.pe1 + g.po1 * g.po1 : g.pe1 * g.pe1) * esize;
-    // every staged position of a chunk must have a register slot
+    // the largest chunk whose staging fits (V1 blocks in LDS if possible)
     f.kc = 0;
     for (size_t extra : {vb, (size_t)0}) {
-      for (int c : {32, 16, 8, 4}) {
-        if ((size_t)c * g.pe1 <= (size_t)kFwdPos * wps * 64 &&
-            (size_t)f.slabs * 2 * 2 * c * wrow * esize + extra <= max_lds) {
+      for (int c : {16, 8, 4}) {
+        // register staging: every staged position of a chunk has a register slot
+        if (c > fwd_max_kc(esize) || (esize != 8 && (size_t)c * g.pe1 > (size_t)kFwdPos * wps * 64))
+          continue;
+        if ((size_t)f.slabs * fwd_slab_bytes(g, c, wrow, esize) + extra <= max_lds) {
           f.kc = c;
           break;
         }
@@ -211,7 +213,7 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
     }
     f.ok = f.kc != 0;
     if (!f.ok) f.kc = 4;
-    const size_t chunk = (size_t)f.slabs * 2 * 2 * f.kc * wrow * esize;
+    const size_t chunk = (size_t)f.slabs * fwd_slab_bytes(g, f.kc, wrow, esize);
     f.vlds = chunk + vb <= max_lds;
     f.lds_bytes = chunk + (f.vlds ? vb : 0);
   }
@@ -263,12 +265,14 @@ void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPl
           (size_t)(qsplit == 1 ? g.pe1 * g.pe1 + g.po1 * g.po1 : g.pe1 * g.pe1) * esize;
       for (int slabs : {1, 2, 4, 8}) {
         if (slabs * wps > maxw) continue;
-        for (int kc : {4, 8, 16, 32}) {
-          if (split && kc != 16) continue;
-          if (!split && (size_t)kc * g.pe1 > (size_t)kFwdPos * wps * 64) continue;
+        for (int kc : {4, 8, 16}) {
+          if (split ? kc != 16 : kc > fwd_max_kc(esize)) continue;
+          if (!split && esize != 8 && (size_t)kc * g.pe1 > (size_t)kFwdPos * wps * 64) continue;
           for (int vl : {0, 1}) {
             if (split && vl) continue;
-            const size_t lds = (size_t)slabs * 2 * 2 * kc * wrow * esize + (vl ? vb : 0);
+            const size_t lds = split ? (size_t)slabs * 2 * 2 * kc * wrow * esize
+                                     : (size_t)slabs * fwd_slab_bytes(g, kc, wrow, esize) +
+                                           (vl ? vb : 0);
             if (lds > max_lds) continue;
             SlabPlan p;
             p.qsplit = qsplit;

@@ -69,7 +69,10 @@ struct EigS {
 
 // Staging budgets of the slab kernels and their launch bounds (threads per
 // workgroup) by register tile count NT, shared by kernels and planner.
-constexpr int kFwdPos = 2;  // folded positions staged per thread per chunk (forward)
+constexpr int kFwdPos = 2;  // folded positions staged per thread per chunk (register staging)
+// Largest chunk (folded rows) of the forward pass: FP64 operands stage raw
+// rows through LDS, FP32 operands through registers.
+constexpr int fwd_max_kc(size_t esize) { return esize == 8 ? 8 : 16; }
 constexpr int fwd_mt(int nt) { return nt <= 3 ? 1024 : (nt == 4 ? 768 : 640); }
 // waves per SIMD the forward pass keeps its registers for: six lets two
 // 12-wave workgroups share a CU, so one workgroup's loads overlap the
@@ -95,6 +98,18 @@ __host__ __device__ inline size_t inv_slab_elems(const Geom& g, int kc, bool ban
   const size_t out = band ? (size_t)2 * kTile * g.n1 : (size_t)g.n1 * g.n2;
   return ((stage > out ? stage : out) + 3) / 4 * 4;
 }
+// FP64 / FP32 forward pass, per z-slab: bytes of LDS for one staged range of
+// raw rows (kc grid rows of n1 values of up to 8 bytes, in whole 1 KB copy
+// segments), and for the slab's two folded buffers ([2][kc][wrow] operands of
+// esize bytes) plus, with FP64 operands, two raw stages of four ranges.
+__host__ __device__ inline int fwd_raw_range(const Geom& g, int kc) {
+  return (kc * g.n1 * 8 + 1023) / 1024 * 1024;
+}
+__host__ __device__ inline size_t fwd_slab_bytes(const Geom& g, int kc, int wrow, size_t esize) {
+  return (size_t)2 * 2 * kc * wrow * esize +
+         (esize == 8 ? (size_t)2 * 4 * fwd_raw_range(g, kc) : 0);
+}
+
 // Staged rows per chunk of the inverse pass (the chunks are copied to LDS in
 // 1 KB segments: 64 bytes per column).
 constexpr int inv_kc(size_t esize) { return (int)(64 / esize); }
