@@ -206,7 +206,7 @@ def measure(g, w, psi_d, occ, vx, prec, steps, warmup, tune, tune_cache=None):
             "phases_ms_per_step": {p: v["ms"] / steps for p, v in phases.items()},
             "roofline": roofline(w, prec, phases, steps),
             "tflops_whole_step": sum(pf.values()) * w.npairs / (ms_step * 1e-3) / 1e12,
-            "plan": g.plan(prec) if prec != "fp16x3" else None, "tune_s": tune_s}
+            "plan": g.plan(prec), "tune_s": tune_s}
 
 
 def bench_ragged(args):
@@ -303,7 +303,7 @@ def main():
     setup_s = time.perf_counter() - t_setup
     psi_d = torch.from_numpy(psi).cuda()
     vx = torch.empty_like(psi_d)
-    precs = ["fp64", "fp32", "bf16x3", "mixed"] if args.prec == "all" else [args.prec]
+    precs = ["fp64", "fp32", "bf16x3", "fp16x3", "mixed"] if args.prec == "all" else [args.prec]
     print(f"# workload {w.name}: {w.n} {w.bc} norb={w.norb} pairs={w.npairs} prec={precs}",
           file=sys.stderr, flush=True)
     runs = {p: measure(g, w, psi_d, occ, vx, p, args.steps, args.warmup, not args.no_tune,

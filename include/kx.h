@@ -61,7 +61,10 @@ typedef enum {
   KX_PREC_FP64 = 0,    /* FP64 MFMA                                          */
   KX_PREC_FP32 = 1,    /* FP32 MFMA, FP32 intermediates                      */
   KX_PREC_BF16X3 = 2,  /* three-term BF16 split of both operands, FP32 accumulate */
-  KX_PREC_FP16X3 = 3,  /* three-term FP16 split, FP32 accumulate             */
+  KX_PREC_FP16X3 = 3,  /* three-term FP16 split of both operands, FP32
+                        * accumulate; every operand scaled by a power of two
+                        * into FP16's range (V by 2^12, data by its largest
+                        * magnitude per item or per wave), scaled back exactly */
   KX_PREC_MIXED = 4    /* FP64 forward transform, f scaling and energies (E_x
                         * as in FP64); the potential's back-transform and the
                         * Vx psi update in split BF16 with FP32 intermediates */
@@ -91,9 +94,7 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
  *   kernel, omega  see above; omega > 0 required for KX_KERNEL_ERFC
  *   batch          number of fields, >= 0 (0 is a no-op)
  *   dtype          storage of rho / phi: KX_F64 or KX_F32
- *   prec           arithmetic of the mode products: KX_PREC_FP64, KX_PREC_FP32,
- *                  KX_PREC_BF16X3 or KX_PREC_MIXED (KX_PREC_FP16X3:
- *                  KX_ERR_UNSUPPORTED).
+ *   prec           arithmetic of the mode products (kx_prec).
  *   rho_dev        batch*N input values;  phi_dev  batch*N outputs (overwritten)
  * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic. */
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
@@ -105,8 +106,8 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
  * updates orbital j and, if i != j, orbital i.  occ_host[norb] are the
  * spin-summed occupations used as literal weights (a closed shell with
  * occ = 2 gives twice the per-spin operator of Eq. (3)).
- *   dtype, prec  as for kx_apply_fL.  With KX_PREC_FP32, KX_PREC_BF16X3 or
- *              KX_PREC_MIXED on KX_F64 storage the orbitals are rounded to
+ *   dtype, prec  as for kx_apply_fL.  With KX_PREC_FP32, KX_PREC_BF16X3,
+ *              KX_PREC_FP16X3 or KX_PREC_MIXED on KX_F64 storage the orbitals are rounded to
  *              FP32 once for the inverse pass and Vx psi is accumulated in
  *              FP32 before it is widened into vxpsi_dev (the handle keeps
  *              8*norb*N bytes of FP32 copies).  KX_PREC_MIXED forms the pair
@@ -143,7 +144,8 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
 
 /* Autotuner: time every launch shape the transform kernels accept for this
  * grid (workgroup z-slabs, staging chunk rows, V blocks in LDS or not,
- * parity split, pencil waves) for precision prec on storage dtype, on
+ * parity split, pencil waves) for precision prec on storage dtype (the
+ * split precisions share one set of shapes, tuned with BF16X3), on
  * synthetic data in batches of `items` pairs (<= 0: the handle's batch size),
  * and keep the fastest per pass for later calls on this handle.
  *   verify      non-zero: also check that every shape gives bitwise the same

@@ -125,6 +125,16 @@ struct kx_grid {
   short* sVO[3] = {nullptr, nullptr, nullptr};
   short* sVET[3] = {nullptr, nullptr, nullptr};
   short* sVOT[3] = {nullptr, nullptr, nullptr};
+  // three-term FP16 splits of 2^12 V (split-FP16 path)
+  short* hVE[3] = {nullptr, nullptr, nullptr};
+  short* hVO[3] = {nullptr, nullptr, nullptr};
+  short* hVET[3] = {nullptr, nullptr, nullptr};
+  short* hVOT[3] = {nullptr, nullptr, nullptr};
+  // split-FP16 scales: per-vector largest magnitudes, per-item result maxima
+  float* dOmax = nullptr;
+  int omax_cap = 0;
+  unsigned* dTmax = nullptr;
+  int tmax_cap = 0;
   // full eigensystem per axis (host), lam ascending, V[i*n + a]
   std::vector<double> lam_host[3];
   std::vector<double> V_host[3];
@@ -239,6 +249,17 @@ EigS eigs_of(const kx_grid* g) {
   return e;
 }
 
+EigS eigh_of(const kx_grid* g) {
+  EigS e;
+  for (int k = 0; k < 3; ++k) {
+    e.E[k] = g->hVE[k];
+    e.O[k] = g->hVO[k];
+    e.ET[k] = g->hVET[k];
+    e.OT[k] = g->hVOT[k];
+  }
+  return e;
+}
+
 // bf16 bit pattern of x, rounded to nearest even (x finite)
 short bf16_rne(double x) {
   const float f = (float)x;
@@ -270,6 +291,24 @@ std::vector<short> split3(const std::vector<double>& a, int n) {
   return out;
 }
 
+// Three FP16 planes of 2^12 a (|a| <= 1 here), rounded to nearest even, with
+// residuals taken in FP64.
+std::vector<short> split3_f16(const std::vector<double>& a, int n) {
+  const size_t m = (size_t)n * n;
+  std::vector<short> out(3 * std::max<size_t>(m, 1), 0);
+  for (size_t i = 0; i < m; ++i) {
+    double r = a[i] * 4096.0;
+    for (int s = 0; s < 3; ++s) {
+      const _Float16 h = (_Float16)r;
+      short b;
+      std::memcpy(&b, &h, sizeof b);
+      out[s * m + i] = b;
+      r -= (double)h;
+    }
+  }
+  return out;
+}
+
 size_t elem_size(int dtype) { return dtype == KX_F64 ? sizeof(double) : sizeof(float); }
 
 bool all_periodic(const kx_grid* g) {
@@ -292,9 +331,9 @@ kx_status check_kernel_args(const kx_grid* g, int kernel, double omega) {
 kx_status check_types(const kx_grid* g, int dtype, int prec) {
   if (dtype != KX_F64 && dtype != KX_F32) return KX_ERR_INVALID_ARG;
   if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED) return KX_ERR_INVALID_ARG;
-  if (prec == KX_PREC_FP16X3) return KX_ERR_UNSUPPORTED;
   if (prec == KX_PREC_MIXED)  // FP64 forward pass, split inverse pass
     return g->plan_d.fwd.ok && g->plan_s.inv.ok ? KX_OK : KX_ERR_UNSUPPORTED;
+  // BF16X3 and FP16X3 share the split kernels' launch shapes
   const Plan& p = prec == KX_PREC_FP64 ? g->plan_d : (prec == KX_PREC_FP32 ? g->plan_f : g->plan_s);
   if (!p.fwd.ok || !p.inv.ok) return KX_ERR_UNSUPPORTED;
   return KX_OK;
@@ -334,6 +373,32 @@ kx_status ensure_workspace(kx_grid* g, int slots) {
   st = dev_alloc((void**)&g->dEpart, sizeof(double) * nstrips * slots);
   if (st != KX_OK) return st;
   g->slots = slots;
+  return KX_OK;
+}
+
+// Scale buffers of the split-FP16 path: nvec per-vector maxima, slots
+// per-item maxima.
+kx_status ensure_aux16(kx_grid* g, int nvec, int slots) {
+  if (nvec > g->omax_cap) {
+    KX_HIP(hipStreamSynchronize(g->stream));
+    ++g->gen;
+    dev_free(g->dOmax);
+    g->dOmax = nullptr;
+    g->omax_cap = 0;
+    kx_status st = dev_alloc((void**)&g->dOmax, sizeof(float) * nvec);
+    if (st != KX_OK) return st;
+    g->omax_cap = nvec;
+  }
+  if (slots > g->tmax_cap) {
+    KX_HIP(hipStreamSynchronize(g->stream));
+    ++g->gen;
+    dev_free(g->dTmax);
+    g->dTmax = nullptr;
+    g->tmax_cap = 0;
+    kx_status st = dev_alloc((void**)&g->dTmax, sizeof(unsigned) * slots);
+    if (st != KX_OK) return st;
+    g->tmax_cap = slots;
+  }
   return KX_OK;
 }
 
@@ -428,15 +493,24 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
       return launch_inverse_d(dtype, mode, G, g->plan_d.inv, E, T, it, nb, psi, occ, dst, st);
     });
   }
-  if (prec == KX_PREC_BF16X3) {
-    const EigS E = eigs_of(g);
+  if (prec == KX_PREC_BF16X3 || prec == KX_PREC_FP16X3) {
+    const bool h16 = prec == KX_PREC_FP16X3;
+    const EigS E = h16 ? eigh_of(g) : eigs_of(g);
+    SplitAux aux;
+    if (h16) {  // the source maxima were computed before the batches
+      aux.h16 = 1;
+      aux.omax = g->dOmax;
+      aux.tmax = g->dTmax;
+      e = launch_zero(g->dTmax, sizeof(unsigned) * nb, st);
+      if (e != hipSuccess) return e;
+    }
     float* T = (float*)g->dT;
     e = timed(g, st, KX_PHASE_FORWARD, [&] {
-      return launch_forward_s(src_dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, st);
+      return launch_forward_s(src_dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, st, aux);
     });
     if (e != hipSuccess) return e;
     e = timed(g, st, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_s(G, g->plan_s.pen, E, g->dF, nb, T, epart, st);
+      return launch_pencil_s(G, g->plan_s.pen, E, g->dF, nb, T, epart, st, aux);
     });
     if (e != hipSuccess) return e;
     if (mode == 1) {
@@ -446,7 +520,8 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
       if (e != hipSuccess) return e;
     }
     return timed(g, st, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, E, T, it, nb, psi, occ, dst, st);
+      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, E, T, it, nb, psi, occ, dst, st,
+                              aux);
     });
   }
   const EigR<float> E = eigf_of(g);
@@ -573,6 +648,10 @@ kx_status prepare_exchange(kx_grid* g, int kernel, double omega, int norb, int d
     st = ensure_t2(g, maxb);
     if (st != KX_OK) return st;
   }
+  if (prec == KX_PREC_FP16X3) {
+    st = ensure_aux16(g, norb, maxb);
+    if (st != KX_OK) return st;
+  }
   st = ensure_ftable(g, kernel, omega);
   if (st != KX_OK) return st;
   st = upload_items(g, 1, norb, cap, g->sched_pairs);
@@ -623,6 +702,10 @@ hipError_t enqueue_exchange(kx_grid* g, const XPlan& xp, hipStream_t s) {
   }
   e = launch_zero(xp.vx_w, elem_size(xp.dtype_w) * xp.nel, s);
   if (e != hipSuccess) return e;
+  if (xp.prec == KX_PREC_FP16X3) {  // the orbitals' largest magnitudes set the FP16 scales
+    e = launch_absmax(xp.psi_w, xp.dtype_w, (long long)g->geom.N, xp.norb, g->dOmax, s);
+    if (e != hipSuccess) return e;
+  }
   for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
     const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
     if (nb <= 0) continue;
@@ -919,9 +1002,12 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
         }
       const std::vector<short> se = split3(ve, pe), set = split3(vet, pe);
       const std::vector<short> so = split3(vo, po), sot = split3(vot, po);
-      short** dst[4] = {&g->sVE[k], &g->sVET[k], &g->sVO[k], &g->sVOT[k]};
-      const std::vector<short>* srcs[4] = {&se, &set, &so, &sot};
-      for (int b = 0; b < 4; ++b) {
+      const std::vector<short> he = split3_f16(ve, pe), het = split3_f16(vet, pe);
+      const std::vector<short> ho = split3_f16(vo, po), hot = split3_f16(vot, po);
+      short** dst[8] = {&g->sVE[k], &g->sVET[k], &g->sVO[k], &g->sVOT[k],
+                        &g->hVE[k], &g->hVET[k], &g->hVO[k], &g->hVOT[k]};
+      const std::vector<short>* srcs[8] = {&se, &set, &so, &sot, &he, &het, &ho, &hot};
+      for (int b = 0; b < 8; ++b) {
         const size_t bytes = sizeof(short) * srcs[b]->size();
         if (dev_alloc((void**)dst[b], bytes) != KX_OK) {
           cleanup();
@@ -1004,7 +1090,13 @@ kx_status kx_destroy(kx_grid* g) {
     dev_free(g->sVO[k]);
     dev_free(g->sVET[k]);
     dev_free(g->sVOT[k]);
+    dev_free(g->hVE[k]);
+    dev_free(g->hVO[k]);
+    dev_free(g->hVET[k]);
+    dev_free(g->hVOT[k]);
   }
+  dev_free(g->dOmax);
+  dev_free(g->dTmax);
   dev_free(g->dF);
   dev_free(g->dT);
   dev_free(g->dT2);
@@ -1048,6 +1140,11 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   for (int b = 0; b < batch; ++b) items[b] = {b, -1};
   st = upload_items(g, 0, batch, chunk, items);
   if (st != KX_OK) return st;
+  if (prec == KX_PREC_FP16X3) {  // the fields' largest magnitudes set the FP16 scales
+    st = ensure_aux16(g, batch, chunk);
+    if (st != KX_OK) return st;
+    KX_HIP(launch_absmax(rho_dev, dtype, (long long)g->geom.N, batch, g->dOmax, g->stream));
+  }
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
     KX_HIP(run_batch(g, g->stream, 0, prec, dtype, rho_dev, g->dItems + b0, nb, dtype, nullptr,
@@ -1158,8 +1255,9 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
     const kx_status st = kx_autotune(g, KX_PREC_FP64, dtype, items, verify, cache_path);
     return st != KX_OK ? st : kx_autotune(g, KX_PREC_BF16X3, dtype, items, verify, cache_path);
   }
+  if (prec == KX_PREC_FP16X3) prec = KX_PREC_BF16X3;  // the same split kernels' shapes
   if (prec != KX_PREC_FP64 && prec != KX_PREC_FP32 && prec != KX_PREC_BF16X3)
-    return prec == KX_PREC_FP16X3 ? KX_ERR_UNSUPPORTED : KX_ERR_INVALID_ARG;
+    return KX_ERR_INVALID_ARG;
   const Geom& G = g->geom;
   // the storage the transform kernels see (reduced precision on FP64 storage
   // runs on FP32 working copies)
@@ -1421,9 +1519,10 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
 
 kx_status kx_get_plan(kx_grid* g, int prec, int* fwd_out, int* pen_out, int* inv_out) {
   if (!g || !fwd_out || !pen_out || !inv_out) return KX_ERR_INVALID_ARG;
-  if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED || prec == KX_PREC_FP16X3)
-    return KX_ERR_INVALID_ARG;
-  Plan p = prec == KX_PREC_FP32 ? g->plan_f : (prec == KX_PREC_BF16X3 ? g->plan_s : g->plan_d);
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED) return KX_ERR_INVALID_ARG;
+  Plan p = prec == KX_PREC_FP32
+               ? g->plan_f
+               : ((prec == KX_PREC_BF16X3 || prec == KX_PREC_FP16X3) ? g->plan_s : g->plan_d);
   if (prec == KX_PREC_MIXED) p.inv = g->plan_s.inv;
   const int f[6] = {p.fwd.qsplit, p.fwd.slabs, p.fwd.waves, p.fwd.kc, p.fwd.vlds ? 1 : 0,
                     (int)p.fwd.lds_bytes};

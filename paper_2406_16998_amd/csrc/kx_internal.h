@@ -187,14 +187,28 @@ hipError_t launch_inverse_f(int storage, int mode, const Geom& g, const SlabPlan
                             const void* psi, const double* occ, void* dst, hipStream_t s);
 // ---- split-BF16 transform kernels (kx_split.hip): FP32 intermediates T
 Plan make_split_plan(const Geom& g, size_t max_lds);
+// Split-FP16 instead of split-BF16 (h16): the per-vector largest magnitudes
+// of the forward pass's sources (omax, count of vectors) and the per-item
+// largest magnitudes of the pencil's result (tmax, float bits, cleared to
+// zero before the pencil launch) set the operands' power-of-two scales.
+struct SplitAux {
+  int h16 = 0;
+  const float* omax = nullptr;
+  unsigned* tmax = nullptr;
+};
 hipError_t launch_forward_s(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigS& e, const void* src, const Item* items, int nitems,
-                            float* T, hipStream_t s);
+                            float* T, hipStream_t s, const SplitAux& aux = SplitAux());
 hipError_t launch_pencil_s(const Geom& g, const PencilPlan& p, const EigS& e, const double* F,
-                           int nitems, float* T, double* epart, hipStream_t s);
+                           int nitems, float* T, double* epart, hipStream_t s,
+                           const SplitAux& aux = SplitAux());
 hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigS& e, const float* T, const Item* items, int nitems,
-                            const void* psi, const double* occ, void* dst, hipStream_t s);
+                            const void* psi, const double* occ, void* dst, hipStream_t s,
+                            const SplitAux& aux = SplitAux());
+// out[v] = max |x[v n .. v n + n)| for v < count (storage KX_F64 or KX_F32)
+hipError_t launch_absmax(const void* x, int storage, long long n, int count, float* out,
+                         hipStream_t s);
 // zero `bytes` (a multiple of 4, 4-byte aligned) with a kernel, so that the
 // clearing can be recorded into a graph
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -46,22 +46,70 @@ __device__ __forceinline__ float bf16_value(short s) {
   return __builtin_bit_cast(float, (unsigned)(unsigned short)s << 16);
 }
 
-__device__ __forceinline__ Split4 split4(float v0, float v1, float v2, float v3) {
+// The 16-bit type of the split terms.  BF16: 8-bit significands, FP32's
+// exponent range, no scaling.  FP16: 11-bit significands and a 5-bit
+// exponent, so the operands are brought into range by powers of two: the V
+// blocks by 2^12 at set-up (|V| <= 1), every data operand by a power of two
+// that puts its largest magnitude in [2^13, 2^14) (per item where the data
+// are staged in chunks, per wave where the whole contraction range is in
+// registers); the products are scaled back exactly.
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+struct BF16 {
+  static constexpr bool kScaled = false;
+  static constexpr float kVScale = 1.f;
+  static __device__ __forceinline__ short bits(float x) { return bf16_bits(x); }
+  static __device__ __forceinline__ float value(short b) { return bf16_value(b); }
+  static __device__ __forceinline__ f4 mma(s4 a, s4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+struct F16 {
+  static constexpr bool kScaled = true;
+  static constexpr float kVScale = 4096.f;  // 2^12, the V blocks' scale
+  static __device__ __forceinline__ short bits(float x) {
+    return __builtin_bit_cast(short, (_Float16)x);  // round to nearest even
+  }
+  static __device__ __forceinline__ float value(short b) {
+    return (float)__builtin_bit_cast(_Float16, b);
+  }
+  static __device__ __forceinline__ f4 mma(s4 a, s4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a),
+                                                 __builtin_bit_cast(h4, b), c, 0, 0, 0);
+  }
+};
+
+// x ~ x0 + x1 + x2, x0 = h(x), x1 = h(x - x0), x2 = h(x - x0 - x1); the
+// residuals are exact in FP32.  sc: the operand's power-of-two scale (FP16).
+template <class H>
+__device__ __forceinline__ Split4 split4(float v0, float v1, float v2, float v3, float sc = 1.f) {
   Split4 o;
   const float v[4] = {v0, v1, v2, v3};
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    float r = v[e];
-    const short a = bf16_bits(r);
-    r -= bf16_value(a);
-    const short b = bf16_bits(r);
-    r -= bf16_value(b);
-    const short c = bf16_bits(r);
+    float r = H::kScaled ? v[e] * sc : v[e];
+    const short a = H::bits(r);
+    r -= H::value(a);
+    const short b = H::bits(r);
+    r -= H::value(b);
+    const short c = H::bits(r);
     o.h[0][e] = a;
     o.h[1][e] = b;
     o.h[2][e] = c;
   }
   return o;
+}
+
+// 2^k with m 2^k in [2^13, 2^14); 1 when m is zero or not finite
+__device__ __forceinline__ float pow2_scale(float m) {
+  if (!(m > 0.f) || !(m <= 3.0e38f)) return 1.f;
+  int ex;
+  (void)frexpf(m, &ex);  // m = f 2^ex, f in [0.5, 1)
+  return ldexpf(1.f, 14 - ex);
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
 }
 
 __device__ __forceinline__ Split4 load_split(const short* __restrict__ p, int plane_stride) {
@@ -72,14 +120,25 @@ __device__ __forceinline__ Split4 load_split(const short* __restrict__ p, int pl
   return o;
 }
 
+template <class H>
 __device__ __forceinline__ f4 mma6(const Split4& a, const Split4& b, f4 c) {
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[2], b.h[0], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[1], b.h[1], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[0], b.h[2], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[1], b.h[0], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[0], b.h[1], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h[0], b.h[0], c, 0, 0, 0);
+  c = H::mma(a.h[2], b.h[0], c);
+  c = H::mma(a.h[1], b.h[1], c);
+  c = H::mma(a.h[0], b.h[2], c);
+  c = H::mma(a.h[1], b.h[0], c);
+  c = H::mma(a.h[0], b.h[1], c);
+  c = H::mma(a.h[0], b.h[0], c);
   return c;
+}
+// largest magnitude over a wave's accumulator tiles
+template <int N>
+__device__ __forceinline__ float tiles_absmax(const f4* t) {
+  float m = 0.f;
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(t[k][r]));
+  return wave_max(m);
 }
 
 constexpr f4 kZ = {0.f, 0.f, 0.f, 0.f};
@@ -88,28 +147,28 @@ constexpr int kSplitKc = 16; // staged K rows per chunk: one MFMA k-step
 extern __shared__ __align__(16) float kx_split_lds[];
 
 // ================================================================ forward
-template <int NTQ>
+template <class H, int NTQ>
 __device__ __forceinline__ void sf_k_step(f4* acc1, const float* __restrict__ arow, int wrow,
-                                          const Split4& b) {
+                                          const Split4& b, float sc) {
   // A slot (lg, e) = S[k0 + 4 lg + e][16 t + li]: arow points at row k0 + 4 lg
 #pragma unroll
   for (int t = 0; t < NTQ; ++t) {
     const float* a = arow + kTile * t;
-    acc1[t] = mma6(split4(a[0], a[wrow], a[2 * wrow], a[3 * wrow]), b, acc1[t]);
+    acc1[t] = mma6<H>(split4<H>(a[0], a[wrow], a[2 * wrow], a[3 * wrow], sc), b, acc1[t]);
   }
 }
 
-template <int NTQ>
+template <class H, int NTQ>
 __device__ __forceinline__ void sf_mode1(const f4* acc1, f4* acc2, const short* __restrict__ V1qT,
-                                         int ldq, int pstride, int lg, int li) {
+                                         int ldq, int pstride, int lg, int li, float sc) {
   // A[m = a][k = x'] = V1q[x'][a] = V1qT[a][x'];  B = split(acc1[t])
 #pragma unroll
   for (int t = 0; t < NTQ; ++t) {
-    const Split4 b = split4(acc1[t][0], acc1[t][1], acc1[t][2], acc1[t][3]);
+    const Split4 b = split4<H>(acc1[t][0], acc1[t][1], acc1[t][2], acc1[t][3], sc);
 #pragma unroll
     for (int u = 0; u < NTQ; ++u) {
       const Split4 a = load_split(V1qT + (kTile * u + li) * ldq + kTile * t + 4 * lg, pstride);
-      acc2[u] = mma6(a, b, acc2[u]);
+      acc2[u] = mma6<H>(a, b, acc2[u]);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -129,10 +188,11 @@ __device__ __forceinline__ void sf_store(const f4* acc2, float* __restrict__ Tzb
 // chunks of kc (a multiple of 16).
 // XST: some staged positions exceed the register budget (grids whose x
 // extent is large against y) and are loaded directly in the stash step.
-template <class S, int NT, bool OFULL, int MODE, bool XST, int MT>
+// omax (FP16): largest magnitude of each source vector (orbital or field).
+template <class H, class S, int NT, bool OFULL, int MODE, bool XST, int MT>
 __global__ void __launch_bounds__(MT, fwd_min_waves(NT))
 split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict__ items,
-              float* __restrict__ T, int slabs, int kc, int qsplit) {
+              float* __restrict__ T, int slabs, int kc, int qsplit, const float* __restrict__ omax) {
   float* lds = kx_split_lds;
   const int tid = threadIdx.x;
   const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
@@ -233,6 +293,11 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
   const int ldp = p == 0 ? g.pe2 : g.po2;
   const int pst2 = ldp * ldp;
 
+  // FP16: the folded products are bounded by four times the product of the
+  // two vectors' largest magnitudes
+  float sc1 = 1.f;
+  if (H::kScaled)
+    sc1 = pow2_scale(4.f * omax[item.i] * (MODE == 1 ? omax[item.j] : 1.f));
   f4 acc1[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc1[t] = kZ;
@@ -249,9 +314,9 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
       const Split4 b = load_split(V2pT + (b0 + li) * ldp + y0 + kk + 4 * lg, pst2);
       const float* __restrict__ arow = cur + (p * kc + kk + 4 * lg) * wrow + qcol(q) + li;
       if (qfull)
-        sf_k_step<NT>(acc1, arow, wrow, b);
+        sf_k_step<H, NT>(acc1, arow, wrow, b, sc1);
       else
-        sf_k_step<NTO>(acc1, arow, wrow, b);
+        sf_k_step<H, NTO>(acc1, arow, wrow, b, sc1);
       __builtin_amdgcn_sched_barrier(0);
     }
     if (c + 1 < nchunks) stash(sb + ((c + 1) & 1) * celems, (c + 1) * kc);
@@ -263,10 +328,24 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
   f4 acc2[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) acc2[u] = kZ;
+  // FP16: acc1 carries 2^12 sc1; its B operand is rescaled per wave
+  float m2 = 1.f, un2 = 1.f;
+  if (H::kScaled) {
+    const float un1 = 1.f / (H::kVScale * sc1);
+    const float sc2 = pow2_scale(tiles_absmax<NT>(acc1) * un1);
+    m2 = un1 * sc2;
+    un2 = 1.f / (H::kVScale * sc2);
+  }
   if (qfull)
-    sf_mode1<NT>(acc1, acc2, V1qT, ldq, ldq * ldq, lg, li);
+    sf_mode1<H, NT>(acc1, acc2, V1qT, ldq, ldq * ldq, lg, li, m2);
   else
-    sf_mode1<NTO>(acc1, acc2, V1qT, ldq, ldq * ldq, lg, li);
+    sf_mode1<H, NTO>(acc1, acc2, V1qT, ldq, ldq * ldq, lg, li, m2);
+  if (H::kScaled) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc2[u][r] *= un2;
+  }
   if (!zin) return;
   const int aoff = q == 0 ? 0 : g.pe1, boff = p == 0 ? 0 : g.pe2;
   float* __restrict__ Tzb =
@@ -278,10 +357,12 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
 }
 
 // ================================================================ pencil
-template <int NT, bool OFULL, int MT>
+// tmax (FP16): per item, the largest magnitude of the result (float bits,
+// raised with atomic maxima; zero before the launch).
+template <class H, int NT, bool OFULL, int MT>
 __global__ void __launch_bounds__(MT)
 split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T,
-             double* __restrict__ epart) {
+             double* __restrict__ epart, unsigned* __restrict__ tmax) {
   constexpr int NTE = NT, NTO = OFULL ? NT : NT - 1;
   const int tid = threadIdx.x;
   const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
@@ -298,21 +379,45 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
 
   // folded column values, k-step t (z' = 16 t + 4 lg + e)
   Split4 be[NT], bo[NT];
+  float sc3 = 1.f;
+  if constexpr (H::kScaled) {  // FP16: one scale for the wave's folded columns
+    float ce[NT][4], co[NT][4], m = 0.f;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    float ce[4], co[4];
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int ee = 0; ee < 4; ++ee) {
-      const int zp = kTile * t + 4 * lg + ee;
-      const bool ie = qin && zp < g.me3, io = qin && zp < g.mo3;
-      const float a = ie ? Tb[(unsigned)zp * slab + li] : 0.f;
-      const float m = io ? Tb[(unsigned)(g.n3 - 1 - zp) * slab + li] : 0.f;
-      ce[ee] = a + m;
-      co[ee] = io ? a - m : 0.f;
+      for (int ee = 0; ee < 4; ++ee) {
+        const int zp = kTile * t + 4 * lg + ee;
+        const bool ie = qin && zp < g.me3, io = qin && zp < g.mo3;
+        const float a = ie ? Tb[(unsigned)zp * slab + li] : 0.f;
+        const float mm = io ? Tb[(unsigned)(g.n3 - 1 - zp) * slab + li] : 0.f;
+        ce[t][ee] = a + mm;
+        co[t][ee] = io ? a - mm : 0.f;
+        m = fmaxf(m, fmaxf(fabsf(ce[t][ee]), fabsf(co[t][ee])));
+      }
+    sc3 = pow2_scale(wave_max(m));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      be[t] = split4<H>(ce[t][0], ce[t][1], ce[t][2], ce[t][3], sc3);
+      bo[t] = split4<H>(co[t][0], co[t][1], co[t][2], co[t][3], sc3);
     }
-    be[t] = split4(ce[0], ce[1], ce[2], ce[3]);
-    bo[t] = split4(co[0], co[1], co[2], co[3]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float ce[4], co[4];
+#pragma unroll
+      for (int ee = 0; ee < 4; ++ee) {
+        const int zp = kTile * t + 4 * lg + ee;
+        const bool ie = qin && zp < g.me3, io = qin && zp < g.mo3;
+        const float a = ie ? Tb[(unsigned)zp * slab + li] : 0.f;
+        const float m = io ? Tb[(unsigned)(g.n3 - 1 - zp) * slab + li] : 0.f;
+        ce[ee] = a + m;
+        co[ee] = io ? a - m : 0.f;
+      }
+      be[t] = split4<H>(ce[0], ce[1], ce[2], ce[3]);
+      bo[t] = split4<H>(co[0], co[1], co[2], co[3]);
+    }
   }
+  const float un3 = 1.f / (H::kVScale * sc3);
 
   // mode 3 (folded):  C[c][q] += A[c][z'] B[z'][q],  A[c][z'] = V3p[z'][c] = V3pT[c][z']
   f4 accE[NT], accO[NT];
@@ -326,13 +431,13 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
 #pragma unroll
     for (int t = 0; t < NTE; ++t) {
       const Split4 a = load_split(e.ET[2] + (kTile * t + li) * pe + kTile * k + 4 * lg, pe * pe);
-      accE[t] = mma6(a, be[k], accE[t]);
+      accE[t] = mma6<H>(a, be[k], accE[t]);
     }
     if (k < NTO) {
 #pragma unroll
       for (int t = 0; t < NTO; ++t) {
         const Split4 a = load_split(e.OT[2] + (kTile * t + li) * po + kTile * k + 4 * lg, po * po);
-        accO[t] = mma6(a, bo[k], accO[t]);
+        accO[t] = mma6<H>(a, bo[k], accO[t]);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -348,18 +453,22 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
       const int c = kTile * t + 4 * lg + r;
       {
         const double f = qin ? Fq[(unsigned)c * slab + li] : 0.0;
-        const double v = accE[t][r];
+        const double v = H::kScaled ? (double)(accE[t][r] * un3) : (double)accE[t][r];
         esum += f * v * v;
         accE[t][r] = (float)(f * v);
       }
       if (t < NTO) {
         const double f = qin ? Fq[(unsigned)(pe + c) * slab + li] : 0.0;
-        const double v = accO[t][r];
+        const double v = H::kScaled ? (double)(accO[t][r] * un3) : (double)accO[t][r];
         esum += f * v * v;
         accO[t][r] = (float)(f * v);
       }
     }
   }
+  // FP16: one scale for the wave's scaled coefficients
+  float sc4 = 1.f;
+  if (H::kScaled) sc4 = pow2_scale(fmaxf(tiles_absmax<NT>(accE), tiles_absmax<NT>(accO)));
+  const float un4 = 1.f / (H::kVScale * sc4);
 
   // inverse mode 3 (folded):  C[z'][q] += A[z'][c] B[c][q],  A = V3p (rows z', k = c)
   f4 outE[NT], outO[NT];
@@ -371,35 +480,41 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     {
-      const Split4 b = split4(accE[t][0], accE[t][1], accE[t][2], accE[t][3]);
+      const Split4 b = split4<H>(accE[t][0], accE[t][1], accE[t][2], accE[t][3], sc4);
 #pragma unroll
       for (int u = 0; u < NTE; ++u) {
         const Split4 a = load_split(e.E[2] + (kTile * u + li) * pe + kTile * t + 4 * lg, pe * pe);
-        outE[u] = mma6(a, b, outE[u]);
+        outE[u] = mma6<H>(a, b, outE[u]);
       }
     }
     if (t < NTO) {
-      const Split4 b = split4(accO[t][0], accO[t][1], accO[t][2], accO[t][3]);
+      const Split4 b = split4<H>(accO[t][0], accO[t][1], accO[t][2], accO[t][3], sc4);
 #pragma unroll
       for (int u = 0; u < NTO; ++u) {
         const Split4 a = load_split(e.O[2] + (kTile * u + li) * po + kTile * t + 4 * lg, po * po);
-        outO[u] = mma6(a, b, outO[u]);
+        outO[u] = mma6<H>(a, b, outO[u]);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+  float tm = 0.f;
   if (qin) {
 #pragma unroll
     for (int u = 0; u < NTE; ++u) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int zp = kTile * u + 4 * lg + r;
-        const float P = outE[u][r];
-        const float Q = (u < NTO) ? outO[u][r] : 0.f;
+        const float P = H::kScaled ? outE[u][r] * un4 : outE[u][r];
+        const float Q = (u < NTO) ? (H::kScaled ? outO[u][r] * un4 : outO[u][r]) : 0.f;
         if (zp < g.me3) Tb[(unsigned)zp * slab + li] = P + Q;
         if (zp < g.mo3) Tb[(unsigned)(g.n3 - 1 - zp) * slab + li] = P - Q;
+        if (H::kScaled) tm = fmaxf(tm, fmaxf(fabsf(P + Q), fabsf(P - Q)));
       }
     }
+  }
+  if (H::kScaled) {  // vector atomic maximum of non-negative float bits
+    tm = wave_max(tm);
+    if (lane == 0 && tm > 0.f) atomicMax(tmax + it, __builtin_bit_cast(unsigned, tm));
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o);
@@ -408,25 +523,25 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
 
 // ================================================================ inverse
 // acc1 layout [q][p][t] flattened as acc1[(q * 2 + p) * NT + t]
-template <int NT, int NTO>
+template <class H, int NT, int NTO>
 __device__ __forceinline__ void si_k_step(f4* acc1q, const float* __restrict__ arow, int p2,
-                                          int pe2, const Split4& b) {
+                                          int pe2, const Split4& b, float sc) {
   // A[m = b][k = a'] = T2[a'][b]: arow points at staged row k0 + 4 lg, column li
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const float* a = arow + kTile * t;
-    acc1q[t] = mma6(split4(a[0], a[p2], a[2 * p2], a[3 * p2]), b, acc1q[t]);
+    acc1q[t] = mma6<H>(split4<H>(a[0], a[p2], a[2 * p2], a[3 * p2], sc), b, acc1q[t]);
   }
 #pragma unroll
   for (int t = 0; t < NTO; ++t) {
     const float* a = arow + pe2 + kTile * t;
-    acc1q[NT + t] = mma6(split4(a[0], a[p2], a[2 * p2], a[3 * p2]), b, acc1q[NT + t]);
+    acc1q[NT + t] = mma6<H>(split4<H>(a[0], a[p2], a[2 * p2], a[3 * p2], sc), b, acc1q[NT + t]);
   }
 }
 
 // lde / ldo: row strides of the even / odd V2 blocks (in global memory or
 // LDS), pse / pso: their plane strides.
-template <int NT, int NTO, bool HASO>
+template <class H, int NT, int NTO, bool HASO>
 __device__ __forceinline__ void si_mode2(const Split4* bs, f4* Q, int u, const short* __restrict__ VE2,
                                          const short* __restrict__ VO2, int lde, int ldo, int pse,
                                          int pso, int lg, int li) {
@@ -436,22 +551,23 @@ __device__ __forceinline__ void si_mode2(const Split4* bs, f4* Q, int u, const s
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const Split4 a = load_split(VE2 + (kTile * u + li) * lde + kTile * t + 4 * lg, pse);
-    Q[0] = mma6(a, bs[(0 * 2 + 0) * NT + t], Q[0]);
-    if (HASO) Q[1] = mma6(a, bs[(1 * 2 + 0) * NT + t], Q[1]);
+    Q[0] = mma6<H>(a, bs[(0 * 2 + 0) * NT + t], Q[0]);
+    if (HASO) Q[1] = mma6<H>(a, bs[(1 * 2 + 0) * NT + t], Q[1]);
     if (t < NTO && u < NTO) {
       const Split4 ao = load_split(VO2 + (kTile * u + li) * ldo + kTile * t + 4 * lg, pso);
-      Q[2] = mma6(ao, bs[(0 * 2 + 1) * NT + t], Q[2]);
-      if (HASO) Q[3] = mma6(ao, bs[(1 * 2 + 1) * NT + t], Q[3]);
+      Q[2] = mma6<H>(ao, bs[(0 * 2 + 1) * NT + t], Q[2]);
+      if (HASO) Q[3] = mma6<H>(ao, bs[(1 * 2 + 1) * NT + t], Q[3]);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-template <class S, int NT, bool OFULL, int MODE, bool VL, int MT>
+// tmax (FP16): per item, the largest magnitude of T (float bits).
+template <class H, class S, int NT, bool OFULL, int MODE, bool VL, int MT>
 __global__ void __launch_bounds__(MT)
 split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restrict__ items,
               const S* __restrict__ psi, const double* __restrict__ occ, S* __restrict__ dst,
-              int slabs, int kc) {
+              int slabs, int kc, const unsigned* __restrict__ tmax) {
   constexpr int NTO = OFULL ? NT : NT - 1;
   // LDS: [pre-split V2 blocks, rows padded (VL)] [slabs][staged chunks / phi plane]
   short* __restrict__ vE = reinterpret_cast<short*>(kx_split_lds);
@@ -510,6 +626,8 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
     be_n = load_split(e.E[0] + xp * g.pe1 + a0 + 4 * lg, g.pe1 * g.pe1);
     if (has_o && a0 < g.po1) bo_n = load_split(e.O[0] + xp * g.po1 + a0 + 4 * lg, g.po1 * g.po1);
   };
+  float sc5 = 1.f;  // FP16: one scale for the item's T
+  if (H::kScaled) sc5 = pow2_scale(__builtin_bit_cast(float, tmax[blockIdx.y]));
   load_b(0);
   issue(sb, 0);
   __builtin_amdgcn_s_waitcnt(0);
@@ -522,15 +640,25 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
       load_b(a0 + kc);
       issue(sb + ((c + 1) & 1) * celems, a0 + kc);
     }
-    si_k_step<NT, NTO>(acc1, cur + 4 * lg * p2 + li, p2, pe2, be);
-    if (has_o && a0 < g.po1) si_k_step<NT, NTO>(acc1 + 2 * NT, cur + (kc + 4 * lg) * p2 + li, p2, pe2, bo);
+    si_k_step<H, NT, NTO>(acc1, cur + 4 * lg * p2 + li, p2, pe2, be, sc5);
+    if (has_o && a0 < g.po1)
+      si_k_step<H, NT, NTO>(acc1 + 2 * NT, cur + (kc + 4 * lg) * p2 + li, p2, pe2, bo, sc5);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
   // split the W tiles once; they are the B operands of every y' tile
+  // (FP16: acc1 carries 2^12 sc5 and is rescaled per wave)
+  float m6 = 1.f, un6 = 1.f;
+  if (H::kScaled) {
+    const float un5 = 1.f / (H::kVScale * sc5);
+    const float sc6 = pow2_scale(tiles_absmax<4 * NT>(acc1) * un5);
+    m6 = un5 * sc6;
+    un6 = 1.f / (H::kVScale * sc6);
+  }
   Split4 bs[4 * NT];
 #pragma unroll
-  for (int k = 0; k < 4 * NT; ++k) bs[k] = split4(acc1[k][0], acc1[k][1], acc1[k][2], acc1[k][3]);
+  for (int k = 0; k < 4 * NT; ++k)
+    bs[k] = split4<H>(acc1[k][0], acc1[k][1], acc1[k][2], acc1[k][3], m6);
 
   const bool xin = zin && xp < g.me1;
   const long long zoff = (long long)(zin ? z : 0) * g.n1 * g.n2;
@@ -552,9 +680,15 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
     const short* VO2 = VL ? vO : e.O[1];
     const int lde = VL ? sinv_ld(pe2) : pe2, ldo = VL ? sinv_ld(po2) : po2;
     if (has_o)
-      si_mode2<NT, NTO, true>(bs, Q, u, VE2, VO2, lde, ldo, pe2 * lde, po2 * ldo, lg, li);
+      si_mode2<H, NT, NTO, true>(bs, Q, u, VE2, VO2, lde, ldo, pe2 * lde, po2 * ldo, lg, li);
     else
-      si_mode2<NT, NTO, false>(bs, Q, u, VE2, VO2, lde, ldo, pe2 * lde, po2 * ldo, lg, li);
+      si_mode2<H, NT, NTO, false>(bs, Q, u, VE2, VO2, lde, ldo, pe2 * lde, po2 * ldo, lg, li);
+    if (H::kScaled) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Q[k][r] *= un6;
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float ee = Q[0][r], eo = has_o ? Q[1][r] : 0.f;
@@ -580,9 +714,10 @@ void allow_lds(K kernel, size_t lds) {
 
 #define KX_NT_CASES(MACRO) MACRO(1) MACRO(2) MACRO(3) MACRO(4) MACRO(5)
 
-template <class S>
+template <class H, class S>
 hipError_t sfwd_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e, const S* src,
-                       const Item* items, int nitems, float* T, hipStream_t st) {
+                       const Item* items, int nitems, float* T, const float* omax,
+                       hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   const dim3 grid((g.n3 + p.slabs - 1) / p.slabs, nitems, p.qsplit);
   const dim3 block(64 * p.waves);
@@ -594,16 +729,17 @@ hipError_t sfwd_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e
 #define KX_CASE(NT)                                                                          \
   case NT: {                                                                                 \
     constexpr int MT = fwd_mt(NT);                                                           \
-    auto k = xst ? (mode == 1 ? (of ? split_forward<S, NT, true, 1, true, MT>                  \
-                                    : split_forward<S, NT, false, 1, true, MT>)                \
-                              : (of ? split_forward<S, NT, true, 0, true, MT>                  \
-                                    : split_forward<S, NT, false, 0, true, MT>))               \
-                 : (mode == 1 ? (of ? split_forward<S, NT, true, 1, false, MT>                 \
-                                    : split_forward<S, NT, false, 1, false, MT>)               \
-                              : (of ? split_forward<S, NT, true, 0, false, MT>                 \
-                                    : split_forward<S, NT, false, 0, false, MT>));             \
+    auto k = xst ? (mode == 1 ? (of ? split_forward<H, S, NT, true, 1, true, MT>                  \
+                                    : split_forward<H, S, NT, false, 1, true, MT>)                \
+                              : (of ? split_forward<H, S, NT, true, 0, true, MT>                  \
+                                    : split_forward<H, S, NT, false, 0, true, MT>))               \
+                 : (mode == 1 ? (of ? split_forward<H, S, NT, true, 1, false, MT>                 \
+                                    : split_forward<H, S, NT, false, 1, false, MT>)               \
+                              : (of ? split_forward<H, S, NT, true, 0, false, MT>                 \
+                                    : split_forward<H, S, NT, false, 0, false, MT>));             \
     allow_lds(k, lb);                                                                        \
-    hipLaunchKernelGGL(k, grid, block, lb, st, g, e, src, items, T, p.slabs, p.kc, p.qsplit); \
+    hipLaunchKernelGGL(k, grid, block, lb, st, g, e, src, items, T, p.slabs, p.kc, p.qsplit, \
+                       omax);                                                                \
     break;                                                                                   \
   }
     KX_NT_CASES(KX_CASE)
@@ -614,8 +750,9 @@ hipError_t sfwd_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e
   return hipGetLastError();
 }
 
+template <class H>
 hipError_t spen_launch(const Geom& g, const PencilPlan& p, const EigS& e, const double* F,
-                       int nitems, float* T, double* epart, hipStream_t st) {
+                       int nitems, float* T, double* epart, unsigned* tmax, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   const long long nstrips = g.slab / kTile;
   const int w = p.waves;
@@ -626,8 +763,8 @@ hipError_t spen_launch(const Geom& g, const PencilPlan& p, const EigS& e, const 
 #define KX_CASE(NT)                                                                      \
   case NT: {                                                                             \
     constexpr int MT = pen_mt(NT);                                                       \
-    auto k = of ? split_pencil<NT, true, MT> : split_pencil<NT, false, MT>;              \
-    hipLaunchKernelGGL(k, grid, block, 0, st, g, e, F, T, epart);                        \
+    auto k = of ? split_pencil<H, NT, true, MT> : split_pencil<H, NT, false, MT>;        \
+    hipLaunchKernelGGL(k, grid, block, 0, st, g, e, F, T, epart, tmax);                  \
     break;                                                                               \
   }
     KX_NT_CASES(KX_CASE)
@@ -638,10 +775,10 @@ hipError_t spen_launch(const Geom& g, const PencilPlan& p, const EigS& e, const 
   return hipGetLastError();
 }
 
-template <class S>
+template <class H, class S>
 hipError_t sinv_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e, const float* T,
                        const Item* items, int nitems, const S* psi, const double* occ, S* dst,
-                       hipStream_t st) {
+                       const unsigned* tmax, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (p.kc != kTile) return hipErrorInvalidValue;  // chunks are exactly one k-step
   const dim3 grid((g.n3 + p.slabs - 1) / p.slabs, nitems);
@@ -652,13 +789,14 @@ hipError_t sinv_launch(int mode, const Geom& g, const SlabPlan& p, const EigS& e
 #define KX_CASE(NT)                                                                         \
   case NT: {                                                                                \
     constexpr int MT = inv_mt(NT);                                                          \
-    auto k = mode == 1 ? (of ? split_inverse<S, NT, true, 1, false, MT> : split_inverse<S, NT, false, 1, false, MT>) \
-                       : (of ? split_inverse<S, NT, true, 0, false, MT> : split_inverse<S, NT, false, 0, false, MT>); \
+    auto k = mode == 1 ? (of ? split_inverse<H, S, NT, true, 1, false, MT> : split_inverse<H, S, NT, false, 1, false, MT>) \
+                       : (of ? split_inverse<H, S, NT, true, 0, false, MT> : split_inverse<H, S, NT, false, 0, false, MT>); \
     if (p.vlds)                                                                             \
-      k = mode == 1 ? (of ? split_inverse<S, NT, true, 1, true, MT> : split_inverse<S, NT, false, 1, true, MT>) \
-                    : (of ? split_inverse<S, NT, true, 0, true, MT> : split_inverse<S, NT, false, 0, true, MT>); \
+      k = mode == 1 ? (of ? split_inverse<H, S, NT, true, 1, true, MT> : split_inverse<H, S, NT, false, 1, true, MT>) \
+                    : (of ? split_inverse<H, S, NT, true, 0, true, MT> : split_inverse<H, S, NT, false, 0, true, MT>); \
     allow_lds(k, lb);                                                                       \
-    hipLaunchKernelGGL(k, grid, block, lb, st, g, e, T, items, psi, occ, dst, p.slabs, p.kc); \
+    hipLaunchKernelGGL(k, grid, block, lb, st, g, e, T, items, psi, occ, dst, p.slabs, p.kc, \
+                       tmax);                                                               \
     break;                                                                                  \
   }
     KX_NT_CASES(KX_CASE)
@@ -694,25 +832,66 @@ Plan make_split_plan(const Geom& g, size_t max_lds) {
 
 hipError_t launch_forward_s(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigS& e, const void* src, const Item* items, int nitems,
-                            float* T, hipStream_t s) {
-  return storage == KX_F64
-             ? sfwd_launch<double>(mode, g, p, e, (const double*)src, items, nitems, T, s)
-             : sfwd_launch<float>(mode, g, p, e, (const float*)src, items, nitems, T, s);
+                            float* T, hipStream_t s, const SplitAux& aux) {
+  if (aux.h16 && !aux.omax) return hipErrorInvalidValue;
+  if (storage == KX_F64)
+    return aux.h16 ? sfwd_launch<F16, double>(mode, g, p, e, (const double*)src, items, nitems, T,
+                                              aux.omax, s)
+                   : sfwd_launch<BF16, double>(mode, g, p, e, (const double*)src, items, nitems,
+                                               T, nullptr, s);
+  return aux.h16 ? sfwd_launch<F16, float>(mode, g, p, e, (const float*)src, items, nitems, T,
+                                           aux.omax, s)
+                 : sfwd_launch<BF16, float>(mode, g, p, e, (const float*)src, items, nitems, T,
+                                            nullptr, s);
 }
 
 hipError_t launch_pencil_s(const Geom& g, const PencilPlan& p, const EigS& e, const double* F,
-                           int nitems, float* T, double* epart, hipStream_t s) {
-  return spen_launch(g, p, e, F, nitems, T, epart, s);
+                           int nitems, float* T, double* epart, hipStream_t s,
+                           const SplitAux& aux) {
+  if (aux.h16 && !aux.tmax) return hipErrorInvalidValue;
+  return aux.h16 ? spen_launch<F16>(g, p, e, F, nitems, T, epart, aux.tmax, s)
+                 : spen_launch<BF16>(g, p, e, F, nitems, T, epart, nullptr, s);
 }
 
 hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigS& e, const float* T, const Item* items, int nitems,
-                            const void* psi, const double* occ, void* dst, hipStream_t s) {
-  return storage == KX_F64
-             ? sinv_launch<double>(mode, g, p, e, T, items, nitems, (const double*)psi, occ,
-                                   (double*)dst, s)
-             : sinv_launch<float>(mode, g, p, e, T, items, nitems, (const float*)psi, occ,
-                                  (float*)dst, s);
+                            const void* psi, const double* occ, void* dst, hipStream_t s,
+                            const SplitAux& aux) {
+  if (aux.h16 && !aux.tmax) return hipErrorInvalidValue;
+  if (storage == KX_F64)
+    return aux.h16 ? sinv_launch<F16, double>(mode, g, p, e, T, items, nitems,
+                                              (const double*)psi, occ, (double*)dst, aux.tmax, s)
+                   : sinv_launch<BF16, double>(mode, g, p, e, T, items, nitems,
+                                               (const double*)psi, occ, (double*)dst, nullptr, s);
+  return aux.h16 ? sinv_launch<F16, float>(mode, g, p, e, T, items, nitems, (const float*)psi,
+                                           occ, (float*)dst, aux.tmax, s)
+                 : sinv_launch<BF16, float>(mode, g, p, e, T, items, nitems, (const float*)psi,
+                                            occ, (float*)dst, nullptr, s);
+}
+
+namespace {
+__global__ void __launch_bounds__(256) absmax_kernel(const void* x, int f64, long long n, float* out) {
+  // one workgroup per vector
+  const long long base = (long long)blockIdx.x * n;
+  float m = 0.f;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const float v = f64 ? (float)fabs(((const double*)x)[base + i]) : fabsf(((const float*)x)[base + i]);
+    m = fmaxf(m, v);
+  }
+  m = wave_max(m);
+  __shared__ float red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+}  // namespace
+
+hipError_t launch_absmax(const void* x, int storage, long long n, int count, float* out,
+                         hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(absmax_kernel, dim3(count), dim3(256), 0, s, x, storage == KX_F64 ? 1 : 0, n,
+                     out);
+  return hipGetLastError();
 }
 
 }  // namespace kx

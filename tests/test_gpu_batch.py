@@ -63,7 +63,7 @@ def test_batch_matches_oracle_fp64(systems):
             assert _rel(vx[j], vx_ref[j]) <= TOL64, (w.name, j)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "fp16x3", "mixed"])
 def test_batch_replays_match_single_system_calls(systems, prec):
     """Three replays of the recorded graph, each after eager single-system work
     that reuses the same handles, must equal the eager results bitwise."""

@@ -23,7 +23,7 @@ TOL64 = 1e-10
 # <= 3 * 2^-24 relative and the accumulation is FP32, so the same bounds hold.
 TOL32_FIELD = 1e-5
 TOL32_ENERGY = 1e-6
-REDUCED = ["fp32", "bf16x3"]
+REDUCED = ["fp32", "bf16x3", "fp16x3"]
 # mixed: FP64 forward pass, f scaling and energies (energies at the FP64
 # tolerance), split-BF16 back-transform and Vx psi update (FP32 tolerances)
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_energies.json")
@@ -380,12 +380,13 @@ def test_exchange_f32_storage_fp64_arithmetic(torch_cuda):
         assert _rel(vx[j], vx_ref[j]) <= 1e-6, j
 
 
-def test_unsupported_precision_reports_status(torch_cuda):
+def test_unknown_precision_reports_status(torch_cuda):
     torch = torch_cuda
     kx = _kx()
     g = kx.Grid((16, 16, 16), (0.3,) * 3, 12, ("dirichlet",) * 3)
     rho = torch.zeros((1, 16, 16, 16), dtype=torch.float64, device="cuda")
-    with pytest.raises(kx.KxError) as e:
-        g.apply_fL(rho, "coulomb", prec="fp16x3")
-    assert e.value.status == 2
+    phi = torch.empty_like(rho)
+    L = kx.lib()
+    for prec in (-1, 5, 99):
+        assert L.kx_apply_fL(g._h, 0, 0.0, 1, 0, rho.data_ptr(), phi.data_ptr(), prec) == 1
     g.close()
