@@ -1396,16 +1396,22 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
                             vx, s);
   };
   // mean time of three launches after one warm-up
+  // best of three rounds of three launches (shapes within a few per cent of
+  // each other are otherwise ranked by noise)
   auto timeit = [&](auto&& launch, auto&& reset, float& ms) -> hipError_t {
     hipError_t e = reset();
     if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = reset();
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    ms /= 3.0f;
+    ms = 1e30f;
+    for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+      float t = 0.f;
+      e = reset();
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      ms = std::min(ms, t / 3.0f);
+    }
     return e;
   };
   // bitwise agreement of buf with the reference copy
