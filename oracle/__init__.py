@@ -7,6 +7,8 @@ obviously correct, slow implementation written directly from the paper.
 """
 from .kx_oracle import (  # noqa: F401
     Grid,
+    ace_apply,
+    ace_build,
     apply_fL,
     exchange,
     fd_weights,

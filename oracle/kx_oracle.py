@@ -28,6 +28,9 @@ What it computes, in the paper's order:
   (Vx psi)_j = -sum_i occ_i phi_ij psi_i with phi_ij = f(-L)(psi_i psi_j),
   and E_x = -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h for a closed shell
   with spin-summed occupations occ (per-spin g = occ/2, two spins).
+* Sec. IV: the exchange operator is used in adaptively compressed (ACE)
+  form, built from W = Vx psi by a Cholesky factorisation of -(psi, W)_h;
+  V_ACE equals Vx on the span of the orbitals.
 
 Arrays are indexed [..., i3, i2, i1] (axis 1 fastest).
 Boundary conditions are homogeneous Dirichlet (values outside the n_k nodes
@@ -251,3 +254,41 @@ def vx_orbital(psi, occ, j, grid, kernel, omega=0.0):
         phi = apply_fL(psi[i] * psi[j], grid, kernel, omega, F)
         out -= occ[i] * phi * psi[i]
     return out
+
+
+# --------------------------------------------------------------------------
+# Sec. IV: the exchange operator in adaptively compressed (ACE) form, the
+# form in which the exchange enters the self-consistent iteration (the
+# construction of Lin, J. Chem. Theory Comput. 12, 2242 (2016))
+# --------------------------------------------------------------------------
+def ace_build(psi, W, dV):
+    """Compressed exchange vectors xi (norb, ...) from the orbitals psi and
+    W = Vx psi (both (norb, n3, n2, n1)):
+
+      M = (psi_j, W_k)_h                (norb x norb, symmetric, negative definite)
+      -M = L L^T                        (Cholesky, L lower with positive diagonal)
+      xi = L^{-1} W                     (row k of xi is xi_k)
+
+    so that V_ACE phi = -sum_k xi_k (xi_k, phi)_h (ace_apply) reproduces
+    Vx on the span of the orbitals.  Raises numpy.linalg.LinAlgError when -M
+    is not positive definite."""
+    psi = np.asarray(psi, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    norb = psi.shape[0]
+    P = psi.reshape(norb, -1)
+    Wm = W.reshape(norb, -1)
+    M = dV * (P @ Wm.T)
+    L = np.linalg.cholesky(-M)
+    xi = np.linalg.solve(L, Wm)  # forward substitution written as a dense solve
+    return xi.reshape(W.shape)
+
+
+def ace_apply(xi, phi, dV):
+    """V_ACE phi = -sum_k xi_k (xi_k, phi_v)_h for fields phi (nvec, ...)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    norb, nvec = xi.shape[0], phi.shape[0]
+    X = xi.reshape(norb, -1)
+    F = phi.reshape(nvec, -1)
+    G = dV * (X @ F.T)          # (xi_k, phi_v)_h
+    return (-(G.T @ X)).reshape(phi.shape)

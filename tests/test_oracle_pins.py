@@ -337,3 +337,61 @@ def test_pair_energy_parseval():
     e1 = g.dV * float(np.sum(F * Bt * Bt))
     e2 = orc.pair_energy(a, b, g, "erfc", 0.106)
     assert abs(e1 - e2) <= 1e-13 * abs(e2)
+
+
+# ---------------------------------------------------------------- ACE form of the exchange (Sec. IV)
+def _ace_case(kernel, omega, bc, norb=5, seed=11):
+    n, h = (9, 8, 10), (0.5, 0.45, 0.4)
+    psi = _small_orbitals(n, h, bc, norb, seed)
+    occ = np.linspace(2.0, 1.0, norb)
+    g = orc.make_grid(n, h, 12, bc)
+    vx, _ = orc.exchange(psi, occ, g, kernel, omega)
+    return g, psi, vx
+
+
+@pytest.mark.parametrize("kernel,omega,bc", [("coulomb", 0.0, (D, D, D)), ("erfc", 0.106, (P, P, P)),
+                                             ("erfc", 0.3, (P, D, P))])
+def test_ace_reproduces_exchange_on_orbitals(kernel, omega, bc):
+    # defining property of the compressed operator: V_ACE psi_j = (Vx psi)_j
+    g, psi, vx = _ace_case(kernel, omega, bc)
+    xi = orc.ace_build(psi, vx, g.dV)
+    out = orc.ace_apply(xi, psi, g.dV)
+    assert np.max(np.abs(out - vx)) <= 1e-12 * np.max(np.abs(vx))
+
+
+def test_ace_equals_projector_form():
+    # V_ACE = W M^{-1} W^T (h-weighted), M = (psi, W)_h: the same operator
+    # written with an explicit inverse instead of the Cholesky factor
+    g, psi, vx = _ace_case("erfc", 0.2, (P, P, D))
+    norb = psi.shape[0]
+    xi = orc.ace_build(psi, vx, g.dV)
+    W = vx.reshape(norb, -1)
+    M = g.dV * (psi.reshape(norb, -1) @ W.T)
+    phi = np.random.default_rng(3).standard_normal((4,) + psi.shape[1:])
+    ref = (W.T @ np.linalg.inv(M) @ (g.dV * (W @ phi.reshape(4, -1).T))).T.reshape(phi.shape)
+    out = orc.ace_apply(xi, phi, g.dV)
+    assert np.max(np.abs(out - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_ace_operator_symmetric_negative_rank():
+    # as a matrix on the grid: symmetric in the h inner product, negative
+    # semidefinite, of rank norb, and zero on fields h-orthogonal to every W_j
+    g, psi, vx = _ace_case("coulomb", 0.0, (D, P, D), norb=4)
+    xi = orc.ace_build(psi, vx, g.dV)
+    N = int(np.prod(psi.shape[1:]))
+    A = orc.ace_apply(xi, np.eye(N).reshape((N,) + psi.shape[1:]), g.dV).reshape(N, N)
+    assert np.max(np.abs(A - A.T)) <= 1e-12 * np.max(np.abs(A))
+    ev = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert ev.max() <= 1e-12 * np.abs(ev).max()
+    assert int(np.sum(ev < -1e-9 * np.abs(ev).max())) == 4
+    W = vx.reshape(4, -1)
+    phi = np.random.default_rng(8).standard_normal(N)
+    phi -= W.T @ np.linalg.solve(W @ W.T, W @ phi)
+    out = orc.ace_apply(xi, phi.reshape((1,) + psi.shape[1:]), g.dV)
+    assert np.max(np.abs(out)) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_ace_rejects_non_negative_definite():
+    g, psi, vx = _ace_case("coulomb", 0.0, (D, D, D), norb=3)
+    with pytest.raises(np.linalg.LinAlgError):
+        orc.ace_build(psi, -vx, g.dV)
