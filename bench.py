@@ -209,6 +209,35 @@ def measure(g, w, psi_d, occ, vx, prec, steps, warmup, tune, tune_cache=None):
             "plan": g.plan(prec), "tune_s": tune_s}
 
 
+def measure_ace(g, psi_d, vx, w, reps=5):
+    """The compressed exchange built from the last Vx psi (kx_ace_build: one
+    status read-back included) and applied to the orbitals themselves
+    (kx_ace_apply, norb fields); average of `reps` calls after one warm-up.
+    Bytes: build reads psi and W, then W again, and writes xi; apply reads xi
+    and phi, then xi again, and writes the output (4 fields each)."""
+    import torch
+    xi = g.ace_build(psi_d, vx)
+    out = g.ace_apply(xi, psi_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.ace_build(psi_d, vx, out=xi)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3 / reps
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(g.stream)
+    for _ in range(reps):
+        g.ace_apply(xi, psi_d, out=out)
+    stop.record(g.stream)
+    torch.cuda.synchronize()
+    apply_ms = start.elapsed_time(stop) / reps
+    field = psi_d.numel() * psi_d.element_size()
+    return {"build_ms": build_ms, "apply_ms": apply_ms, "nvec": w.norb,
+            "apply_GBps": 4 * field / (apply_ms * 1e-3) / 1e9,
+            "build_GBps": 4 * field / (build_ms * 1e-3) / 1e9}
+
+
 def bench_ragged(args):
     """The six-system ragged batch through kx_batch_apply_exchange (one graph
     replay per step).  The call synchronises, so steps are timed on the host
@@ -344,6 +373,7 @@ def main():
     if "fp64" in runs:
         result["speedup_vs_fp64"] = {p: r["value"] / runs["fp64"]["value"] for p, r in runs.items()}
         result["speedup_vs_fp64_at_1e-8_Ha"] = hr["value"] / runs["fp64"]["value"]
+    result["ace"] = measure_ace(g, psi_d, vx, w)
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, psi, occ)

@@ -173,6 +173,31 @@ kx_status kx_exchange_energy(kx_grid* g, double* ex_out);
  * Synchronises the stream.  A test hook for sampled-pair checks. */
 kx_status kx_pair_energies(kx_grid* g, int npairs, const int* pairs_host, double* e_out_host);
 
+/* Exact exchange in adaptively compressed (ACE) form (Sec. IV: the exchange
+ * operator enters the self-consistent iteration through the compressed
+ * operator of Lin, J. Chem. Theory Comput. 12, 2242 (2016)).  From the
+ * orbitals psi and W = Vx psi (the output of kx_apply_exchange):
+ *   M = (psi_j, W_k)_h  (norb x norb),  -M = L L^T  (Cholesky, L lower with a
+ *   positive diagonal),  xi = L^{-1} W,
+ * so that V_ACE phi = -sum_k xi_k (xi_k, phi)_h equals Vx on the span of the
+ * orbitals.  FP64 arithmetic; fields stored as dtype (KX_F64 / KX_F32).
+ *   norb        1 .. min(1024, N)
+ *   psi_dev, w_dev  norb*N device fields, orbital k at k*N
+ *   xi_dev      norb*N device output (not aliasing psi_dev or w_dev)
+ * KX_ERR_NUMERIC if -M is not positive definite (xi is not written then).
+ * Synchronises the stream once (to read the factorisation status); the
+ * small matrices and partial sums live in the handle's workspace, which
+ * grows on first use. */
+kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, const void* w_dev,
+                       void* xi_dev);
+
+/* out_v = V_ACE phi_v = -sum_k xi_k (xi_k, phi_v)_h for nvec fields.
+ *   xi_dev      norb*N (from kx_ace_build), phi_dev nvec*N, out_dev nvec*N
+ *               (out_dev must not alias xi_dev or phi_dev); nvec 1 .. 4096
+ * Enqueued on the handle's stream; no synchronisation. */
+kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int nvec,
+                       const void* phi_dev, void* out_dev);
+
 /* Copy lam_axis (n_axis values, ascending) and V_axis (n_axis x n_axis,
  * row-major, V[i*n + a] = component i of eigenvector a) to the host.  Either
  * output may be NULL.  Synchronises the stream.  A test hook. */

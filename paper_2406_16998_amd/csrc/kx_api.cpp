@@ -171,6 +171,16 @@ struct kx_grid {
   size_t work32_cap = 0;
   long long pairE_cap = 0;
   double* dEx = nullptr;
+  // compressed exchange: gram partial sums, the small matrix (overwritten by
+  // its Cholesky factor), the factor's inverse, the (xi, phi) coefficients
+  double* dAcePart = nullptr;
+  long long ace_part_cap = 0;
+  double* dAceA = nullptr;
+  double* dAceLinv = nullptr;
+  long long ace_mat_cap = 0;
+  double* dAceG = nullptr;
+  long long ace_g_cap = 0;
+  int* dAceStatus = nullptr;
   int last_norb = -1;
   // optional per-launch timing (hipEvents on the handle's stream)
   bool prof_on = false;
@@ -1105,6 +1115,11 @@ kx_status kx_destroy(kx_grid* g) {
   dev_free(g->dOcc);
   dev_free(g->dPairE);
   dev_free(g->dEx);
+  dev_free(g->dAcePart);
+  dev_free(g->dAceA);
+  dev_free(g->dAceLinv);
+  dev_free(g->dAceG);
+  dev_free(g->dAceStatus);
   dev_free(g->dPsi32);
   dev_free(g->dVx32);
   if (g->hOcc) (void)hipHostFree(g->hOcc);
@@ -1551,6 +1566,94 @@ kx_status kx_exchange_energy(kx_grid* g, double* ex_out) {
     return KX_ERR_DEVICE;
   }
   *ex_out = v;
+  return KX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kAceMaxOrb = 1024;   // one-workgroup Cholesky
+constexpr int kAceMaxVec = 4096;
+
+// grow a device buffer of doubles to at least n elements
+kx_status ensure_doubles(kx_grid* g, double** p, long long* cap, long long n) {
+  if (n <= *cap) return KX_OK;
+  KX_HIP(hipStreamSynchronize(g->stream));
+  dev_free(*p);
+  *p = nullptr;
+  *cap = 0;
+  kx_status st = dev_alloc((void**)p, sizeof(double) * (size_t)n);
+  if (st != KX_OK) return st;
+  *cap = n;
+  return KX_OK;
+}
+
+kx_status check_ace_fields(const kx_grid* g, int norb, int dtype, const void* a, const void* b,
+                           const void* out) {
+  if (!g || norb < 1 || norb > kAceMaxOrb || (long long)norb > g->geom.N) return KX_ERR_INVALID_ARG;
+  if (dtype != KX_F64 && dtype != KX_F32) return KX_ERR_INVALID_ARG;
+  if (!a || !b || !out || out == a || out == b) return KX_ERR_INVALID_ARG;
+  return KX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, const void* w_dev,
+                       void* xi_dev) {
+  kx_status st = check_ace_fields(g, norb, dtype, psi_dev, w_dev, xi_dev);
+  if (st != KX_OK) return st;
+  const long long N = g->geom.N, nn = (long long)norb * norb;
+  const long long grp = ace_groups(N, norb, norb);
+  st = ensure_doubles(g, &g->dAcePart, &g->ace_part_cap, grp * nn);
+  if (st != KX_OK) return st;
+  if (nn > g->ace_mat_cap) {
+    long long cap = g->ace_mat_cap;
+    st = ensure_doubles(g, &g->dAceA, &cap, nn);
+    if (st != KX_OK) return st;
+    cap = g->ace_mat_cap;
+    st = ensure_doubles(g, &g->dAceLinv, &cap, nn);
+    if (st != KX_OK) return st;
+    g->ace_mat_cap = nn;
+  }
+  if (!g->dAceStatus) {
+    st = dev_alloc((void**)&g->dAceStatus, sizeof(int));
+    if (st != KX_OK) return st;
+  }
+  const double dV = g->h[0] * g->h[1] * g->h[2];
+  // -M = -(psi, W)_h, then its Cholesky factor and the factor's inverse
+  KX_HIP(launch_gram(dtype, psi_dev, norb, w_dev, norb, N, grp, g->dAcePart, -dV, g->dAceA,
+                     g->stream));
+  KX_HIP(launch_chol_inv(g->dAceA, norb, g->dAceLinv, g->dAceStatus, g->stream));
+  int fail = 0;
+  KX_HIP(hipMemcpyAsync(&fail, g->dAceStatus, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+  KX_HIP(hipStreamSynchronize(g->stream));
+  if (fail != 0) return KX_ERR_NUMERIC;
+  // xi = L^{-1} W
+  KX_HIP(launch_combine(dtype, g->dAceLinv, norb, 1, norb, norb, w_dev, N, 1.0, xi_dev,
+                        g->stream));
+  return KX_OK;
+}
+
+kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int nvec,
+                       const void* phi_dev, void* out_dev) {
+  kx_status st = check_ace_fields(g, norb, dtype, xi_dev, phi_dev, out_dev);
+  if (st != KX_OK) return st;
+  if (nvec < 1 || nvec > kAceMaxVec) return KX_ERR_INVALID_ARG;
+  const long long N = g->geom.N, nk = (long long)norb * nvec;
+  const long long grp = ace_groups(N, norb, nvec);
+  st = ensure_doubles(g, &g->dAcePart, &g->ace_part_cap, grp * nk);
+  if (st != KX_OK) return st;
+  st = ensure_doubles(g, &g->dAceG, &g->ace_g_cap, nk);
+  if (st != KX_OK) return st;
+  const double dV = g->h[0] * g->h[1] * g->h[2];
+  // G[k][v] = (xi_k, phi_v)_h, then out_v = -sum_k G[k][v] xi_k
+  KX_HIP(launch_gram(dtype, xi_dev, norb, phi_dev, nvec, N, grp, g->dAcePart, dV, g->dAceG,
+                     g->stream));
+  KX_HIP(launch_combine(dtype, g->dAceG, 1, nvec, nvec, norb, xi_dev, N, -1.0, out_dev,
+                        g->stream));
   return KX_OK;
 }
 

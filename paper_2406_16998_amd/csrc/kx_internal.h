@@ -226,6 +226,18 @@ hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* item
 hipError_t launch_exchange_energy(const double* pair_e, const double* occ, int norb, double* ex,
                                   hipStream_t s);
 
+// ---- compressed exchange algebra (kx_ace.hip); fields are rows of N values
+// point-range groups for a gram of na x nb (partials <= 128 MB)
+long long ace_groups(long long N, int na, int nb);
+// out[i][j] = scale * sum_r A[i][r] B[j][r] (part: ngrp * na * nb doubles)
+hipError_t launch_gram(int storage, const void* A, int na, const void* B, int nb, long long N,
+                       long long ngrp, double* part, double scale, double* out, hipStream_t s);
+// A = L L^T in place (lower), Linv = L^{-1}; status = 0 or (failed pivot + 1)
+hipError_t launch_chol_inv(double* A, int n, double* Linv, int* status, hipStream_t s);
+// Out[v][r] = alpha * sum_k C[v ldv + k ldk] X[k][r]
+hipError_t launch_combine(int storage, const double* C, long long ldv, long long ldk, int m, int n,
+                          const void* X, long long N, double alpha, void* Out, hipStream_t s);
+
 __host__ __device__ inline long long pair_index(int i, int j, int norb) {
   // i <= j, row-major upper triangle
   return (long long)i * norb - (long long)i * (i - 1) / 2 + (j - i);

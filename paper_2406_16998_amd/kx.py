@@ -27,7 +27,7 @@ EXPORTS = (
     "kx_setup_laplacian", "kx_apply_fL", "kx_apply_exchange", "kx_exchange_energy",
     "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
-    "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan",
+    "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -72,6 +72,8 @@ def lib():
                                         ctypes.POINTER(vp), ctypes.POINTER(dp),
                                         ctypes.POINTER(vp), c_int, dp],
             "kx_profile": [vp, c_int],
+            "kx_ace_build": [vp, c_int, c_int, vp, vp, vp],
+            "kx_ace_apply": [vp, c_int, c_int, vp, c_int, vp, vp],
             "kx_profile_read": [vp, c_int, dp, ctypes.POINTER(ctypes.c_longlong)],
         }
         for name, args in sig.items():
@@ -221,6 +223,28 @@ class Grid:
         v = ctypes.c_double()
         _check(lib().kx_exchange_energy(self._h, ctypes.byref(v)), "kx_exchange_energy")
         return v.value
+
+    def ace_build(self, psi, w, out=None):
+        """Compressed exchange vectors xi = L^{-1} W, -(psi, W)_h = L L^T,
+        for psi and W = Vx psi of shape (norb, n3, n2, n1)."""
+        import torch
+        dtype = "f64" if psi.dtype == torch.float64 else "f32"
+        if out is None:
+            out = torch.empty_like(w)
+        st = lib().kx_ace_build(self._h, psi.shape[0], DTYPE[dtype], _ptr(psi), _ptr(w), _ptr(out))
+        _check(st, "kx_ace_build")
+        return out
+
+    def ace_apply(self, xi, phi, out=None):
+        """V_ACE phi = -sum_k xi_k (xi_k, phi)_h for phi of shape (nvec, n3, n2, n1)."""
+        import torch
+        dtype = "f64" if xi.dtype == torch.float64 else "f32"
+        if out is None:
+            out = torch.empty_like(phi)
+        st = lib().kx_ace_apply(self._h, xi.shape[0], DTYPE[dtype], _ptr(xi), phi.shape[0], _ptr(phi),
+                                _ptr(out))
+        _check(st, "kx_ace_apply")
+        return out
 
     def pair_energies(self, pairs):
         import numpy as np
