@@ -50,15 +50,27 @@ __global__ void __launch_bounds__(256) gram_partial(const SA* __restrict__ A, in
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
-  for (long long rb = r0; rb < r1; rb += kGK) {
+  // the next step's values are loaded into registers while this step is
+  // multiplied
+  double na_[8], nb_[8];
+  auto fetch = [&](long long rb) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const long long r = rb + lcol + c;
       const bool rin = r < r1;
-      As[(lcol + c) * kGLd + lrow] = (ain && rin) ? (double)arow[r] : 0.0;
-      Bs[(lcol + c) * kGLd + lrow] = (bin && rin) ? (double)brow[r] : 0.0;
+      na_[c] = (ain && rin) ? (double)arow[r] : 0.0;
+      nb_[c] = (bin && rin) ? (double)brow[r] : 0.0;
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (long long rb = r0; rb < r1; rb += kGK) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      As[(lcol + c) * kGLd + lrow] = na_[c];
+      Bs[(lcol + c) * kGLd + lrow] = nb_[c];
     }
     __syncthreads();
+    if (rb + kGK < r1) fetch(rb + kGK);
 #pragma unroll 4
     for (int k = 0; k < kGK; ++k) {
       double av[8], bv[8];
@@ -163,22 +175,31 @@ __global__ void __launch_bounds__(256) combine(const double* __restrict__ C, lon
   // columns k0 + 8 (t % 2) ..
   const int xk = t >> 4, xr = (t & 15) * 4;
   const int cv = t >> 1, ck = (t & 1) * 8;
-  for (int k0 = 0; k0 < n; k0 += kCK) {
-    {
-      const int k = k0 + xk;
+  // the next step's values are loaded into registers while this step is
+  // multiplied
+  double nx[4], nc[8];
+  auto fetch = [&](int k0) {
+    const int k = k0 + xk;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const long long r = r0 + xr + b;
-        Xs[xk * kCR + xr + b] = (k < n && r < N) ? (double)X[(long long)k * N + r] : 0.0;
-      }
-      const int v = v0 + cv;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int k2 = k0 + ck + c;
-        Cs[(ck + c) * (kCV + 2) + cv] = (v < m && k2 < n) ? C[v * ldv + k2 * ldk] : 0.0;
-      }
+    for (int b = 0; b < 4; ++b) {
+      const long long r = r0 + xr + b;
+      nx[b] = (k < n && r < N) ? (double)X[(long long)k * N + r] : 0.0;
     }
+    const int v = v0 + cv;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int k2 = k0 + ck + c;
+      nc[c] = (v < m && k2 < n) ? C[v * ldv + k2 * ldk] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < n; k0 += kCK) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Xs[xk * kCR + xr + b] = nx[b];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) Cs[(ck + c) * (kCV + 2) + cv] = nc[c];
     __syncthreads();
+    if (k0 + kCK < n) fetch(k0 + kCK);
 #pragma unroll 4
     for (int k = 0; k < kCK; ++k) {
       double cvv[8], xv[4];
