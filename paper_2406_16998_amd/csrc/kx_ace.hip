@@ -11,7 +11,9 @@
 //            workgroup;
 //   combine  Out = alpha C X (each output row a combination of the rows of X),
 //            one pass over X and Out.
-// FP64 arithmetic throughout; fields stored as double or float.
+// The gram and the combination are dense contractions on FP64 MFMA tiles
+// (staging through LDS, next step prefetched into registers).  FP64
+// arithmetic throughout; fields stored as double or float.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,15 +30,60 @@ constexpr int kCV = 128;      // combine: output rows per workgroup
 constexpr int kCR = 64;       // combine: grid points per workgroup
 constexpr int kCK = 16;       // combine: rows of X per staged step
 
+// eight consecutive values (16-byte aligned) widened to double
+__device__ __forceinline__ void load8(const double* p, double* v) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const d2 x = *reinterpret_cast<const d2*>(p + 2 * q);
+    v[2 * q] = x[0];
+    v[2 * q + 1] = x[1];
+  }
+}
+__device__ __forceinline__ void load8(const float* p, double* v) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const f4 x = *reinterpret_cast<const f4*>(p + 4 * q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[4 * q + e] = (double)x[e];
+  }
+}
+
+// four consecutive values (16-byte aligned) widened to double
+__device__ __forceinline__ void load4(const double* p, double* v) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const d2 x = *reinterpret_cast<const d2*>(p + 2 * q);
+    v[2 * q] = x[0];
+    v[2 * q + 1] = x[1];
+  }
+}
+__device__ __forceinline__ void load4(const float* p, double* v) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 x = *reinterpret_cast<const f4*>(p);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = (double)x[e];
+}
+
 // part[grp][i][j] = sum over points r of group grp of A[i][r] B[j][r].
-// 256 threads as a 16 x 16 grid, each owning an 8 x 8 block of the tile.
+// 256 threads = 4 waves; wave w owns the 64 x 64 quarter (w / 2, w % 2) of
+// the 128 x 128 tile as 4 x 4 blocks of 16 x 16 on v_mfma_f64_16x16x4f64
+// (lane l = 16 lg + li holds A[li][lg] and B[lg][li]; element e of a block
+// accumulator holds D[4 e + lg][li]).  The staged points are the products'
+// K dimension: A[m][k] = As[k][m], B[k][n] = Bs[k][n].
 template <class SA, class SB>
 __global__ void __launch_bounds__(256) gram_partial(const SA* __restrict__ A, int na,
                                                     const SB* __restrict__ B, int nb, long long N,
                                                     long long per, double* __restrict__ part) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
   __shared__ double As[kGK * kGLd];
   __shared__ double Bs[kGK * kGLd];
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int t = threadIdx.x;
+  const int lane = t & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
   const int i0 = blockIdx.y * kGT, j0 = blockIdx.z * kGT;
   const long long r0 = (long long)blockIdx.x * per;
   const long long r1 = r0 + per < N ? r0 + per : N;
@@ -45,15 +92,23 @@ __global__ void __launch_bounds__(256) gram_partial(const SA* __restrict__ A, in
   const bool ain = i0 + lrow < na, bin = j0 + lrow < nb;
   const SA* __restrict__ arow = A + (long long)(ain ? i0 + lrow : 0) * N;
   const SB* __restrict__ brow = B + (long long)(bin ? j0 + lrow : 0) * N;
-  double acc[8][8];
+  v4d acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
   // the next step's values are loaded into registers while this step is
   // multiplied
   double na_[8], nb_[8];
+  // whole steps of rows that exist, on 16-byte aligned rows: 16-byte loads
+  const bool vec = ((N * (long long)sizeof(SA)) % 16 == 0) && ((N * (long long)sizeof(SB)) % 16 == 0) &&
+                   ((reinterpret_cast<unsigned long long>(A) | reinterpret_cast<unsigned long long>(B)) & 15) == 0;
   auto fetch = [&](long long rb) {
+    if (vec && ain && bin && rb + kGK <= r1 && (rb & 7) == 0) {
+      load8(arow + rb + lcol, na_);
+      load8(brow + rb + lcol, nb_);
+      return;
+    }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const long long r = rb + lcol + c;
@@ -71,29 +126,35 @@ __global__ void __launch_bounds__(256) gram_partial(const SA* __restrict__ A, in
     }
     __syncthreads();
     if (rb + kGK < r1) fetch(rb + kGK);
-#pragma unroll 4
-    for (int k = 0; k < kGK; ++k) {
-      double av[8], bv[8];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) av[a] = As[k * kGLd + ty * 8 + a];
+    for (int k4 = 0; k4 < kGK; k4 += 4) {
+      const double* __restrict__ ar = As + (k4 + lg) * kGLd + wi + li;
+      const double* __restrict__ br = Bs + (k4 + lg) * kGLd + wj + li;
+      double av[4], bv[4];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) bv[b] = Bs[k * kGLd + tx * 8 + b];
+      for (int a = 0; a < 4; ++a) av[a] = ar[16 * a];
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 4; ++b) bv[b] = br[16 * b];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
   double* __restrict__ pg = part + (long long)blockIdx.x * na * nb;
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int i = i0 + ty * 8 + a;
-    if (i >= na) continue;
+  for (int a = 0; a < 4; ++a) {
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int j = j0 + tx * 8 + b;
-      if (j < nb) pg[(long long)i * nb + j] = acc[a][b];
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + wi + 16 * a + 4 * e + lg;
+      if (i >= na) continue;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = j0 + wj + 16 * b + li;
+        if (j < nb) pg[(long long)i * nb + j] = acc[a][b][e];
+      }
     }
   }
 }
@@ -109,14 +170,22 @@ __global__ void __launch_bounds__(256) gram_reduce(const double* __restrict__ pa
   out[k] = scale * s;
 }
 
-// A (n x n, symmetric, lower triangle used) is overwritten by its Cholesky
-// factor L (A = L L^T, right-looking, one workgroup); then Linv = L^{-1}
-// (lower triangular, upper part zero), one column per thread by forward
-// substitution.  status = 0, or k + 1 when the k-th pivot is not positive
-// (A is not positive definite); Linv is not written then.
-__global__ void __launch_bounds__(1024) chol_inv(double* __restrict__ A, int n,
+// A (n x n, symmetric, lower triangle used) is factored as L L^T
+// (right-looking, one workgroup); then Linv = L^{-1} (lower triangular, upper
+// part zero), one column per thread by forward substitution.  status = 0, or
+// k + 1 when the k-th pivot is not positive (A is not positive definite);
+// Linv is not written then.  INLDS: the matrix is copied into LDS and
+// factored there (n^2 doubles of dynamic LDS), else A is overwritten by L.
+extern __shared__ __align__(16) double kx_chol_lds[];
+template <bool INLDS>
+__global__ void __launch_bounds__(1024) chol_inv(double* __restrict__ Ag, int n,
                                                  double* __restrict__ Linv, int* status) {
   const int t = threadIdx.x, nt = blockDim.x;
+  double* A = Ag;
+  if (INLDS) {
+    A = kx_chol_lds;
+    for (long long k = t; k < (long long)n * n; k += nt) A[k] = Ag[k];
+  }
   const int tx = t & 31, ty = t >> 5, nx = 32, ny = nt >> 5;
   __shared__ int fail;
   if (t == 0) fail = 0;
@@ -155,22 +224,27 @@ __global__ void __launch_bounds__(1024) chol_inv(double* __restrict__ A, int n,
 }
 
 // Out[v][r] = alpha * sum_k C[v * ldv + k * ldk] X[k][r], v < m, k < n.
-// 256 threads as 16 (points) x 16 (rows), each owning 8 rows x 4 points.
+// 256 threads = 4 waves; wave w owns output rows 32 w .. 32 w + 31 of the
+// 128-row block and all 64 points, as 2 x 4 blocks of 16 x 16 on
+// v_mfma_f64_16x16x4f64 with A[m][k] = Cs[k][m] and B[k][n] = Xs[k][n].
 template <class S>
 __global__ void __launch_bounds__(256) combine(const double* __restrict__ C, long long ldv,
                                                long long ldk, int m, int n,
                                                const S* __restrict__ X, long long N, double alpha,
                                                S* __restrict__ Out) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
   __shared__ double Xs[kCK * kCR];
   __shared__ double Cs[kCK * (kCV + 2)];
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int t = threadIdx.x;
+  const int lane = t & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const long long r0 = (long long)blockIdx.x * kCR;
   const int v0 = blockIdx.y * kCV;
-  double acc[8][4];
+  v4d acc[2][4];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
   // staging: X rows k0 + t / 16, points 4 (t % 16) ..; C rows v0 + t / 2,
   // columns k0 + 8 (t % 2) ..
   const int xk = t >> 4, xr = (t & 15) * 4;
@@ -178,12 +252,18 @@ __global__ void __launch_bounds__(256) combine(const double* __restrict__ C, lon
   // the next step's values are loaded into registers while this step is
   // multiplied
   double nx[4], nc[8];
+  const bool vec = ((N * (long long)sizeof(S)) % 16 == 0) &&
+                   (reinterpret_cast<unsigned long long>(X) & 15) == 0;
   auto fetch = [&](int k0) {
     const int k = k0 + xk;
+    if (vec && k < n && r0 + xr + 4 <= N) {
+      load4(X + (long long)k * N + r0 + xr, nx);
+    } else {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const long long r = r0 + xr + b;
-      nx[b] = (k < n && r < N) ? (double)X[(long long)k * N + r] : 0.0;
+      for (int b = 0; b < 4; ++b) {
+        const long long r = r0 + xr + b;
+        nx[b] = (k < n && r < N) ? (double)X[(long long)k * N + r] : 0.0;
+      }
     }
     const int v = v0 + cv;
 #pragma unroll
@@ -200,28 +280,34 @@ __global__ void __launch_bounds__(256) combine(const double* __restrict__ C, lon
     for (int c = 0; c < 8; ++c) Cs[(ck + c) * (kCV + 2) + cv] = nc[c];
     __syncthreads();
     if (k0 + kCK < n) fetch(k0 + kCK);
-#pragma unroll 4
-    for (int k = 0; k < kCK; ++k) {
-      double cvv[8], xv[4];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) cvv[a] = Cs[k * (kCV + 2) + ty * 8 + a];
+    for (int k4 = 0; k4 < kCK; k4 += 4) {
+      const double* __restrict__ cr = Cs + (k4 + lg) * (kCV + 2) + 32 * wave + li;
+      const double* __restrict__ xr_ = Xs + (k4 + lg) * kCR + li;
+      double av[2], bv[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) xv[b] = Xs[k * kCR + tx * 4 + b];
+      for (int a = 0; a < 2; ++a) av[a] = cr[16 * a];
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 4; ++b) bv[b] = xr_[16 * b];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(cvv[a], xv[b], acc[a][b]);
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int v = v0 + ty * 8 + a;
-    if (v >= m) continue;
+  for (int a = 0; a < 2; ++a) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const long long r = r0 + tx * 4 + b;
-      if (r < N) Out[(long long)v * N + r] = (S)(alpha * acc[a][b]);
+    for (int e = 0; e < 4; ++e) {
+      const int v = v0 + 32 * wave + 16 * a + 4 * e + lg;
+      if (v >= m) continue;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const long long r = r0 + 16 * b + li;
+        if (r < N) Out[(long long)v * N + r] = (S)(alpha * acc[a][b][e]);
+      }
     }
   }
 }
@@ -260,7 +346,21 @@ hipError_t launch_gram(int storage, const void* A, int na, const void* B, int nb
 
 hipError_t launch_chol_inv(double* A, int n, double* Linv, int* status, hipStream_t s) {
   if (n <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_inv, dim3(1), dim3(1024), 0, s, A, n, Linv, status);
+  const size_t lds = (size_t)n * n * sizeof(double);
+  int dev = 0, maxl = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&maxl, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    maxl = 0;
+  }
+  if (lds <= (size_t)maxl &&
+      hipFuncSetAttribute((const void*)chol_inv<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) == hipSuccess) {
+    hipLaunchKernelGGL(chol_inv<true>, dim3(1), dim3(1024), lds, s, A, n, Linv, status);
+  } else {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(chol_inv<false>, dim3(1), dim3(1024), 0, s, A, n, Linv, status);
+  }
   return hipGetLastError();
 }
 
