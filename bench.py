@@ -134,7 +134,17 @@ def cpu_baseline(w, psi, occ, target_s=20.0):
     t0 = time.perf_counter()
     orc.exchange(np.asarray(psi[:k], dtype=np.float64), occ[:k], grid, w.kernel, w.omega)
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": pairs / dt, "unit": "pair-solves/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": model,
             "sample": f"oracle exchange over the first {k} orbitals ({pairs} of {w.npairs} pairs) "
                       f"of the same workload, {dt:.1f} s"}
 
