@@ -6,7 +6,9 @@ The oracle cannot run every pair at this size, so the checks are:
     pairs (the oracle reads the FP32 orbitals promoted exactly to FP64, so the
     difference is compute error only): 1e-10 relative;
   * each reduced precision against the same oracle sample at its energy
-    tolerance, and against the full FP64 GPU path for E_x and Vx psi.
+    tolerance, and against the full FP64 GPU path for E_x and Vx psi;
+  * the compressed exchange built from the FP64 path's Vx psi reproduces it
+    on the orbitals (V_ACE psi_j = (Vx psi)_j, FP32-rounded xi: 1e-6).
 """
 import numpy as np
 import pytest
@@ -53,6 +55,15 @@ def test_periodic144_f32_storage_sampled():
     print(f"fp64 E_x={ex64!r}", flush=True)
     for e, r in zip(pe64, ref):
         assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * emax
+    # compressed exchange from the FP64 path's Vx psi (FP32 fields, FP64
+    # arithmetic): V_ACE psi_j = (Vx psi)_j to FP32 rounding of xi
+    xi = g.ace_build(psi_d, vx64)
+    vace = g.ace_apply(xi, psi_d)
+    torch.cuda.synchronize()
+    for j in (0, 131, 255):
+        assert _rel(vace[j].cpu().numpy(), vx64[j].cpu().numpy()) <= 1e-6, j
+    del xi, vace
+    print("ace property checked", flush=True)
     vx64 = vx64.cpu().numpy()
 
     for prec in ("fp32", "bf16x3"):
