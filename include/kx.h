@@ -50,7 +50,8 @@ typedef enum {
   KX_ERR_OUT_OF_MEMORY = 4, /* device or pinned host allocation failed          */
   KX_ERR_DEVICE = 5,        /* a HIP runtime call failed                         */
   KX_ERR_STATE = 6,         /* e.g. energy requested before any exchange call   */
-  KX_ERR_NUMERIC = 7        /* eigen-solver did not converge / non-finite input */
+  KX_ERR_NUMERIC = 7        /* eigen-solver did not converge / non-finite input /
+                             * compressed-exchange overlap not negative definite */
 } kx_status;
 
 typedef enum { KX_BC_DIRICHLET = 0, KX_BC_PERIODIC = 1 } kx_bc;
