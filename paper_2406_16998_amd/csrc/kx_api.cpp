@@ -1314,7 +1314,7 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
           // accept only a shape this build would itself propose
           std::vector<SlabPlan> cf, ci;
           std::vector<PencilPlan> cp;
-          plan_candidates(G, (size_t)lds, kind, cf, cp, ci);
+          plan_candidates(G, (size_t)lds, kind, cf, cp, ci, elem_size(dtype_w));
           auto same = [](const SlabPlan& a, const SlabPlan& b) {
             return a.qsplit == b.qsplit && a.slabs == b.slabs && a.waves == b.waves &&
                    a.kc == b.kc && a.vlds == b.vlds && a.lds_bytes == b.lds_bytes;
@@ -1448,7 +1448,7 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
 
   std::vector<SlabPlan> cf, ci;
   std::vector<PencilPlan> cp;
-  plan_candidates(G, (size_t)lds, kind, cf, cp, ci);
+  plan_candidates(G, (size_t)lds, kind, cf, cp, ci, elem_size(dtype_w));
   if (cf.empty() || cp.empty() || ci.empty()) {
     release();
     return KX_ERR_UNSUPPORTED;

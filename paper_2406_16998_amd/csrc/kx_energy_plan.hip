@@ -248,7 +248,7 @@ Plan make_plan(const Geom& g, size_t max_lds, size_t esize) {
 // double operands, 1: float operands, 2: split-BF16), each within the
 // kernels' launch bounds, register staging budgets and the LDS size.
 void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPlan>& fwd,
-                     std::vector<PencilPlan>& pen, std::vector<SlabPlan>& inv) {
+                     std::vector<PencilPlan>& pen, std::vector<SlabPlan>& inv, size_t ssize) {
   fwd.clear();
   pen.clear();
   inv.clear();
@@ -270,10 +270,13 @@ void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPl
           if (!split && esize != 8 && (size_t)kc * g.pe1 > (size_t)kFwdPos * wps * 64) continue;
           for (int vl : {0, 1}) {
             if (split && vl) continue;
-            const size_t lds = split ? (size_t)slabs * 2 * 2 * kc * wrow * esize
-                                     : (size_t)slabs * fwd_slab_bytes(g, kc, wrow, esize) +
+            const size_t lds8 = split ? (size_t)slabs * 2 * 2 * kc * wrow * esize
+                                      : (size_t)slabs * fwd_slab_bytes(g, kc, wrow, esize) +
+                                            (vl ? vb : 0);
+            if (lds8 > max_lds) continue;  // launchable for 8-byte storage too
+            const size_t lds = split ? lds8
+                                     : (size_t)slabs * fwd_slab_bytes(g, kc, wrow, esize, ssize) +
                                            (vl ? vb : 0);
-            if (lds > max_lds) continue;
             SlabPlan p;
             p.qsplit = qsplit;
             p.slabs = slabs;

@@ -99,15 +99,17 @@ __host__ __device__ inline size_t inv_slab_elems(const Geom& g, int kc, bool ban
   return ((stage > out ? stage : out) + 3) / 4 * 4;
 }
 // FP64 / FP32 forward pass, per z-slab: bytes of LDS for one staged range of
-// raw rows (kc grid rows of n1 values of up to 8 bytes, in whole 1 KB copy
-// segments), and for the slab's two folded buffers ([2][kc][wrow] operands of
-// esize bytes) plus, with FP64 operands, two raw stages of four ranges.
-__host__ __device__ inline int fwd_raw_range(const Geom& g, int kc) {
-  return (kc * g.n1 * 8 + 1023) / 1024 * 1024;
+// raw rows (kc grid rows of n1 stored values of ssize bytes, in whole 1 KB
+// copy segments), and for the slab's two folded buffers ([2][kc][wrow]
+// operands of esize bytes) plus, with FP64 operands, two raw stages of four
+// ranges.
+__host__ __device__ inline int fwd_raw_range(const Geom& g, int kc, size_t ssize) {
+  return (int)(((size_t)kc * g.n1 * ssize + 1023) / 1024 * 1024);
 }
-__host__ __device__ inline size_t fwd_slab_bytes(const Geom& g, int kc, int wrow, size_t esize) {
+__host__ __device__ inline size_t fwd_slab_bytes(const Geom& g, int kc, int wrow, size_t esize,
+                                                 size_t ssize = 8) {
   return (size_t)2 * 2 * kc * wrow * esize +
-         (esize == 8 ? (size_t)2 * 4 * fwd_raw_range(g, kc) : 0);
+         (esize == 8 ? (size_t)2 * 4 * fwd_raw_range(g, kc, ssize) : 0);
 }
 
 // Staged rows per chunk of the inverse pass (the chunks are copied to LDS in
@@ -147,9 +149,12 @@ struct Plan {
 };
 // esize: bytes per element of the mode-product operands (8 or 4)
 Plan make_plan(const Geom& g, size_t max_lds, size_t esize);
-// every valid launch shape (kind 0: double operands, 1: float, 2: split-BF16)
+// every valid launch shape (kind 0: double operands, 1: float, 2: split-BF16);
+// ssize: bytes of the stored orbitals the shapes are sized for (forward LDS;
+// every shape also fits 8-byte storage, for which the launch enlarges it)
 void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPlan>& fwd,
-                     std::vector<PencilPlan>& pen, std::vector<SlabPlan>& inv);
+                     std::vector<PencilPlan>& pen, std::vector<SlabPlan>& inv,
+                     size_t ssize = 8);
 
 // ---- set-up kernels (kx_setup.hip) ----
 // Jacobi eigensolver of the symmetric n x n matrix A (global memory); writes
