@@ -182,18 +182,32 @@ def roofline(w, prec, phases, steps):
 
 def measure(g, w, psi_d, occ, vx, prec, steps, warmup, tune, tune_cache=None):
     """Warm-up, then `steps` timed exchange applications (HIP events on the
-    stream the library runs on); per-phase times from the library's events."""
+    stream the library runs on).  Per-phase times (phases_ms_per_step) come
+    from the library's events on the last warm-up step; the roofline's
+    launch time from events around the dominant phase's launches in the
+    timed steps."""
     import torch
     t0 = time.perf_counter()
     if tune:
         g.autotune(prec=prec, dtype="f64" if psi_d.dtype == torch.float64 else "f32",
                    cache_path=tune_cache)
     tune_s = time.perf_counter() - t0
-    for k in range(warmup):
+    # the last warm-up step (or one extra untimed step) times every phase's
+    # launches; the timed steps bracket only the dominant phase's launches
+    # (each event pair drains the stream between two launches)
+    for k in range(max(warmup, 1)):
+        if k == max(warmup, 1) - 1:
+            g.profile(True)
         g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec=prec, out=vx)
         g.exchange_energy()
-        print(f"# {prec} warmup {k + 1}/{warmup} done", file=sys.stderr, flush=True)
-    g.profile(True)
+        print(f"# {prec} warmup {k + 1}/{max(warmup, 1)} done", file=sys.stderr, flush=True)
+    phases1 = {}
+    for ph in ("forward", "pencil", "inverse", "energy"):
+        ms, cnt = g.profile_read(ph)
+        phases1[ph] = {"ms": ms, "launches": cnt}
+    g.profile(False)
+    dom = max(("forward", "pencil", "inverse"), key=lambda p: phases1[p]["ms"])
+    g.profile_phases([dom])
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -204,16 +218,15 @@ def measure(g, w, psi_d, occ, vx, prec, steps, warmup, tune, tune_cache=None):
     torch.cuda.synchronize()
     ms_total = start.elapsed_time(stop)
     ex = g.exchange_energy()
-    phases = {}
-    for ph in ("forward", "pencil", "inverse", "energy"):
-        ms, cnt = g.profile_read(ph)
-        phases[ph] = {"ms": ms, "launches": cnt}
+    ms, cnt = g.profile_read(dom)
+    phases = {p: {"ms": 0.0, "launches": 0} for p in phases1}
+    phases[dom] = {"ms": ms, "launches": cnt}
     g.profile(False)
     ms_step = ms_total / steps
     print(f"# {prec}: {steps} steps {ms_total:.1f} ms", file=sys.stderr, flush=True)
     pf = phase_flops(w)
     return {"value": w.npairs / (ms_step * 1e-3), "ms_per_step": ms_step, "E_x": ex,
-            "phases_ms_per_step": {p: v["ms"] / steps for p, v in phases.items()},
+            "phases_ms_per_step": {p: v["ms"] for p, v in phases1.items()},
             "roofline": roofline(w, prec, phases, steps),
             "tflops_whole_step": sum(pf.values()) * w.npairs / (ms_step * 1e-3) / 1e12,
             "plan": g.plan(prec), "tune_s": tune_s}

@@ -217,6 +217,11 @@ typedef enum {
 } kx_phase;
 kx_status kx_profile(kx_grid* g, int enable);
 kx_status kx_profile_read(kx_grid* g, int phase, double* total_ms, long long* launches);
+/* As kx_profile(g, 1), but brackets only the launches of the phases whose bit
+ * (1 << KX_PHASE_*) is set in mask (1..15).  Each pair of events makes the
+ * stream drain between the launches it separates, so timing one phase
+ * disturbs a run less than timing all of them. */
+kx_status kx_profile_phases(kx_grid* g, int mask);
 
 /* Free every device allocation of the handle (after synchronising its stream).
  * NULL is accepted. */

@@ -184,6 +184,7 @@ struct kx_grid {
   int last_norb = -1;
   // optional per-launch timing (hipEvents on the handle's stream)
   bool prof_on = false;
+  int prof_mask = 0xF;  // phases whose launches are bracketed (1 << KX_PHASE_*)
   bool capturing = false;  // work is being recorded into a graph: no timing events
   // identity and buffer generation: a recorded graph bakes in device
   // addresses, so any reallocation invalidates it
@@ -431,7 +432,7 @@ kx_status ensure_t2(kx_grid* g, int slots) {
 // Bracket one kernel launch with timing events when profiling is on.
 template <class F>
 hipError_t timed(kx_grid* g, hipStream_t s, int kind, F&& launch) {
-  if (!g->prof_on || g->capturing) return launch();
+  if (!g->prof_on || g->capturing || !((g->prof_mask >> kind) & 1)) return launch();
   const size_t k = g->prof_kind.size();
   while (g->prof_ev.size() < 2 * (k + 1)) {
     hipEvent_t ev;
@@ -1700,6 +1701,19 @@ kx_status kx_profile(kx_grid* g, int enable) {
     return KX_ERR_DEVICE;
   }
   g->prof_on = enable == 1;
+  g->prof_mask = 0xF;
+  g->prof_kind.clear();
+  return KX_OK;
+}
+
+kx_status kx_profile_phases(kx_grid* g, int mask) {
+  if (!g || mask < 1 || mask > 0xF) return KX_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(g->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return KX_ERR_DEVICE;
+  }
+  g->prof_on = true;
+  g->prof_mask = mask;
   g->prof_kind.clear();
   return KX_OK;
 }

@@ -28,6 +28,7 @@ EXPORTS = (
     "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
+    "kx_profile_phases",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -72,6 +73,7 @@ def lib():
                                         ctypes.POINTER(vp), ctypes.POINTER(dp),
                                         ctypes.POINTER(vp), c_int, dp],
             "kx_profile": [vp, c_int],
+            "kx_profile_phases": [vp, c_int],
             "kx_ace_build": [vp, c_int, c_int, vp, vp, vp],
             "kx_ace_apply": [vp, c_int, c_int, vp, c_int, vp, vp],
             "kx_profile_read": [vp, c_int, dp, ctypes.POINTER(ctypes.c_longlong)],
@@ -268,6 +270,13 @@ class Grid:
 
     def profile(self, enable=True):
         _check(lib().kx_profile(self._h, 1 if enable else 0), "kx_profile")
+
+    def profile_phases(self, phases):
+        """Time only the launches of the named phases (see profile)."""
+        mask = 0
+        for ph in phases:
+            mask |= 1 << PHASE[ph]
+        _check(lib().kx_profile_phases(self._h, mask), "kx_profile_phases")
 
     def profile_read(self, phase):
         """(total ms, launches) of one phase since profile(True)."""

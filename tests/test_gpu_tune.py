@@ -66,3 +66,26 @@ def test_cache_file_round_trip(kx, tmp_path):
     assert g2.plan("bf16x3") == g1.plan("bf16x3")
     g1.close()
     g2.close()
+
+
+def test_profile_phases_brackets_only_the_chosen_phase(kx):
+    # the bench times its steps with only the dominant phase's launches
+    # bracketed; the other phases must then record nothing
+    import torch
+    w, psi, occ = make_workload("mixed40x36x44_erfc")
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    psi_d = torch.from_numpy(psi).cuda()
+    g.profile(True)
+    g.apply_exchange(psi_d, occ, w.kernel, w.omega)
+    counts = {ph: g.profile_read(ph)[1] for ph in ("forward", "pencil", "inverse", "energy")}
+    assert all(c > 0 for c in counts.values()), counts
+    g.profile_phases(["forward"])
+    g.apply_exchange(psi_d, occ, w.kernel, w.omega)
+    ms, cnt = g.profile_read("forward")
+    assert cnt == counts["forward"] and ms > 0
+    for ph in ("pencil", "inverse", "energy"):
+        assert g.profile_read(ph)[1] == 0, ph
+    g.profile(False)
+    with pytest.raises(kx.KxError):
+        g.profile_phases([])
+    g.close()
