@@ -332,7 +332,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the exchange path has no multi-GPU mode in this build",
+        print("bench.py measures one GPU only: the exchange path runs on a single GPU",
               file=sys.stderr)
         sys.exit(2)
 

@@ -45,7 +45,7 @@ extern "C" {
 typedef enum {
   KX_OK = 0,
   KX_ERR_INVALID_ARG = 1,   /* bad size, spacing, order, enum, pointer or count */
-  KX_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement      */
+  KX_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement     */
   KX_ERR_SINGULAR = 3,      /* unscreened kernel with a zero eigenvalue of -L   */
   KX_ERR_OUT_OF_MEMORY = 4, /* device or pinned host allocation failed          */
   KX_ERR_DEVICE = 5,        /* a HIP runtime call failed                         */
@@ -154,7 +154,7 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
  *               otherwise; the plan is then left unchanged); no cache use
  *   cache_path  NULL, or a text file: a line for this grid shape, precision
  *               and device is read instead of timing (accepted only if the
- *               shape is one this build proposes); a new result is appended
+ *               shape is one the planner proposes); a new result is appended
  * Allocates temporary device buffers (2*items orbitals in and out) and
  * synchronises the stream. */
 kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,

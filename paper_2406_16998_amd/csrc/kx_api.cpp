@@ -764,7 +764,7 @@ const char* kx_status_string(int s) {
   switch (s) {
     case KX_OK: return "ok";
     case KX_ERR_INVALID_ARG: return "invalid argument";
-    case KX_ERR_UNSUPPORTED: return "unsupported in this build";
+    case KX_ERR_UNSUPPORTED: return "unsupported by the library";
     case KX_ERR_SINGULAR: return "singular: unscreened kernel with a zero eigenvalue";
     case KX_ERR_OUT_OF_MEMORY: return "out of memory";
     case KX_ERR_DEVICE: return "HIP runtime error";
@@ -1312,7 +1312,7 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
           pn.lds_bytes = pl;
           iv.vlds = ivv != 0;
           iv.lds_bytes = il;
-          // accept only a shape this build would itself propose
+          // accept only a shape the planner itself proposes
           std::vector<SlabPlan> cf, ci;
           std::vector<PencilPlan> cp;
           plan_candidates(G, (size_t)lds, kind, cf, cp, ci, elem_size(dtype_w));
