@@ -1,0 +1,79 @@
+"""The benchmark's flop and byte model and its roofline arithmetic, checked on
+the CPU against direct counts (no GPU, no library calls)."""
+import itertools
+
+import pytest
+
+import bench
+from synth import WORKLOADS
+from synth.orbitals import Workload
+
+
+def _toy(norb=3, n=(6, 5, 7), storage="f64"):
+    return Workload("toy", n, (0.5,) * 3, 4, ("periodic",) * 3, "erfc", 0.2, norb, 2.0, 1, 8, True,
+                    storage)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 48, 96, 144])
+def test_mode_flops_counts_folded_products(n):
+    # brute force: for every vector along the axis, a ceil(n/2)-square and a
+    # floor(n/2)-square product, one multiply and one add per element
+    N = n * 10
+    me, mo = (n + 1) // 2, n // 2
+    direct = sum(2 * (me * me + mo * mo) for _ in range(N // n))
+    assert bench.mode_flops(N, n) == direct
+    if n % 2 == 0:  # half of the unfolded 2 n flops per point
+        assert bench.mode_flops(N, n) == N * n
+
+
+def test_phase_flops_at_96_cubed():
+    w = WORKLOADS["periodic96_erfc"]
+    pf = bench.phase_flops(w)
+    assert pf["forward"] == pf["inverse"] == 2 * w.N * 96
+    assert pf["pencil"] == 2 * w.N * 96
+    # folding halves the unfolded count 4 N (n1 + n2 + n3)
+    assert sum(pf.values()) * 2 == w.flops_per_pair()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3", "mixed"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_phase_bytes_sum_over_pairs(prec, storage):
+    # the per-step byte model against a loop over the pairs (i <= j)
+    w = _toy(norb=4, storage=storage)
+    s_store = 8 if storage == "f64" else 4
+    s = s_store if prec == "fp64" else 4
+    t = {"fp64": 8, "fp32": 4, "bf16x3": 4, "fp16x3": 4, "mixed": 8}[prec]
+    tot = {"forward": 0, "pencil": 0, "inverse": 0}
+    for i, j in itertools.combinations_with_replacement(range(w.norb), 2):
+        orbs = 1 if i == j else 2
+        if prec == "mixed":
+            tot["forward"] += (orbs * s_store + 8) * w.N
+            tot["pencil"] += (8 + 4) * w.N
+            tot["inverse"] += (4 + 3 * orbs * s) * w.N
+        else:
+            tot["forward"] += (orbs * s + t) * w.N
+            tot["pencil"] += 2 * t * w.N
+            tot["inverse"] += (t + 3 * orbs * s) * w.N
+    assert bench.phase_bytes(w, prec) == tot
+
+
+def test_roofline_picks_the_bound_and_the_dominant_phase():
+    w = WORKLOADS["periodic96_erfc"]
+    launches = 129
+    # forward dominant: 2 ms a launch
+    phases = {"forward": {"ms": 2.0 * launches, "launches": launches},
+              "pencil": {"ms": 1.0 * launches, "launches": launches},
+              "inverse": {"ms": 1.5 * launches, "launches": launches},
+              "energy": {"ms": 0.1, "launches": launches}}
+    r = bench.roofline(w, "fp64", phases, steps=1)
+    assert r["kernel"] == "forward" and r["avg_launch_ms"] == pytest.approx(2.0)
+    pb = bench.phase_bytes(w, "fp64")["forward"] / launches
+    pf = bench.phase_flops(w)["forward"] * w.npairs / launches
+    # FP64 forward at 96^3: 24 N bytes against 192 N flops per pair, so the
+    # HBM time at 8 TB/s exceeds the MFMA time at 78.6 TF/s
+    assert pb / 8e12 > pf / 78.6e12 and r["bound"] == "hbm"
+    assert r["achieved"] == pytest.approx(pb / 2e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    # a split path is priced against its own peak
+    r = bench.roofline(w, "bf16x3", phases, steps=1)
+    assert r["mfma_peak"] == 2500.0
