@@ -281,7 +281,7 @@ def bench_ragged(args):
     for prec in precs:
         if not args.no_tune:
             for s in systems:
-                s[3].autotune(prec=prec, dtype="f64")
+                s[3].autotune(prec=prec, dtype="f64", cache_path=args.tune_cache)
         call = lambda: kx.batch_apply_exchange([s[3] for s in systems], [s[4] for s in systems],  # noqa: E731
                                                [s[2] for s in systems], [s[0].kernel for s in systems],
                                                [s[0].omega for s in systems], prec=prec, outs=outs)
