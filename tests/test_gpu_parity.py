@@ -245,6 +245,35 @@ def test_exchange_production_size_reduced_precision(torch_cuda, prec):
     g.close()
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_exchange_production_size_tuned(torch_cuda, prec):
+    """The 128-orbital 96^3 erfc workload with the launch shapes the
+    benchmark times (autotuned first, as it does): E_x and the sampled pair
+    energies against the stored oracle values, Vx psi of one orbital against
+    the oracle."""
+    torch = torch_cuda
+    name = "periodic96_erfc"
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)[name]
+    kx = _kx()
+    w, psi, occ = make_workload(name)
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    g.autotune(prec=prec, dtype="f64")
+    print(f"tuned {prec} plan {g.plan(prec)}", flush=True)
+    vx = g.apply_exchange(torch.from_numpy(psi).cuda(), occ, w.kernel, w.omega, prec=prec)
+    ex = g.exchange_energy()
+    pe = g.pair_energies(gold["pairs"])
+    print(f"tuned {prec} E_x gpu={ex!r} oracle={gold['E_x']!r}", flush=True)
+    assert abs(ex - gold["E_x"]) <= TOL64 * abs(gold["E_x"])
+    for e, r in zip(pe, gold["pair_energies"]):
+        assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * abs(gold["E_x"])
+    ref = orc.vx_orbital(psi, occ, 40, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
+    tol_f = TOL64 if prec == "fp64" else TOL32_FIELD
+    assert _rel(vx[40].cpu().numpy(), ref) <= tol_f
+    g.close()
+
+
 # ------------------------------------------------------------------ error paths
 def test_error_statuses_on_device(torch_cuda):
     torch = torch_cuda
