@@ -47,9 +47,10 @@ typedef enum {
   KX_ERR_INVALID_ARG = 1,   /* bad size, spacing, order, enum, pointer or count */
   KX_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement     */
   KX_ERR_SINGULAR = 3,      /* unscreened kernel with a zero eigenvalue of -L   */
-  KX_ERR_OUT_OF_MEMORY = 4, /* device or pinned host allocation failed          */
+  KX_ERR_OUT_OF_MEMORY = 4, /* device allocation failed                         */
   KX_ERR_DEVICE = 5,        /* a HIP runtime call failed                         */
-  KX_ERR_STATE = 6,         /* e.g. energy requested before any exchange call   */
+  KX_ERR_STATE = 6,         /* workspace not reserved, or energy requested
+                             * before any exchange call                         */
   KX_ERR_NUMERIC = 7        /* eigen-solver did not converge / non-finite input /
                              * compressed-exchange overlap not negative definite */
 } kx_status;
@@ -73,8 +74,8 @@ typedef enum {
 /* Storage type of psi / rho / phi / vxpsi. */
 typedef enum { KX_F64 = 0, KX_F32 = 1 } kx_dtype;
 
-/* Opaque handle: owns the device copies of V_k and lam_k, the cached f table,
- * the pair schedule and the intermediate workspace. */
+/* Opaque handle: owns the device copies of V_k and lam_k, the f table, the
+ * pair schedule and the intermediate workspace. */
 typedef struct kx_grid kx_grid;
 
 /* Build L_1, L_2, L_3 (Sec. III, Eq. (12)) and diagonalise each on the device
@@ -91,12 +92,31 @@ typedef struct kx_grid kx_grid;
 kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
                              const int bc[3], void* hip_stream, kx_grid** out);
 
+/* Reserve the workspace of later kx_apply_fL and kx_apply_exchange calls
+ * (the apply calls allocate nothing).  Grows the handle's buffers so that
+ *   norb > 0:  kx_apply_exchange on up to norb orbitals, and
+ *   norb == 0: kx_apply_fL on batches of fields (any batch size; fields are
+ *              processed in launches of at most the handle's batch size),
+ * in precision prec on storage dtype; earlier reservations are kept (a call
+ * never shrinks them).  Per launch slot the intermediates take 8 bytes per
+ * value of the padded grid (plus 4 for KX_PREC_MIXED); an exchange reservation
+ * adds the pair schedule and pair energies (16 bytes per pair) and, for
+ * reduced precision on KX_F64 storage, FP32 copies of psi and Vx psi
+ * (8*norb*N bytes).  Synchronises the stream when a buffer grows; a grown
+ * buffer replaces the old one, so work recorded earlier into a graph must
+ * not be replayed after a call that grew the workspace.
+ *   norb  0 .. 65535 */
+kx_status kx_reserve(kx_grid* g, int norb, int prec, int dtype);
+
 /* phi = f(-L) rho for a batch of fields (Eqs. (20)-(21)).
  *   kernel, omega  see above; omega > 0 required for KX_KERNEL_ERFC
  *   batch          number of fields, >= 0 (0 is a no-op)
  *   dtype          storage of rho / phi: KX_F64 or KX_F32
  *   prec           arithmetic of the mode products (kx_prec).
  *   rho_dev        batch*N input values;  phi_dev  batch*N outputs (overwritten)
+ * Enqueues kernels only (no allocation, host transfer or synchronisation), so
+ * the call can be recorded into a caller's HIP graph.  KX_ERR_STATE if
+ * kx_reserve was not called for prec and dtype.
  * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic. */
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
                       const void* rho_dev, void* phi_dev, int prec);
@@ -110,15 +130,22 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
  *   dtype, prec  as for kx_apply_fL.  With KX_PREC_FP32, KX_PREC_BF16X3,
  *              KX_PREC_FP16X3 or KX_PREC_MIXED on KX_F64 storage the orbitals are rounded to
  *              FP32 once for the inverse pass and Vx psi is accumulated in
- *              FP32 before it is widened into vxpsi_dev (the handle keeps
- *              8*norb*N bytes of FP32 copies).  KX_PREC_MIXED forms the pair
+ *              FP32 before it is widened into vxpsi_dev (the FP32 copies
+ *              reserved by kx_reserve).  KX_PREC_MIXED forms the pair
  *              products and all energies from the FP64 orbitals in FP64.
  *   psi_dev    norb*N orbitals (read only)
  *   vxpsi_dev  norb*N outputs, overwritten (not accumulated into)
  * Also prepares E_x = -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h with
  * (u,v)_h = h1 h2 h3 sum_r u v (Eqs. (4), (9)) and the per-pair energies,
  * read back by kx_exchange_energy / kx_pair_energies.  The reduction order is
- * fixed: results are bitwise reproducible run to run. */
+ * fixed: results are bitwise reproducible run to run, and do not depend on
+ * the batch size.
+ * Enqueues kernels only: the f table, the pair schedule and the occupations
+ * (as kernel arguments) are written by kernels, so the call allocates
+ * nothing, makes no host transfer or synchronisation and can be recorded
+ * into a caller's HIP graph (the recorded work carries occ_host's values).
+ * KX_ERR_STATE if kx_reserve was not called for at least norb orbitals in
+ * prec and dtype. */
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
                             const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                             int prec);
@@ -133,6 +160,7 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
  *   dtype, prec      shared by all systems
  *   psi_dev, occ_host, vxpsi_dev  per system, as for kx_apply_exchange
  *   ex_out           NULL or nsys doubles: E_x per system
+ * Reserves each handle's workspace as kx_reserve does.
  * Synchronises before returning; afterwards kx_exchange_energy and
  * kx_pair_energies on each handle report that system.  Validation and all
  * allocation happen before any recorded work; on error no system is
@@ -186,16 +214,17 @@ kx_status kx_pair_energies(kx_grid* g, int npairs, const int* pairs_host, double
  *   psi_dev, w_dev  norb*N device fields, orbital k at k*N
  *   xi_dev      norb*N device output (not aliasing psi_dev or w_dev)
  * KX_ERR_NUMERIC if -M is not positive definite (xi is not written then).
- * Synchronises the stream once (to read the factorisation status); the
- * small matrices and partial sums live in the handle's workspace, which
- * grows on first use. */
+ * Synchronises the stream once (to read the factorisation status).  The
+ * small matrices and partial sums live in the handle, grown here to also
+ * cover kx_ace_apply on up to 4096 fields with up to norb vectors. */
 kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, const void* w_dev,
                        void* xi_dev);
 
 /* out_v = V_ACE phi_v = -sum_k xi_k (xi_k, phi_v)_h for nvec fields.
  *   xi_dev      norb*N (from kx_ace_build), phi_dev nvec*N, out_dev nvec*N
  *               (out_dev must not alias xi_dev or phi_dev); nvec 1 .. 4096
- * Enqueued on the handle's stream; no synchronisation. */
+ * Enqueued on the handle's stream: no allocation or synchronisation.
+ * KX_ERR_STATE if no kx_ace_build on this handle had at least norb orbitals. */
 kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int nvec,
                        const void* phi_dev, void* out_dev);
 

@@ -61,40 +61,63 @@ void laplacian_1d(int n, double h, int order, int bc, double* L) {
   }
 }
 
-// Symmetric pairs i <= j grouped into batches with no orbital shared between
-// two pairs of a batch: first all diagonal pairs (i, i), then the rounds of a
-// round-robin tournament on norb (plus a dummy when norb is odd), each batch
-// optionally cut to max_batch pairs.
-void build_schedule(int norb, int max_batch, std::vector<Item>& pairs, std::vector<int>& offsets) {
-  pairs.clear();
+// Batch offsets of the pair schedule of norb orbitals (the launch order that
+// launch_schedule writes on the device: the diagonal pairs, then the rounds of
+// the round-robin tournament): each group is cut into ceil(size / cap) batches
+// of near-equal size (cap <= 0: no cut).  No orbital appears twice in a batch.
+void schedule_offsets(int norb, int cap, std::vector<int>& offsets) {
   offsets.clear();
-  auto flush_round = [&](const std::vector<Item>& round) {
-    size_t k = 0;
-    while (k < round.size()) {
-      const size_t take =
-          max_batch > 0 ? std::min(round.size() - k, (size_t)max_batch) : round.size() - k;
-      offsets.push_back((int)pairs.size());
-      pairs.insert(pairs.end(), round.begin() + k, round.begin() + k + take);
-      k += take;
+  int pos = 0;
+  auto cut = [&](int size) {
+    if (size <= 0) return;
+    const int parts = cap > 0 ? (size + cap - 1) / cap : 1;
+    const int base = size / parts, extra = size % parts;
+    for (int k = 0; k < parts; ++k) {
+      offsets.push_back(pos);
+      pos += base + (k < extra ? 1 : 0);
     }
   };
-  std::vector<Item> round;
-  for (int i = 0; i < norb; ++i) round.push_back({i, i});
-  flush_round(round);
+  cut(norb);
   const int m = (norb + 1) & ~1;
-  for (int r = 0; r < m - 1; ++r) {
-    round.clear();
-    for (int k = 0; k < m / 2; ++k) {
-      const int pa = k, pb = m - 1 - k;
-      const int p0 = (pa == 0) ? 0 : 1 + (pa - 1 + r) % (m - 1);
-      const int q0 = 1 + (pb - 1 + r) % (m - 1);
-      const int i = std::min(p0, q0), j = std::max(p0, q0);
-      if (j < norb) round.push_back({i, j});
-    }
-    flush_round(round);
-  }
-  offsets.push_back((int)pairs.size());
+  for (int r = 0; r + 1 < m; ++r) cut(norb / 2);
+  offsets.push_back(pos);
 }
+
+// The same order on the host (kx_pair_schedule).
+void schedule_pairs(int norb, std::vector<Item>& pairs) {
+  pairs.clear();
+  for (int i = 0; i < norb; ++i) pairs.push_back({i, i});
+  const int m = (norb + 1) & ~1;
+  for (int r = 0; r + 1 < m; ++r)
+    for (int k = 0; k < m / 2; ++k) {
+      const Item p = rr_pair(m, r, k);
+      if (p.j < norb) pairs.push_back(p);
+    }
+}
+
+// Device buffers one exchange application (or one batch of fields) works in,
+// with the number of values each holds.  The handle owns one set (grown only
+// by kx_reserve, kx_autotune and the batch entry point).
+struct Work {
+  void* T = nullptr;         // intermediates: slots fields of Geom::slot values
+  float* T2 = nullptr;       // the mixed path's FP32 copy of the pencil's result
+  double* epart = nullptr;   // per-strip energy partials, slots * nstrips
+  unsigned* tmax = nullptr;  // split-FP16 per-item result maxima, slots
+  Item* fitems = nullptr;    // (b, -1), b < slots: the items of a batch of fields
+  int slots = 0;             // items per launch
+  size_t tbytes = 0;         // bytes per slot of T (8- or 4-byte values)
+  Item* items = nullptr;     // pair schedule
+  long long items_cap = 0;
+  double* pairE = nullptr;   // pair energies, upper-triangle index
+  long long pairE_cap = 0;
+  double* occ = nullptr;     // occupations
+  int occ_cap = 0;
+  float* omax = nullptr;     // split-FP16 per-vector largest magnitudes
+  int omax_cap = 0;
+  float* psi32 = nullptr;    // FP32 working copies of psi and Vx psi
+  float* vx32 = nullptr;
+  size_t work32_cap = 0;
+};
 
 }  // namespace
 
@@ -104,10 +127,10 @@ struct kx_grid {
   double h[3];
   int order;
   int bc[3];
+  int device = 0;  // the device current at set-up
   hipStream_t stream;
   Geom geom;
   Plan plan_d, plan_f, plan_s;  // launch shapes: double / float / split-bf16 operands
-  // eigensystems (device): padded V, V^T, lambda per axis
   // folded eigen-blocks per axis (device): even / odd halves and transposes
   double* dVE[3] = {nullptr, nullptr, nullptr};
   double* dVO[3] = {nullptr, nullptr, nullptr};
@@ -130,47 +153,17 @@ struct kx_grid {
   short* hVO[3] = {nullptr, nullptr, nullptr};
   short* hVET[3] = {nullptr, nullptr, nullptr};
   short* hVOT[3] = {nullptr, nullptr, nullptr};
-  // split-FP16 scales: per-vector largest magnitudes, per-item result maxima
-  float* dOmax = nullptr;
-  int omax_cap = 0;
-  unsigned* dTmax = nullptr;
-  int tmax_cap = 0;
   // full eigensystem per axis (host), lam ascending, V[i*n + a]
   std::vector<double> lam_host[3];
   std::vector<double> V_host[3];
-  // f table cache
+  // f table, filled for the requested kernel by every application
   double* dF = nullptr;
-  int f_kernel = -1;
-  double f_omega = 0.0;
-  // workspace
-  double* dT = nullptr;
-  float* dT2 = nullptr;  // FP32 intermediate of the mixed path (slots2 slots)
-  int slots2 = 0;
-  int slots = 0;
-  double* dEpart = nullptr;
-  int epart_slots = 0;
-  int max_slots = 64;
-  // item lists (device), cached by their key
-  Item* dItems = nullptr;
-  size_t items_cap = 0;
-  int items_key_kind = -1;  // 0 = fields (batch), 1 = pair schedule (norb)
-  int items_key = -1;
-  int items_maxb = -1;
-  std::vector<Item> sched_pairs;
-  std::vector<int> sched_offsets;
-  // exchange results
-  double* dOcc = nullptr;
-  int occ_cap = 0;
-  double* hOcc = nullptr;  // pinned staging
-  hipEvent_t occ_done = nullptr;
-  double* dPairE = nullptr;
-  // FP32 working copies of psi and Vx psi for reduced-precision exchange on
-  // FP64 storage (elements each)
-  float* dPsi32 = nullptr;
-  float* dVx32 = nullptr;
-  size_t work32_cap = 0;
-  long long pairE_cap = 0;
+  // workspace (grown by kx_reserve) and results
+  Work ws;
+  int max_slots = 64;   // largest batch of pairs / fields per launch
+  int batch_cap = 64;   // pairs per launch of the exchange schedule (<= max_slots)
   double* dEx = nullptr;
+  const double* last_pairE = nullptr;  // where the last application left its pair energies
   // compressed exchange: gram partial sums, the small matrix (overwritten by
   // its Cholesky factor), the factor's inverse, the (xi, phi) coefficients
   double* dAcePart = nullptr;
@@ -180,6 +173,7 @@ struct kx_grid {
   long long ace_mat_cap = 0;
   double* dAceG = nullptr;
   long long ace_g_cap = 0;
+  int ace_norb = 0;  // largest orbital count kx_ace_apply is reserved for
   int* dAceStatus = nullptr;
   int last_norb = -1;
   // optional per-launch timing (hipEvents on the handle's stream)
@@ -350,83 +344,153 @@ kx_status check_types(const kx_grid* g, int dtype, int prec) {
   return KX_OK;
 }
 
-kx_status ensure_ftable(kx_grid* g, int kernel, double omega) {
-  const double om = (kernel == KX_KERNEL_ERFC) ? omega : 0.0;
-  if (g->dF && g->f_kernel == kernel && g->f_omega == om) return KX_OK;
-  if (!g->dF) {
-    ++g->gen;
-    kx_status st = dev_alloc((void**)&g->dF, sizeof(double) * g->geom.fsize);
-    if (st != KX_OK) return st;
+// True while work on stream s is being recorded into a graph.
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
   }
+  return cs == hipStreamCaptureStatusActive;
+}
+
+// f(lam1_a + lam2_b + lam3_c) for the requested kernel, written by a kernel
+// into the handle's table (every application writes it, so that work
+// recorded into a graph carries its own table).
+hipError_t fill_ftable(kx_grid* g, int kernel, double omega, hipStream_t s) {
+  const double om = (kernel == KX_KERNEL_ERFC) ? omega : 0.0;
   const double* le[3] = {g->dLamE[0], g->dLamE[1], g->dLamE[2]};
   const double* lo[3] = {g->dLamO[0], g->dLamO[1], g->dLamO[2]};
-  KX_HIP(launch_ftable(le, lo, g->geom, kernel, om, g->dF, g->stream));
-  g->f_kernel = kernel;
-  g->f_omega = om;
-  return KX_OK;
+  return launch_ftable(le, lo, g->geom, kernel, om, g->dF, s);
 }
 
-kx_status ensure_workspace(kx_grid* g, int slots) {
-  if (slots <= g->slots) return KX_OK;
+// Bytes of one slot of the intermediate for precision prec.
+size_t t_bytes(const Geom& G, int prec) {
+  const bool dbl = prec == KX_PREC_FP64 || prec == KX_PREC_MIXED;
+  return (dbl ? sizeof(double) : sizeof(float)) * (size_t)G.slot;
+}
+
+// Grow the handle's per-launch buffers to `slots` items: T (8-byte values, so
+// that every precision fits), the energy partials, the field items, and, when
+// asked, the mixed path's FP32 copy and the split-FP16 result maxima.  The
+// padded rows of the intermediates are never written by the transform kernels
+// and are cleared here, by a kernel.  May synchronise the stream.
+kx_status reserve_slots(kx_grid* g, int slots, bool t2, bool aux16) {
+  Work& w = g->ws;
+  const Geom& G = g->geom;
+  const bool grow_t = slots > w.slots;
+  const bool grow_t2 = t2 && (grow_t || !w.T2);
+  const bool grow_aux = aux16 && (grow_t || !w.tmax);
+  if (!grow_t && !grow_t2 && !grow_aux) return KX_OK;
   // the previous buffers may still be in use by queued work
   KX_HIP(hipStreamSynchronize(g->stream));
-  dev_free(g->dT);
-  dev_free(g->dEpart);
-  g->dT = nullptr;
-  g->dEpart = nullptr;
-  g->slots = 0;
   ++g->gen;
-  kx_status st = dev_alloc((void**)&g->dT, sizeof(double) * (size_t)g->geom.slot * slots);
-  if (st != KX_OK) return st;
-  // padded rows are never written by the kernels; keep them zero
-  KX_HIP(hipMemsetAsync(g->dT, 0, sizeof(double) * (size_t)g->geom.slot * slots, g->stream));
-  const size_t nstrips = (size_t)(g->geom.slab / kTile);
-  st = dev_alloc((void**)&g->dEpart, sizeof(double) * nstrips * slots);
-  if (st != KX_OK) return st;
-  g->slots = slots;
+  const int ns = std::max(slots, w.slots);
+  if (grow_t) {
+    dev_free(w.T);
+    dev_free(w.epart);
+    dev_free(w.fitems);
+    w.T = nullptr;
+    w.epart = nullptr;
+    w.fitems = nullptr;
+    w.slots = 0;
+    const size_t tb = sizeof(double) * (size_t)G.slot * ns;
+    kx_status st = dev_alloc(&w.T, tb);
+    if (st != KX_OK) return st;
+    KX_HIP(launch_zero(w.T, tb, g->stream));
+    const size_t nstrips = (size_t)(G.slab / kTile);
+    st = dev_alloc((void**)&w.epart, sizeof(double) * nstrips * ns);
+    if (st != KX_OK) return st;
+    st = dev_alloc((void**)&w.fitems, sizeof(Item) * ns);
+    if (st != KX_OK) return st;
+    KX_HIP(launch_field_items(ns, w.fitems, g->stream));
+    w.slots = ns;
+    w.tbytes = sizeof(double) * (size_t)G.slot;
+  }
+  if (grow_t2 || (w.T2 && grow_t)) {
+    dev_free(w.T2);
+    w.T2 = nullptr;
+    const size_t b = sizeof(float) * (size_t)G.slot * ns;
+    kx_status st = dev_alloc((void**)&w.T2, b);
+    if (st != KX_OK) return st;
+    KX_HIP(launch_zero(w.T2, b, g->stream));
+  }
+  if (grow_aux || (w.tmax && grow_t)) {
+    dev_free(w.tmax);
+    w.tmax = nullptr;
+    kx_status st = dev_alloc((void**)&w.tmax, sizeof(unsigned) * ns);
+    if (st != KX_OK) return st;
+  }
   return KX_OK;
 }
 
-// Scale buffers of the split-FP16 path: nvec per-vector maxima, slots
-// per-item maxima.
-kx_status ensure_aux16(kx_grid* g, int nvec, int slots) {
-  if (nvec > g->omax_cap) {
-    KX_HIP(hipStreamSynchronize(g->stream));
-    ++g->gen;
-    dev_free(g->dOmax);
-    g->dOmax = nullptr;
-    g->omax_cap = 0;
-    kx_status st = dev_alloc((void**)&g->dOmax, sizeof(float) * nvec);
-    if (st != KX_OK) return st;
-    g->omax_cap = nvec;
-  }
-  if (slots > g->tmax_cap) {
-    KX_HIP(hipStreamSynchronize(g->stream));
-    ++g->gen;
-    dev_free(g->dTmax);
-    g->dTmax = nullptr;
-    g->tmax_cap = 0;
-    kx_status st = dev_alloc((void**)&g->dTmax, sizeof(unsigned) * slots);
-    if (st != KX_OK) return st;
-    g->tmax_cap = slots;
-  }
-  return KX_OK;
-}
-
-// The FP32 copy of the intermediate that the mixed path's inverse pass reads.
-kx_status ensure_t2(kx_grid* g, int slots) {
-  if (slots <= g->slots2) return KX_OK;
+// grow a device array to n elements of `size` bytes (contents not kept)
+template <class T>
+kx_status grow(kx_grid* g, T** p, long long* cap, long long n) {
+  if (n <= *cap) return KX_OK;
   KX_HIP(hipStreamSynchronize(g->stream));
-  dev_free(g->dT2);
-  g->dT2 = nullptr;
-  g->slots2 = 0;
   ++g->gen;
-  kx_status st = dev_alloc((void**)&g->dT2, sizeof(float) * (size_t)g->geom.slot * slots);
+  dev_free(*p);
+  *p = nullptr;
+  *cap = 0;
+  kx_status st = dev_alloc((void**)p, sizeof(T) * (size_t)std::max<long long>(n, 1));
   if (st != KX_OK) return st;
-  // padded rows are never written by the kernels; keep them zero
-  KX_HIP(hipMemsetAsync(g->dT2, 0, sizeof(float) * (size_t)g->geom.slot * slots, g->stream));
-  g->slots2 = slots;
+  *cap = n;
   return KX_OK;
+}
+
+// Every buffer an exchange application on up to norb orbitals (or, with
+// norb == 0, batches of fields) in precision prec on storage dtype needs.
+kx_status reserve(kx_grid* g, int norb, int prec, int dtype) {
+  const int slots = norb > 0 ? std::min(g->max_slots, norb) : g->max_slots;
+  kx_status st = reserve_slots(g, slots, prec == KX_PREC_MIXED, prec == KX_PREC_FP16X3);
+  if (st != KX_OK) return st;
+  Work& w = g->ws;
+  if (prec == KX_PREC_FP16X3) {  // one scale per orbital, or per field of a launch
+    long long cap = w.omax_cap;
+    st = grow(g, &w.omax, &cap, std::max(norb, w.slots));
+    if (st != KX_OK) return st;
+    w.omax_cap = (int)cap;
+  }
+  if (norb == 0) return KX_OK;
+  const long long npairs = (long long)norb * (norb + 1) / 2;
+  long long cap = w.items_cap;
+  st = grow(g, &w.items, &cap, npairs);
+  if (st != KX_OK) return st;
+  w.items_cap = cap;
+  cap = w.pairE_cap;
+  st = grow(g, &w.pairE, &cap, npairs);
+  if (st != KX_OK) return st;
+  w.pairE_cap = cap;
+  cap = w.occ_cap;
+  st = grow(g, &w.occ, &cap, norb);
+  if (st != KX_OK) return st;
+  w.occ_cap = (int)cap;
+  if (prec != KX_PREC_FP64 && dtype == KX_F64) {
+    const long long nel = (long long)norb * g->geom.N;
+    long long c1 = (long long)w.work32_cap, c2 = (long long)w.work32_cap;
+    st = grow(g, &w.psi32, &c1, nel);
+    if (st != KX_OK) return st;
+    st = grow(g, &w.vx32, &c2, nel);
+    if (st != KX_OK) return st;
+    w.work32_cap = (size_t)std::min(c1, c2);
+  }
+  return KX_OK;
+}
+
+void free_work(Work& w) {
+  dev_free(w.T);
+  dev_free(w.T2);
+  dev_free(w.epart);
+  dev_free(w.tmax);
+  dev_free(w.fitems);
+  dev_free(w.items);
+  dev_free(w.pairE);
+  dev_free(w.occ);
+  dev_free(w.omax);
+  dev_free(w.psi32);
+  dev_free(w.vx32);
+  w = Work();
 }
 
 // Bracket one kernel launch with timing events when profiling is on.
@@ -449,43 +513,43 @@ hipError_t timed(kx_grid* g, hipStream_t s, int kind, F&& launch) {
 }
 
 // One batch of nb items through the three transform passes (and, for the
-// exchange, the per-pair energy reduction), in the arithmetic of prec.
-// src (the forward pass input) has storage src_dtype; psi and dst (the
-// inverse pass) have storage dtype.
-hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dtype,
+// exchange, the per-pair energy reduction), in the arithmetic of prec, in the
+// buffers of w.  src (the forward pass input) has storage src_dtype; psi and
+// dst (the inverse pass) have storage dtype.
+hipError_t run_batch(kx_grid* g, const Work& w, hipStream_t st, int mode, int prec, int src_dtype,
                      const void* src, const Item* it, int nb, int dtype, const void* psi,
                      const double* occ, void* dst, int norb, double dV) {
   const Geom& G = g->geom;
-  double* epart = mode == 1 ? g->dEpart : nullptr;
+  double* epart = mode == 1 ? w.epart : nullptr;
   const int nstrips = (int)(G.slab / kTile);
   hipError_t e;
   if (prec == KX_PREC_MIXED) {
     // forward, f scaling and energies in FP64; the pencil's result rounded
     // into the FP32 intermediate; split-BF16 inverse pass
     const EigR<double> E = eig_of(g);
-    double* T = (double*)g->dT;
+    double* T = (double*)w.T;
     e = timed(g, st, KX_PHASE_FORWARD, [&] {
       return launch_forward_d(src_dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, st);
     });
     if (e != hipSuccess) return e;
     e = timed(g, st, KX_PHASE_PENCIL, [&] {
-      return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, epart, st, g->dT2);
+      return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, epart, st, w.T2);
     });
     if (e != hipSuccess) return e;
     if (mode == 1) {
       e = timed(g, st, KX_PHASE_ENERGY, [&] {
-        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, w.pairE, st);
       });
       if (e != hipSuccess) return e;
     }
     return timed(g, st, KX_PHASE_INVERSE, [&] {
-      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, eigs_of(g), g->dT2, it, nb, psi, occ,
+      return launch_inverse_s(dtype, mode, G, g->plan_s.inv, eigs_of(g), w.T2, it, nb, psi, occ,
                               dst, st);
     });
   }
   if (prec == KX_PREC_FP64) {
     const EigR<double> E = eig_of(g);
-    double* T = (double*)g->dT;
+    double* T = (double*)w.T;
     e = timed(g, st, KX_PHASE_FORWARD, [&] {
       return launch_forward_d(src_dtype, mode, G, g->plan_d.fwd, E, src, it, nb, T, st);
     });
@@ -496,7 +560,7 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
     if (e != hipSuccess) return e;
     if (mode == 1) {
       e = timed(g, st, KX_PHASE_ENERGY, [&] {
-        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, w.pairE, st);
       });
       if (e != hipSuccess) return e;
     }
@@ -510,12 +574,12 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
     SplitAux aux;
     if (h16) {  // the source maxima were computed before the batches
       aux.h16 = 1;
-      aux.omax = g->dOmax;
-      aux.tmax = g->dTmax;
-      e = launch_zero(g->dTmax, sizeof(unsigned) * nb, st);
+      aux.omax = w.omax;
+      aux.tmax = w.tmax;
+      e = launch_zero(w.tmax, sizeof(unsigned) * nb, st);
       if (e != hipSuccess) return e;
     }
-    float* T = (float*)g->dT;
+    float* T = (float*)w.T;
     e = timed(g, st, KX_PHASE_FORWARD, [&] {
       return launch_forward_s(src_dtype, mode, G, g->plan_s.fwd, E, src, it, nb, T, st, aux);
     });
@@ -526,7 +590,7 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
     if (e != hipSuccess) return e;
     if (mode == 1) {
       e = timed(g, st, KX_PHASE_ENERGY, [&] {
-        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
+        return launch_pair_energy(epart, nstrips, it, nb, norb, dV, w.pairE, st);
       });
       if (e != hipSuccess) return e;
     }
@@ -536,7 +600,7 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
     });
   }
   const EigR<float> E = eigf_of(g);
-  float* T = (float*)g->dT;
+  float* T = (float*)w.T;
   e = timed(g, st, KX_PHASE_FORWARD, [&] {
     return launch_forward_f(src_dtype, mode, G, g->plan_f.fwd, E, src, it, nb, T, st);
   });
@@ -547,7 +611,7 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
   if (e != hipSuccess) return e;
   if (mode == 1) {
     e = timed(g, st, KX_PHASE_ENERGY, [&] {
-      return launch_pair_energy(epart, nstrips, it, nb, norb, dV, g->dPairE, st);
+      return launch_pair_energy(epart, nstrips, it, nb, norb, dV, w.pairE, st);
     });
     if (e != hipSuccess) return e;
   }
@@ -556,27 +620,7 @@ hipError_t run_batch(kx_grid* g, hipStream_t st, int mode, int prec, int src_dty
   });
 }
 
-kx_status upload_items(kx_grid* g, int kind, int key, int maxb, const std::vector<Item>& items) {
-  if (g->items_key_kind == kind && g->items_key == key && g->items_maxb == maxb) return KX_OK;
-  KX_HIP(hipStreamSynchronize(g->stream));
-  if (items.size() > g->items_cap) {
-    ++g->gen;
-    dev_free(g->dItems);
-    g->dItems = nullptr;
-    g->items_cap = 0;
-    kx_status st = dev_alloc((void**)&g->dItems, sizeof(Item) * std::max<size_t>(items.size(), 1));
-    if (st != KX_OK) return st;
-    g->items_cap = items.size();
-  }
-  if (!items.empty())
-    KX_HIP(hipMemcpy(g->dItems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
-  g->items_key_kind = kind;
-  g->items_key = key;
-  g->items_maxb = maxb;
-  return KX_OK;
-}
-
-// One exchange application, resolved against the handle's buffers.
+// One exchange application, resolved against a set of buffers.
 struct XPlan {
   int kernel = 0, norb = 0, prec = 0, dtype = 0, dtype_w = 0;
   double omega = 0.0, dV = 0.0;
@@ -586,14 +630,15 @@ struct XPlan {
   const void* psi_w = nullptr;
   void* vx_w = nullptr;
   size_t nel = 0;
+  std::vector<double> occ;      // the occupations, sent to the device as kernel arguments
+  std::vector<int> offsets;     // batch offsets into the pair schedule
 };
 
-// Validate the arguments, make every buffer the application needs (workspace,
-// schedule, f table, results, working copies) and upload the occupations on
-// the handle's stream.  May synchronise the stream (allocation).
-kx_status prepare_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
-                           const void* psi_dev, const double* occ_host, void* vxpsi_dev, int prec,
-                           XPlan& xp) {
+// Validate the arguments of one exchange application and check that w holds
+// everything it needs.  Touches no device state.
+kx_status plan_exchange(const kx_grid* g, const Work& w, int kernel, double omega, int norb,
+                        int dtype, const void* psi_dev, const double* occ_host, void* vxpsi_dev,
+                        int prec, XPlan& xp) {
   if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
   kx_status st = check_kernel_args(g, kernel, omega);
   if (st != KX_OK) return st;
@@ -604,36 +649,7 @@ kx_status prepare_exchange(kx_grid* g, int kernel, double omega, int norb, int d
   if ((double)norb * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
   for (int i = 0; i < norb; ++i)
     if (!std::isfinite(occ_host[i])) return KX_ERR_INVALID_ARG;
-
   const long long npairs = (long long)norb * (norb + 1) / 2;
-  // results buffers
-  if (npairs > g->pairE_cap) {
-    KX_HIP(hipStreamSynchronize(g->stream));
-    ++g->gen;
-    dev_free(g->dPairE);
-    g->dPairE = nullptr;
-    g->pairE_cap = 0;
-    st = dev_alloc((void**)&g->dPairE, sizeof(double) * std::max<long long>(npairs, 1));
-    if (st != KX_OK) return st;
-    g->pairE_cap = npairs;
-  }
-  if (norb > g->occ_cap) {
-    KX_HIP(hipStreamSynchronize(g->stream));
-    ++g->gen;
-    dev_free(g->dOcc);
-    if (g->hOcc) (void)hipHostFree(g->hOcc);
-    g->dOcc = nullptr;
-    g->hOcc = nullptr;
-    g->occ_cap = 0;
-    st = dev_alloc((void**)&g->dOcc, sizeof(double) * norb);
-    if (st != KX_OK) return st;
-    if (hipHostMalloc((void**)&g->hOcc, sizeof(double) * norb, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      g->hOcc = nullptr;
-      return KX_ERR_OUT_OF_MEMORY;
-    }
-    g->occ_cap = norb;
-  }
   xp = XPlan();
   xp.kernel = kernel;
   xp.omega = omega;
@@ -644,94 +660,62 @@ kx_status prepare_exchange(kx_grid* g, int kernel, double omega, int norb, int d
   xp.vx = xp.vx_w = vxpsi_dev;
   xp.dV = g->h[0] * g->h[1] * g->h[2];
   if (norb == 0) return KX_OK;
-
-  // schedule (cached per norb and batch cap)
-  const int cap = g->max_slots;
-  if (!(g->items_key_kind == 1 && g->items_key == norb && g->items_maxb == cap)) {
-    build_schedule(norb, cap, g->sched_pairs, g->sched_offsets);
-  }
-  int maxb = 0;
-  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b)
-    maxb = std::max(maxb, g->sched_offsets[b + 1] - g->sched_offsets[b]);
-  st = ensure_workspace(g, maxb);
-  if (st != KX_OK) return st;
-  if (prec == KX_PREC_MIXED) {
-    st = ensure_t2(g, maxb);
-    if (st != KX_OK) return st;
-  }
-  if (prec == KX_PREC_FP16X3) {
-    st = ensure_aux16(g, norb, maxb);
-    if (st != KX_OK) return st;
-  }
-  st = ensure_ftable(g, kernel, omega);
-  if (st != KX_OK) return st;
-  st = upload_items(g, 1, norb, cap, g->sched_pairs);
-  if (st != KX_OK) return st;
-
-  // occupations: pinned staging, reused once the previous upload finished
-  KX_HIP(hipEventSynchronize(g->occ_done));
-  std::memcpy(g->hOcc, occ_host, sizeof(double) * norb);
-  KX_HIP(hipMemcpyAsync(g->dOcc, g->hOcc, sizeof(double) * norb, hipMemcpyHostToDevice, g->stream));
-  KX_HIP(hipEventRecord(g->occ_done, g->stream));
-
+  if (w.slots < 1 || w.items_cap < npairs || w.pairE_cap < npairs || w.occ_cap < norb)
+    return KX_ERR_STATE;
+  if (prec == KX_PREC_MIXED && !w.T2) return KX_ERR_STATE;
+  if (prec == KX_PREC_FP16X3 && (!w.tmax || w.omax_cap < norb)) return KX_ERR_STATE;
+  xp.occ.assign(occ_host, occ_host + norb);
+  schedule_offsets(norb, std::min(g->batch_cap, w.slots), xp.offsets);
   // Reduced precision on FP64 storage: the orbitals are rounded to FP32 once
   // and Vx psi is accumulated in FP32, then widened into the output; the
   // per-pair passes then move half the bytes.
   xp.nel = (size_t)norb * g->geom.N;
-  xp.narrow = prec != KX_PREC_FP64 && dtype == KX_F64 &&
+  xp.narrow = prec != KX_PREC_FP64 && dtype == KX_F64 && xp.nel <= w.work32_cap &&
               (reinterpret_cast<uintptr_t>(psi_dev) % 16) == 0 &&
               (reinterpret_cast<uintptr_t>(vxpsi_dev) % 16) == 0;
   if (xp.narrow) {
-    if (xp.nel > g->work32_cap) {
-      KX_HIP(hipStreamSynchronize(g->stream));
-      ++g->gen;
-      dev_free(g->dPsi32);
-      dev_free(g->dVx32);
-      g->dPsi32 = g->dVx32 = nullptr;
-      g->work32_cap = 0;
-      st = dev_alloc((void**)&g->dPsi32, sizeof(float) * xp.nel);
-      if (st != KX_OK) return st;
-      st = dev_alloc((void**)&g->dVx32, sizeof(float) * xp.nel);
-      if (st != KX_OK) return st;
-      g->work32_cap = xp.nel;
-    }
-    xp.psi_w = g->dPsi32;
-    xp.vx_w = g->dVx32;
+    xp.psi_w = w.psi32;
+    xp.vx_w = w.vx32;
     xp.dtype_w = KX_F32;
   }
   return KX_OK;
 }
 
-// The device work of one prepared exchange application, on stream s: kernels
-// only (no memset or host transfer), so it can be recorded into a graph.
-hipError_t enqueue_exchange(kx_grid* g, const XPlan& xp, hipStream_t s) {
+// The device work of one planned exchange application on stream s: kernels
+// only (no allocation, host transfer, memset or synchronisation), so it can
+// be recorded into a graph.  The f table, the pair schedule and the
+// occupations are written by kernels first.
+hipError_t enqueue_exchange(kx_grid* g, const XPlan& xp, const Work& w, hipStream_t s) {
   if (xp.norb == 0) return launch_zero(g->dEx, sizeof(double), s);
-  hipError_t e;
+  hipError_t e = fill_ftable(g, xp.kernel, xp.omega, s);
+  if (e == hipSuccess) e = launch_schedule(xp.norb, w.items, s);
+  if (e == hipSuccess) e = launch_put_doubles(xp.occ.data(), xp.norb, w.occ, s);
+  if (e != hipSuccess) return e;
   if (xp.narrow) {
-    e = launch_narrow((const double*)xp.psi, g->dPsi32, (long long)xp.nel, s);
+    e = launch_narrow((const double*)xp.psi, w.psi32, (long long)xp.nel, s);
     if (e != hipSuccess) return e;
   }
   e = launch_zero(xp.vx_w, elem_size(xp.dtype_w) * xp.nel, s);
   if (e != hipSuccess) return e;
   if (xp.prec == KX_PREC_FP16X3) {  // the orbitals' largest magnitudes set the FP16 scales
-    e = launch_absmax(xp.psi_w, xp.dtype_w, (long long)g->geom.N, xp.norb, g->dOmax, s);
+    e = launch_absmax(xp.psi_w, xp.dtype_w, (long long)g->geom.N, xp.norb, w.omax, s);
     if (e != hipSuccess) return e;
   }
-  for (size_t b = 0; b + 1 < g->sched_offsets.size(); ++b) {
-    const int o0 = g->sched_offsets[b], nb = g->sched_offsets[b + 1] - o0;
+  // the mixed path's FP64 forward pass reads the caller's orbitals
+  const bool mixed = xp.prec == KX_PREC_MIXED;
+  for (size_t b = 0; b + 1 < xp.offsets.size(); ++b) {
+    const int o0 = xp.offsets[b], nb = xp.offsets[b + 1] - o0;
     if (nb <= 0) continue;
-    // the mixed path's FP64 forward pass reads the caller's orbitals
-    const bool mixed = xp.prec == KX_PREC_MIXED;
-    e = run_batch(g, s, 1, xp.prec, mixed ? xp.dtype : xp.dtype_w, mixed ? xp.psi : xp.psi_w,
-                  g->dItems + o0, nb, xp.dtype_w, xp.psi_w, g->dOcc, xp.vx_w, xp.norb, xp.dV);
+    e = run_batch(g, w, s, 1, xp.prec, mixed ? xp.dtype : xp.dtype_w, mixed ? xp.psi : xp.psi_w,
+                  w.items + o0, nb, xp.dtype_w, xp.psi_w, w.occ, xp.vx_w, xp.norb, xp.dV);
     if (e != hipSuccess) return e;
   }
   if (xp.narrow) {
-    e = launch_widen(g->dVx32, (double*)xp.vx, (long long)xp.nel, s);
+    e = launch_widen(w.vx32, (double*)xp.vx, (long long)xp.nel, s);
     if (e != hipSuccess) return e;
   }
   return timed(g, s, KX_PHASE_ENERGY, [&] {
-    return launch_exchange_energy(g->dPairE, g->dOcc, xp.norb, g->dEx, s);
+    return launch_exchange_energy(w.pairE, w.occ, xp.norb, g->dEx, s);
   });
 }
 
@@ -792,13 +776,9 @@ kx_status kx_pair_schedule(int norb, int max_batch, int* npairs_out, int* nbatch
                            int* pairs_out, int* batch_offsets_out) {
   if (norb < 0 || norb > 65535 || !npairs_out || !nbatches_out) return KX_ERR_INVALID_ARG;
   std::vector<Item> pairs;
-  std::vector<int> offs;
-  build_schedule(norb, max_batch, pairs, offs);
-  // drop empty batches (norb == 0)
   std::vector<int> o2;
-  for (size_t b = 0; b + 1 < offs.size(); ++b)
-    if (offs[b + 1] > offs[b]) o2.push_back(offs[b]);
-  o2.push_back((int)pairs.size());
+  schedule_pairs(norb, pairs);
+  schedule_offsets(norb, max_batch, o2);
   *npairs_out = (int)pairs.size();
   *nbatches_out = (int)o2.size() - 1;
   if (pairs_out) {
@@ -835,6 +815,11 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
   }
   g->order = fd_order;
   g->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    return KX_ERR_DEVICE;
+  }
   Geom& G = g->geom;
   G.n1 = n[0];
   G.n2 = n[1];
@@ -876,6 +861,7 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
     const int v = std::atoi(env);
     if (v >= 1 && v <= 4096) g->max_slots = v;
   }
+  g->batch_cap = g->max_slots;
 
   auto fail = [&](kx_status st) {
     kx_destroy(g);
@@ -1072,12 +1058,9 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
     }
   }
   cleanup();
-  if (dev_alloc((void**)&g->dEx, sizeof(double) * 2) != KX_OK) return fail(KX_ERR_OUT_OF_MEMORY);
-  if (hipEventCreateWithFlags(&g->occ_done, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    g->occ_done = nullptr;
-    return fail(KX_ERR_DEVICE);
-  }
+  if (dev_alloc((void**)&g->dEx, sizeof(double) * 2) != KX_OK ||
+      dev_alloc((void**)&g->dF, sizeof(double) * (size_t)G.fsize) != KX_OK)
+    return fail(KX_ERR_OUT_OF_MEMORY);
   *out = g;
   return KX_OK;
 }
@@ -1106,29 +1089,26 @@ kx_status kx_destroy(kx_grid* g) {
     dev_free(g->hVET[k]);
     dev_free(g->hVOT[k]);
   }
-  dev_free(g->dOmax);
-  dev_free(g->dTmax);
+  free_work(g->ws);
   dev_free(g->dF);
-  dev_free(g->dT);
-  dev_free(g->dT2);
-  dev_free(g->dEpart);
-  dev_free(g->dItems);
-  dev_free(g->dOcc);
-  dev_free(g->dPairE);
   dev_free(g->dEx);
   dev_free(g->dAcePart);
   dev_free(g->dAceA);
   dev_free(g->dAceLinv);
   dev_free(g->dAceG);
   dev_free(g->dAceStatus);
-  dev_free(g->dPsi32);
-  dev_free(g->dVx32);
-  if (g->hOcc) (void)hipHostFree(g->hOcc);
-  if (g->occ_done) (void)hipEventDestroy(g->occ_done);
   for (hipEvent_t ev : g->prof_ev) (void)hipEventDestroy(ev);
   (void)hipGetLastError();
   delete g;
   return KX_OK;
+}
+
+kx_status kx_reserve(kx_grid* g, int norb, int prec, int dtype) {
+  if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
+  kx_status st = check_types(g, dtype, prec);
+  if (st != KX_OK) return st;
+  if ((double)norb * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
+  return reserve(g, norb, prec, dtype);
 }
 
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
@@ -1142,30 +1122,28 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   if (!rho_dev || !phi_dev) return KX_ERR_INVALID_ARG;
   if ((double)batch * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
   if (rho_dev == phi_dev) return KX_ERR_INVALID_ARG;
+  const Work& w = g->ws;
+  if (w.slots < 1 || (prec == KX_PREC_MIXED && !w.T2) || (prec == KX_PREC_FP16X3 && !w.tmax))
+    return KX_ERR_STATE;
+  // FP16 scales: one per field of a launch, kept in the per-item maxima's
+  // companion array sized by the launch
+  if (prec == KX_PREC_FP16X3 && w.omax_cap < w.slots) return KX_ERR_STATE;
 
-  const int chunk = std::min(batch, g->max_slots);
-  st = ensure_workspace(g, chunk);
-  if (st != KX_OK) return st;
-  if (prec == KX_PREC_MIXED) {
-    st = ensure_t2(g, chunk);
-    if (st != KX_OK) return st;
-  }
-  st = ensure_ftable(g, kernel, omega);
-  if (st != KX_OK) return st;
-  std::vector<Item> items(batch);
-  for (int b = 0; b < batch; ++b) items[b] = {b, -1};
-  st = upload_items(g, 0, batch, chunk, items);
-  if (st != KX_OK) return st;
-  if (prec == KX_PREC_FP16X3) {  // the fields' largest magnitudes set the FP16 scales
-    st = ensure_aux16(g, batch, chunk);
-    if (st != KX_OK) return st;
-    KX_HIP(launch_absmax(rho_dev, dtype, (long long)g->geom.N, batch, g->dOmax, g->stream));
-  }
+  hipStream_t s = g->stream;
+  g->capturing = stream_capturing(s);
+  KX_HIP(fill_ftable(g, kernel, omega, s));
+  const int chunk = std::min(batch, w.slots);
+  const size_t fb = elem_size(dtype) * (size_t)g->geom.N;
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
-    KX_HIP(run_batch(g, g->stream, 0, prec, dtype, rho_dev, g->dItems + b0, nb, dtype, nullptr,
-                     nullptr, phi_dev, 0, 0.0));
+    const void* src = static_cast<const char*>(rho_dev) + fb * b0;
+    void* dst = static_cast<char*>(phi_dev) + fb * b0;
+    if (prec == KX_PREC_FP16X3)  // the fields' largest magnitudes set the FP16 scales
+      KX_HIP(launch_absmax(src, dtype, (long long)g->geom.N, nb, w.omax, s));
+    KX_HIP(run_batch(g, w, s, 0, prec, dtype, src, w.fitems, nb, dtype, nullptr, nullptr, dst, 0,
+                     0.0));
   }
+  g->capturing = false;
   return KX_OK;
 }
 
@@ -1174,11 +1152,15 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
                             int prec) {
   if (!g) return KX_ERR_INVALID_ARG;
   XPlan xp;
-  kx_status st = prepare_exchange(g, kernel, omega, norb, dtype, psi_dev, occ_host, vxpsi_dev, prec,
-                                  xp);
+  kx_status st = plan_exchange(g, g->ws, kernel, omega, norb, dtype, psi_dev, occ_host, vxpsi_dev,
+                               prec, xp);
   if (st != KX_OK) return st;
-  KX_HIP(enqueue_exchange(g, xp, g->stream));
+  g->capturing = stream_capturing(g->stream);
+  const hipError_t e = enqueue_exchange(g, xp, g->ws, g->stream);
+  g->capturing = false;
+  KX_HIP(e);
   g->last_norb = norb;
+  g->last_pairE = g->ws.pairE;
   return KX_OK;
 }
 
@@ -1195,12 +1177,23 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
       if (grids[m] == grids[k]) return KX_ERR_INVALID_ARG;  // one workspace per system
   }
   std::vector<XPlan> xps(nsys);
-  for (int k = 0; k < nsys; ++k) {
-    kx_status st = prepare_exchange(grids[k], kernels[k], omegas[k], norbs[k], dtype, psi_dev[k],
-                                    occ_host[k], vxpsi_dev[k], prec, xps[k]);
+  for (int k = 0; k < nsys; ++k) {  // validation first, then the workspaces
+    kx_status st = check_types(grids[k], dtype, prec);
+    if (st != KX_OK) return st;
+    if (norbs[k] < 0 || norbs[k] > 65535) return KX_ERR_INVALID_ARG;
+    Work none;
+    st = plan_exchange(grids[k], none, kernels[k], omegas[k], 0, dtype, psi_dev[k], occ_host[k],
+                       vxpsi_dev[k], prec, xps[k]);
     if (st != KX_OK) return st;
   }
-  // uploads and any earlier work on the systems' own streams come first
+  for (int k = 0; k < nsys; ++k) {
+    kx_status st = reserve(grids[k], norbs[k], prec, dtype);
+    if (st == KX_OK)
+      st = plan_exchange(grids[k], grids[k]->ws, kernels[k], omegas[k], norbs[k], dtype,
+                         psi_dev[k], occ_host[k], vxpsi_dev[k], prec, xps[k]);
+    if (st != KX_OK) return st;
+  }
+  // any earlier work on the systems' own streams comes first
   for (int k = 0; k < nsys; ++k) KX_HIP(hipStreamSynchronize(grids[k]->stream));
 
   kx_grid* o = grids[0];
@@ -1212,7 +1205,14 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
     key.insert(key.end(), {grids[k]->id, grids[k]->gen, (unsigned long long)kernels[k], om,
                            (unsigned long long)norbs[k], (unsigned long long)prec,
                            (unsigned long long)dtype, (unsigned long long)(uintptr_t)psi_dev[k],
-                           (unsigned long long)(uintptr_t)vxpsi_dev[k]});
+                           (unsigned long long)(uintptr_t)vxpsi_dev[k],
+                           (unsigned long long)grids[k]->batch_cap});
+    // the occupations travel as kernel arguments of the recorded work
+    for (int i = 0; i < norbs[k]; ++i) {
+      unsigned long long o;
+      std::memcpy(&o, &occ_host[k][i], sizeof o);
+      key.push_back(o);
+    }
   }
   if (!(b.exec && b.key == key)) {
     release_batch_graph(o, false);
@@ -1233,7 +1233,7 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
       e = hipStreamWaitEvent(b.branch[k], b.fork, 0);
       if (e != hipSuccess) break;
       grids[k]->capturing = true;
-      e = enqueue_exchange(grids[k], xps[k], b.branch[k]);
+      e = enqueue_exchange(grids[k], xps[k], grids[k]->ws, b.branch[k]);
       grids[k]->capturing = false;
       if (e != hipSuccess) break;
       e = hipEventRecord(b.join[k], b.branch[k]);
@@ -1258,6 +1258,7 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
   KX_HIP(hipStreamSynchronize(b.origin));
   for (int k = 0; k < nsys; ++k) {
     grids[k]->last_norb = norbs[k];
+    grids[k]->last_pairE = grids[k]->ws.pairE;
     if (ex_out)
       KX_HIP(hipMemcpy(&ex_out[k], grids[k]->dEx, sizeof(double), hipMemcpyDeviceToHost));
   }
@@ -1343,16 +1344,14 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
   const size_t esw = elem_size(dtype_w);
   const size_t fbytes = esw * (size_t)norb_t * G.N;
   const size_t tbytes = (kind == 0 ? sizeof(double) : sizeof(float)) * (size_t)nb * G.slot;
-  kx_status st = ensure_workspace(g, nb);
+  kx_status st = reserve_slots(g, nb, false, false);
   if (st != KX_OK) return st;
-  st = ensure_ftable(g, KX_KERNEL_ERFC, 0.106);
-  if (st != KX_OK) return st;
+  KX_HIP(fill_ftable(g, KX_KERNEL_ERFC, 0.106, g->stream));
   std::vector<Item> its(nb);
   for (int k = 0; k < nb; ++k) its[k] = {2 * k, 2 * k + 1};
-  st = upload_items(g, 3, nb, nb, its);
-  if (st != KX_OK) return st;
   void *psi = nullptr, *vx = nullptr, *tsave = nullptr, *ref = nullptr;
   double* occ = nullptr;
+  Item* dit = nullptr;
   unsigned long long* cnt = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto release = [&]() {
@@ -1362,6 +1361,7 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
     dev_free(tsave);
     dev_free(ref);
     dev_free(occ);
+    dev_free(dit);
     dev_free(cnt);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -1369,9 +1369,15 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
   if (dev_alloc(&psi, fbytes) != KX_OK || dev_alloc(&vx, fbytes) != KX_OK ||
       dev_alloc(&tsave, tbytes) != KX_OK || dev_alloc(&ref, std::max(tbytes, fbytes)) != KX_OK ||
       dev_alloc((void**)&occ, sizeof(double) * norb_t) != KX_OK ||
+      dev_alloc((void**)&dit, sizeof(Item) * nb) != KX_OK ||
       dev_alloc((void**)&cnt, sizeof(unsigned long long)) != KX_OK) {
     release();
     return KX_ERR_OUT_OF_MEMORY;
+  }
+  if (hipMemcpy(dit, its.data(), sizeof(Item) * nb, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return KX_ERR_DEVICE;
   }
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     release();
@@ -1386,29 +1392,28 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
     release();
     return KX_ERR_DEVICE;
   }
-  const Item* dit = g->dItems;
   auto fwd = [&](const SlabPlan& p) -> hipError_t {
     if (kind == 0)
-      return launch_forward_d(dtype_w, 1, G, p, eig_of(g), psi, dit, nb, (double*)g->dT, s);
+      return launch_forward_d(dtype_w, 1, G, p, eig_of(g), psi, dit, nb, (double*)g->ws.T, s);
     if (kind == 1)
-      return launch_forward_f(dtype_w, 1, G, p, eigf_of(g), psi, dit, nb, (float*)g->dT, s);
-    return launch_forward_s(dtype_w, 1, G, p, eigs_of(g), psi, dit, nb, (float*)g->dT, s);
+      return launch_forward_f(dtype_w, 1, G, p, eigf_of(g), psi, dit, nb, (float*)g->ws.T, s);
+    return launch_forward_s(dtype_w, 1, G, p, eigs_of(g), psi, dit, nb, (float*)g->ws.T, s);
   };
   auto pen = [&](const PencilPlan& p) -> hipError_t {
     if (kind == 0)
-      return launch_pencil_d(G, p, eig_of(g), g->dF, nb, (double*)g->dT, g->dEpart, s);
+      return launch_pencil_d(G, p, eig_of(g), g->dF, nb, (double*)g->ws.T, g->ws.epart, s);
     if (kind == 1)
-      return launch_pencil_f(G, p, eigf_of(g), g->dF, nb, (float*)g->dT, g->dEpart, s);
-    return launch_pencil_s(G, p, eigs_of(g), g->dF, nb, (float*)g->dT, g->dEpart, s);
+      return launch_pencil_f(G, p, eigf_of(g), g->dF, nb, (float*)g->ws.T, g->ws.epart, s);
+    return launch_pencil_s(G, p, eigs_of(g), g->dF, nb, (float*)g->ws.T, g->ws.epart, s);
   };
   auto inv = [&](const SlabPlan& p) -> hipError_t {
     if (kind == 0)
-      return launch_inverse_d(dtype_w, 1, G, p, eig_of(g), (const double*)g->dT, dit, nb, psi, occ,
+      return launch_inverse_d(dtype_w, 1, G, p, eig_of(g), (const double*)g->ws.T, dit, nb, psi, occ,
                               vx, s);
     if (kind == 1)
-      return launch_inverse_f(dtype_w, 1, G, p, eigf_of(g), (const float*)g->dT, dit, nb, psi,
+      return launch_inverse_f(dtype_w, 1, G, p, eigf_of(g), (const float*)g->ws.T, dit, nb, psi,
                               occ, vx, s);
-    return launch_inverse_s(dtype_w, 1, G, p, eigs_of(g), (const float*)g->dT, dit, nb, psi, occ,
+    return launch_inverse_s(dtype_w, 1, G, p, eigs_of(g), (const float*)g->ws.T, dit, nb, psi, occ,
                             vx, s);
   };
   // mean time of three launches after one warm-up
@@ -1457,7 +1462,7 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
   bool all_same = true;
   // forward: reference with the current shape, then every candidate
   if (fwd(plan.fwd) != hipSuccess ||
-      hipMemcpyAsync(ref, g->dT, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      hipMemcpyAsync(ref, g->ws.T, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail_dev();
   float best = 1e30f;
   SlabPlan bf = plan.fwd;
@@ -1466,7 +1471,7 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
     if (timeit([&] { return fwd(c); }, none, ms) != hipSuccess) return fail_dev();
     if (verify) {
       bool same = false;
-      if (same_as_ref(g->dT, tbytes, same) != hipSuccess) return fail_dev();
+      if (same_as_ref(g->ws.T, tbytes, same) != hipSuccess) return fail_dev();
       all_same = all_same && same;
     }
     if (ms < best) {
@@ -1476,11 +1481,11 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
   }
   // pencil: each run starts from the forward output
   if (fwd(bf) != hipSuccess ||
-      hipMemcpyAsync(tsave, g->dT, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(tsave, g->ws.T, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       pen(plan.pen) != hipSuccess ||
-      hipMemcpyAsync(ref, g->dT, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      hipMemcpyAsync(ref, g->ws.T, tbytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail_dev();
-  auto restore_t = [&]() { return hipMemcpyAsync(g->dT, tsave, tbytes, hipMemcpyDeviceToDevice, s); };
+  auto restore_t = [&]() { return hipMemcpyAsync(g->ws.T, tsave, tbytes, hipMemcpyDeviceToDevice, s); };
   best = 1e30f;
   PencilPlan bp = plan.pen;
   for (const PencilPlan& c : cp) {
@@ -1489,7 +1494,7 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
     if (verify) {
       bool same = false;
       if (restore_t() != hipSuccess || pen(c) != hipSuccess ||
-          same_as_ref(g->dT, tbytes, same) != hipSuccess)
+          same_as_ref(g->ws.T, tbytes, same) != hipSuccess)
         return fail_dev();
       all_same = all_same && same;
     }
@@ -1608,7 +1613,15 @@ kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, con
   if (st != KX_OK) return st;
   const long long N = g->geom.N, nn = (long long)norb * norb;
   const long long grp = ace_groups(N, norb, norb);
-  st = ensure_doubles(g, &g->dAcePart, &g->ace_part_cap, grp * nn);
+  // partial sums for this build and for every later kx_ace_apply on up to
+  // kAceMaxVec fields, and the apply's coefficients: kx_ace_apply allocates
+  // nothing
+  long long part = grp * nn;
+  for (int nv = 1; nv <= kAceMaxVec; ++nv)
+    part = std::max(part, ace_groups(N, norb, nv) * norb * (long long)nv);
+  st = ensure_doubles(g, &g->dAcePart, &g->ace_part_cap, part);
+  if (st != KX_OK) return st;
+  st = ensure_doubles(g, &g->dAceG, &g->ace_g_cap, (long long)norb * kAceMaxVec);
   if (st != KX_OK) return st;
   if (nn > g->ace_mat_cap) {
     long long cap = g->ace_mat_cap;
@@ -1632,6 +1645,7 @@ kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, con
   KX_HIP(hipMemcpyAsync(&fail, g->dAceStatus, sizeof(int), hipMemcpyDeviceToHost, g->stream));
   KX_HIP(hipStreamSynchronize(g->stream));
   if (fail != 0) return KX_ERR_NUMERIC;
+  g->ace_norb = std::max(g->ace_norb, norb);
   // xi = L^{-1} W
   KX_HIP(launch_combine(dtype, g->dAceLinv, norb, 1, norb, norb, w_dev, N, 1.0, xi_dev,
                         g->stream));
@@ -1645,10 +1659,8 @@ kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int 
   if (nvec < 1 || nvec > kAceMaxVec) return KX_ERR_INVALID_ARG;
   const long long N = g->geom.N, nk = (long long)norb * nvec;
   const long long grp = ace_groups(N, norb, nvec);
-  st = ensure_doubles(g, &g->dAcePart, &g->ace_part_cap, grp * nk);
-  if (st != KX_OK) return st;
-  st = ensure_doubles(g, &g->dAceG, &g->ace_g_cap, nk);
-  if (st != KX_OK) return st;
+  // buffers reserved by kx_ace_build
+  if (norb > g->ace_norb || grp * nk > g->ace_part_cap || nk > g->ace_g_cap) return KX_ERR_STATE;
   const double dV = g->h[0] * g->h[1] * g->h[2];
   // G[k][v] = (xi_k, phi_v)_h, then out_v = -sum_k G[k][v] xi_k
   KX_HIP(launch_gram(dtype, xi_dev, norb, phi_dev, nvec, N, grp, g->dAcePart, dV, g->dAceG,
@@ -1671,7 +1683,7 @@ kx_status kx_pair_energies(kx_grid* g, int npairs, const int* pairs_host, double
   const long long total = (long long)norb * (norb + 1) / 2;
   std::vector<double> all(total);
   if (hipStreamSynchronize(g->stream) != hipSuccess ||
-      hipMemcpy(all.data(), g->dPairE, sizeof(double) * total, hipMemcpyDeviceToHost) !=
+      hipMemcpy(all.data(), g->last_pairE, sizeof(double) * total, hipMemcpyDeviceToHost) !=
           hipSuccess) {
     (void)hipGetLastError();
     return KX_ERR_DEVICE;

@@ -3,6 +3,9 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "kx_internal.h"
@@ -133,7 +136,65 @@ __global__ void __launch_bounds__(256) diff_kernel(const unsigned* __restrict__ 
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
 }
 
+// diagonal pairs at [0, norb); round r of the tournament at norb + r c,
+// c = floor(norb / 2) real pairs per round (the dummy's pair is skipped)
+__global__ void __launch_bounds__(256) schedule_kernel(int norb, Item* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = (norb + 1) & ~1;
+  const int c = norb / 2;
+  if (t < norb) out[t] = Item{t, t};
+  if (t < m - 1) {
+    Item* __restrict__ o = out + norb + (long long)t * c;
+    int n = 0;
+    for (int k = 0; k < m / 2; ++k) {
+      const Item p = rr_pair(m, t, k);
+      if (p.j < norb) o[n++] = p;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) field_items_kernel(int n, Item* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) out[b] = Item{b, -1};
+}
+
+constexpr int kPutVals = 64;  // doubles per launch: 512 bytes of kernel arguments
+struct PutVals {
+  double v[kPutVals];
+};
+__global__ void __launch_bounds__(64) put_doubles_kernel(PutVals vals, int n,
+                                                        double* __restrict__ dst) {
+  const int k = threadIdx.x;
+  if (k < n) dst[k] = vals.v[k];
+}
+
 }  // namespace
+
+hipError_t launch_schedule(int norb, Item* out, hipStream_t s) {
+  if (norb <= 0) return hipSuccess;
+  const int m = (norb + 1) & ~1;
+  const int t = norb > m - 1 ? norb : m - 1;
+  hipLaunchKernelGGL(schedule_kernel, dim3((t + 255) / 256), dim3(256), 0, s, norb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_items(int n, Item* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(field_items_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_doubles(const double* vals, int n, double* dst, hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += kPutVals) {
+    PutVals pv;
+    const int cnt = n - k0 < kPutVals ? n - k0 : kPutVals;
+    for (int k = 0; k < kPutVals; ++k) pv.v[k] = k < cnt ? vals[k0 + k] : 0.0;
+    hipLaunchKernelGGL(put_doubles_kernel, dim3(1), dim3(64), 0, s, pv, cnt, dst + k0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_pattern(void* p, long long n, bool dbl, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -151,6 +212,24 @@ hipError_t launch_diff(const void* a, const void* b, size_t bytes, unsigned long
   hipLaunchKernelGGL(diff_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const unsigned*)a,
                      (const unsigned*)b, words, count);
   return hipGetLastError();
+}
+
+void allow_dynamic_lds(const void* fn, size_t lds) {
+  if (lds <= 64 * 1024) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& set = done[{fn, dev}];
+  if (set >= lds) return;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess)
+    set = lds;
+  else
+    (void)hipGetLastError();
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {

@@ -214,6 +214,10 @@ hipError_t launch_inverse_s(int storage, int mode, const Geom& g, const SlabPlan
 // out[v] = max |x[v n .. v n + n)| for v < count (storage KX_F64 or KX_F32)
 hipError_t launch_absmax(const void* x, int storage, long long n, int count, float* out,
                          hipStream_t s);
+// Let kernel fn take `lds` bytes of dynamic LDS (above the 64 KiB default).
+// The attribute is set once per kernel and device and remembered, so that a
+// launch recorded into a graph makes no further runtime call for it.
+void allow_dynamic_lds(const void* fn, size_t lds);
 // zero `bytes` (a multiple of 4, 4-byte aligned) with a kernel, so that the
 // clearing can be recorded into a graph
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
@@ -242,6 +246,32 @@ hipError_t launch_chol_inv(double* A, int n, double* Linv, int* status, hipStrea
 // Out[v][r] = alpha * sum_k C[v ldv + k ldk] X[k][r]
 hipError_t launch_combine(int storage, const double* C, long long ldv, long long ldk, int m, int n,
                           const void* X, long long N, double alpha, void* Out, hipStream_t s);
+
+// Pair k of round r (0 <= r < m - 1, 0 <= k < m / 2) of the round-robin
+// tournament on m (even) players: player 0 stays, the others rotate.  Returns
+// (min, max) of the two players; a player >= norb is the dummy of an odd
+// orbital count.
+__host__ __device__ inline Item rr_pair(int m, int r, int k) {
+  const int pa = k, pb = m - 1 - k;
+  const int p0 = (pa == 0) ? 0 : 1 + (pa - 1 + r) % (m - 1);
+  const int q0 = 1 + (pb - 1 + r) % (m - 1);
+  Item it;
+  it.i = p0 < q0 ? p0 : q0;
+  it.j = p0 < q0 ? q0 : p0;
+  return it;
+}
+
+// The launch order of the symmetric pairs of norb orbitals: the norb diagonal
+// pairs (i, i), then the m - 1 rounds of the tournament (m = norb rounded up to
+// even), each holding floor(norb / 2) disjoint pairs.  Written on the device
+// (npairs items), so that an exchange application can be recorded into a
+// graph without a host transfer.
+hipError_t launch_schedule(int norb, Item* out, hipStream_t s);
+// out[b] = (b, -1) for b < n (the items of a batch of fields)
+hipError_t launch_field_items(int n, Item* out, hipStream_t s);
+// dst[k] = vals[k] for k < n, the values travelling as kernel arguments (no
+// host transfer, so the copy can be recorded into a graph)
+hipError_t launch_put_doubles(const double* vals, int n, double* dst, hipStream_t s);
 
 __host__ __device__ inline long long pair_index(int i, int j, int norb) {
   // i <= j, row-major upper triangle

@@ -707,9 +707,7 @@ split_inverse(Geom g, EigS e, const float* __restrict__ T, const Item* __restric
 
 template <class K>
 void allow_lds(K kernel, size_t lds) {
-  if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+  allow_dynamic_lds((const void*)kernel, lds);
 }
 
 #define KX_NT_CASES(MACRO) MACRO(1) MACRO(2) MACRO(3) MACRO(4) MACRO(5)

@@ -28,7 +28,7 @@ EXPORTS = (
     "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
-    "kx_profile_phases",
+    "kx_profile_phases", "kx_reserve",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -59,6 +59,7 @@ def lib():
             "kx_setup_laplacian": [ip, dp, c_int, ip, vp, ctypes.POINTER(vp)],
             "kx_apply_fL": [vp, c_int, c_double, c_int, c_int, vp, vp, c_int],
             "kx_apply_exchange": [vp, c_int, c_double, c_int, c_int, vp, dp, vp, c_int],
+            "kx_reserve": [vp, c_int, c_int, c_int],
             "kx_exchange_energy": [vp, dp],
             "kx_pair_energies": [vp, c_int, ip, dp],
             "kx_get_eigensystem": [vp, c_int, dp, dp],
@@ -93,6 +94,56 @@ def _check(st, where):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _span(t):
+    a = t.data_ptr()
+    return a, a + t.numel() * t.element_size()
+
+
+def check_fields(t, shape3, device, name, batch_dims=1):
+    """Raise ValueError unless t is a contiguous float32/float64 tensor on the
+    handle's device with shape (batch, n3, n2, n1).  Returns the library's
+    storage code.  Runs before any library call, so that a host tensor, a
+    wrong shape or dtype never reaches a kernel as a raw pointer."""
+    import torch
+    if not isinstance(getattr(t, "dtype", None), torch.dtype):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor, got one on {t.device}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name}: on cuda:{t.device.index}, the handle was set up on cuda:{device}")
+    if t.dtype not in (torch.float32, torch.float64):
+        raise ValueError(f"{name}: dtype must be float32 or float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.dim() != 3 + batch_dims or tuple(t.shape[batch_dims:]) != tuple(shape3):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} is not (batch,) + {tuple(shape3)}")
+    return DTYPE["f64" if t.dtype == torch.float64 else "f32"]
+
+
+def check_out(out, src, name="out"):
+    """out must match src in dtype, shape and device and must not overlap it."""
+    if out.dtype != src.dtype or tuple(out.shape) != tuple(src.shape) or out.device != src.device:
+        raise ValueError(f"{name}: must match the input's dtype, shape and device "
+                         f"({src.dtype}, {tuple(src.shape)}, {src.device}); got "
+                         f"({out.dtype}, {tuple(out.shape)}, {out.device})")
+    if not out.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    a0, a1 = _span(src)
+    b0, b1 = _span(out)
+    if src.numel() > 0 and a0 < b1 and b0 < a1:
+        raise ValueError(f"{name}: overlaps the input")
+
+
+def check_occ(occ, norb):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(occ, dtype=np.float64).reshape(-1))
+    if a.shape[0] != norb:
+        raise ValueError(f"occ: {a.shape[0]} values for {norb} orbitals")
+    if not np.all(np.isfinite(a)):
+        raise ValueError("occ: values must be finite")
+    return a
 
 
 def _dptr(a):
@@ -137,13 +188,19 @@ def batch_apply_exchange(grids, psis, occs, kernels, omegas, prec="fp64", outs=N
     import numpy as np
     import torch
     n = len(grids)
+    if not (len(psis) == len(occs) == len(kernels) == len(omegas) == n):
+        raise ValueError("one psi, occ, kernel and omega per grid")
     if outs is None:
         outs = [torch.empty_like(p) for p in psis]
-    dts = {p.dtype for p in psis} | {o.dtype for o in outs}
-    if len(dts) != 1 or not all(p.is_cuda and p.is_contiguous() for p in list(psis) + list(outs)):
-        raise ValueError("psis and outs: contiguous device tensors of one dtype")
+    if len(outs) != n:
+        raise ValueError("one output per grid")
+    for k, (g, p, o) in enumerate(zip(grids, psis, outs)):
+        check_fields(p, g.shape3, g.device, f"psis[{k}]")
+        check_out(o, p, f"outs[{k}]")
+    if len({p.dtype for p in psis}) != 1:
+        raise ValueError("psis: one dtype for every system")
     dtype = DTYPE["f64" if psis[0].dtype == torch.float64 else "f32"]
-    occ_arrays = [np.ascontiguousarray(np.asarray(o, dtype=np.float64)) for o in occs]
+    occ_arrays = [check_occ(o, int(p.shape[0])) for o, p in zip(occs, psis)]
     norbs = (ctypes.c_int * n)(*[int(p.shape[0]) for p in psis])
     ks = (ctypes.c_int * n)(*[KERNEL[k] for k in kernels])
     oms = (ctypes.c_double * n)(*[float(w) for w in omegas])
@@ -182,6 +239,8 @@ class Grid:
         _check(st, "kx_setup_laplacian")
         self._h = handle
         self.N = self.n[0] * self.n[1] * self.n[2]
+        self.shape3 = (self.n[2], self.n[1], self.n[0])
+        self.device = torch.cuda.current_device()
         self._np = np
 
     def close(self):
@@ -195,28 +254,45 @@ class Grid:
         except Exception:
             pass
 
-    def apply_fL(self, rho, kernel, omega=0.0, prec="fp64", out=None):
-        """phi = f(-L) rho; rho is a (batch, n3, n2, n1) device tensor."""
+    def reserve(self, norb, prec="fp64", dtype="f64"):
+        """kx_reserve: workspace for later calls on up to norb orbitals (0:
+        batches of fields) in precision prec on storage dtype."""
+        _check(lib().kx_reserve(self._h, int(norb), PREC[prec], DTYPE[dtype]), "kx_reserve")
+
+    def apply_fL(self, rho, kernel, omega=0.0, prec="fp64", out=None, reserve=True):
+        """phi = f(-L) rho; rho is a (batch, n3, n2, n1) device tensor.  With
+        reserve=False the workspace must already be reserved (for work
+        recorded into a graph)."""
         import torch
-        dtype = "f64" if rho.dtype == torch.float64 else "f32"
-        batch = rho.shape[0] if rho.dim() == 4 else 1
+        dt = check_fields(rho, self.shape3, self.device, "rho")
         if out is None:
             out = torch.empty_like(rho)
-        st = lib().kx_apply_fL(self._h, KERNEL[kernel], float(omega), batch, DTYPE[dtype], _ptr(rho),
+        check_out(out, rho)
+        if reserve:
+            self.reserve(0, prec, "f64" if dt == DTYPE["f64"] else "f32")
+        st = lib().kx_apply_fL(self._h, KERNEL[kernel], float(omega), rho.shape[0], dt, _ptr(rho),
                                _ptr(out), PREC[prec])
         _check(st, "kx_apply_fL")
         return out
 
-    def apply_exchange(self, psi, occ, kernel, omega=0.0, prec="fp64", out=None):
-        """(Vx psi) for psi of shape (norb, n3, n2, n1); occ a host sequence."""
-        import numpy as np
+    def _exchange_args(self, psi, occ, out):
         import torch
-        dtype = "f64" if psi.dtype == torch.float64 else "f32"
-        norb = psi.shape[0]
-        occ_a = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        dt = check_fields(psi, self.shape3, self.device, "psi")
+        occ_a = check_occ(occ, psi.shape[0])
         if out is None:
             out = torch.empty_like(psi)
-        st = lib().kx_apply_exchange(self._h, KERNEL[kernel], float(omega), norb, DTYPE[dtype], _ptr(psi),
+        check_out(out, psi)
+        return dt, occ_a, out
+
+    def apply_exchange(self, psi, occ, kernel, omega=0.0, prec="fp64", out=None, reserve=True):
+        """(Vx psi) for psi of shape (norb, n3, n2, n1); occ a host sequence.
+        With reserve=False the workspace must already be reserved (for work
+        recorded into a graph)."""
+        dt, occ_a, out = self._exchange_args(psi, occ, out)
+        norb = psi.shape[0]
+        if reserve:
+            self.reserve(norb, prec, "f64" if dt == DTYPE["f64"] else "f32")
+        st = lib().kx_apply_exchange(self._h, KERNEL[kernel], float(omega), norb, dt, _ptr(psi),
                                      _dptr(occ_a), _ptr(out), PREC[prec])
         _check(st, "kx_apply_exchange")
         return out
@@ -230,20 +306,33 @@ class Grid:
         """Compressed exchange vectors xi = L^{-1} W, -(psi, W)_h = L L^T,
         for psi and W = Vx psi of shape (norb, n3, n2, n1)."""
         import torch
-        dtype = "f64" if psi.dtype == torch.float64 else "f32"
+        dt = check_fields(psi, self.shape3, self.device, "psi")
+        check_fields(w, self.shape3, self.device, "w")
+        if w.dtype != psi.dtype or w.shape != psi.shape:
+            raise ValueError("w: must match psi's dtype and shape")
         if out is None:
             out = torch.empty_like(w)
-        st = lib().kx_ace_build(self._h, psi.shape[0], DTYPE[dtype], _ptr(psi), _ptr(w), _ptr(out))
+        check_out(out, w)
+        check_out(out, psi)
+        st = lib().kx_ace_build(self._h, psi.shape[0], dt, _ptr(psi), _ptr(w), _ptr(out))
         _check(st, "kx_ace_build")
         return out
 
     def ace_apply(self, xi, phi, out=None):
         """V_ACE phi = -sum_k xi_k (xi_k, phi)_h for phi of shape (nvec, n3, n2, n1)."""
         import torch
-        dtype = "f64" if xi.dtype == torch.float64 else "f32"
+        dt = check_fields(xi, self.shape3, self.device, "xi")
+        check_fields(phi, self.shape3, self.device, "phi")
+        if phi.dtype != xi.dtype:
+            raise ValueError("phi: must match xi's dtype")
         if out is None:
             out = torch.empty_like(phi)
-        st = lib().kx_ace_apply(self._h, xi.shape[0], DTYPE[dtype], _ptr(xi), phi.shape[0], _ptr(phi),
+        check_out(out, phi)
+        a0, a1 = _span(xi)
+        b0, b1 = _span(out)
+        if a0 < b1 and b0 < a1:
+            raise ValueError("out: overlaps xi")
+        st = lib().kx_ace_apply(self._h, xi.shape[0], dt, _ptr(xi), phi.shape[0], _ptr(phi),
                                 _ptr(out))
         _check(st, "kx_ace_apply")
         return out

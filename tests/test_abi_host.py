@@ -111,3 +111,23 @@ def test_null_handle_and_host_helper_validation():
     for s in range(8):
         assert L.kx_status_string(s)
     assert L.kx_status_string(99) == b"unknown status"
+
+
+@needs_lib
+@pytest.mark.parametrize("norb,cap", [(128, 48), (128, 64), (33, 7), (256, 100), (9, 4)])
+def test_pair_schedule_cuts_groups_evenly(norb, cap):
+    # the diagonal group (norb pairs) and every tournament round (norb // 2
+    # pairs) are cut into ceil(size / cap) batches whose sizes differ by at
+    # most one, in launch order
+    pairs, offs = kx.pair_schedule(norb, cap)
+    sizes = list(np.diff(offs))
+    groups = [norb] + [norb // 2] * (((norb + 1) & ~1) - 1)
+    k = 0
+    for size in groups:
+        parts = -(-size // cap)
+        got = sizes[k:k + parts]
+        assert sum(got) == size and max(got) - min(got) <= 1 and max(got) <= cap, (size, got)
+        k += parts
+    assert k == len(sizes)
+    # the diagonal pairs come first, in index order
+    assert [tuple(p) for p in pairs[:norb]] == [(i, i) for i in range(norb)]
