@@ -179,7 +179,9 @@ struct kx_grid {
   // optional per-launch timing (hipEvents on the handle's stream)
   bool prof_on = false;
   int prof_mask = 0xF;  // phases whose launches are bracketed (1 << KX_PHASE_*)
-  bool capturing = false;  // work is being recorded into a graph: no timing events
+  bool capturing = false;  // no timing events (the batch graph)
+  bool recording = false;  // a caller records this call into a graph: timing events are
+                           // recorded as graph nodes, but none is created
   // identity and buffer generation: a recorded graph bakes in device
   // addresses, so any reallocation invalidates it
   unsigned long long id = 0;
@@ -498,6 +500,7 @@ template <class F>
 hipError_t timed(kx_grid* g, hipStream_t s, int kind, F&& launch) {
   if (!g->prof_on || g->capturing || !((g->prof_mask >> kind) & 1)) return launch();
   const size_t k = g->prof_kind.size();
+  if (g->recording && g->prof_ev.size() < 2 * (k + 1)) return launch();
   while (g->prof_ev.size() < 2 * (k + 1)) {
     hipEvent_t ev;
     if (hipEventCreate(&ev) != hipSuccess) return hipErrorOutOfMemory;
@@ -1130,20 +1133,22 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   if (prec == KX_PREC_FP16X3 && w.omax_cap < w.slots) return KX_ERR_STATE;
 
   hipStream_t s = g->stream;
-  g->capturing = stream_capturing(s);
-  KX_HIP(fill_ftable(g, kernel, omega, s));
+  g->recording = stream_capturing(s);
+  hipError_t e = fill_ftable(g, kernel, omega, s);
   const int chunk = std::min(batch, w.slots);
   const size_t fb = elem_size(dtype) * (size_t)g->geom.N;
-  for (int b0 = 0; b0 < batch; b0 += chunk) {
+  for (int b0 = 0; b0 < batch && e == hipSuccess; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
     const void* src = static_cast<const char*>(rho_dev) + fb * b0;
     void* dst = static_cast<char*>(phi_dev) + fb * b0;
     if (prec == KX_PREC_FP16X3)  // the fields' largest magnitudes set the FP16 scales
-      KX_HIP(launch_absmax(src, dtype, (long long)g->geom.N, nb, w.omax, s));
-    KX_HIP(run_batch(g, w, s, 0, prec, dtype, src, w.fitems, nb, dtype, nullptr, nullptr, dst, 0,
-                     0.0));
+      e = launch_absmax(src, dtype, (long long)g->geom.N, nb, w.omax, s);
+    if (e == hipSuccess)
+      e = run_batch(g, w, s, 0, prec, dtype, src, w.fitems, nb, dtype, nullptr, nullptr, dst, 0,
+                    0.0);
   }
-  g->capturing = false;
+  g->recording = false;
+  KX_HIP(e);
   return KX_OK;
 }
 
@@ -1155,9 +1160,9 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
   kx_status st = plan_exchange(g, g->ws, kernel, omega, norb, dtype, psi_dev, occ_host, vxpsi_dev,
                                prec, xp);
   if (st != KX_OK) return st;
-  g->capturing = stream_capturing(g->stream);
+  g->recording = stream_capturing(g->stream);
   const hipError_t e = enqueue_exchange(g, xp, g->ws, g->stream);
-  g->capturing = false;
+  g->recording = false;
   KX_HIP(e);
   g->last_norb = norb;
   g->last_pairE = g->ws.pairE;

@@ -65,7 +65,7 @@ def test_roofline_picks_the_bound_and_the_dominant_phase():
               "pencil": {"ms": 1.0 * launches, "launches": launches},
               "inverse": {"ms": 1.5 * launches, "launches": launches},
               "energy": {"ms": 0.1, "launches": launches}}
-    r = bench.roofline(w, "fp64", phases, steps=1)
+    r = bench.roofline(w, "fp64", phases, launches_per_step=launches)
     assert r["kernel"] == "forward" and r["avg_launch_ms"] == pytest.approx(2.0)
     pb = bench.phase_bytes(w, "fp64")["forward"] / launches
     pf = bench.phase_flops(w)["forward"] * w.npairs / launches
@@ -75,5 +75,19 @@ def test_roofline_picks_the_bound_and_the_dominant_phase():
     assert r["achieved"] == pytest.approx(pb / 2e-3 / 1e9)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
     # a split path is priced against its own peak
-    r = bench.roofline(w, "bf16x3", phases, steps=1)
+    r = bench.roofline(w, "bf16x3", phases, launches_per_step=launches)
     assert r["mfma_peak"] == 2500.0
+
+
+def test_vx_energy_is_the_exchange_energy_of_the_exact_operator():
+    # 1/4 sum_j occ_j <psi_j, (Vx psi)_j>_h = E_x for the operator the oracle
+    # applies (non-uniform occupations), so the benchmark's second energy
+    # measure has the oracle's E_x as its reference
+    import numpy as np
+    import oracle as orc
+    from synth import make_workload
+    w, psi, occ = make_workload("dirichlet20x27x34_coulomb")
+    occ = occ * np.linspace(1.0, 0.3, w.norb)
+    vx, ex = orc.exchange(psi, occ, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
+    assert abs(bench.vx_energy(psi, vx, occ, w.dV) - ex) <= 1e-12 * abs(ex)
+    assert abs(bench.vx_energy(psi, 1.001 * vx, occ, w.dV) - ex) > 1e-4 * abs(ex)

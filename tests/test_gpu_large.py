@@ -2,11 +2,15 @@
 erfc kernel, 32896 pair solves per application.
 
 The oracle cannot run every pair at this size, so the checks are:
-  * the FP64 GPU path against oracle pair energies on a seeded sample of
-    pairs (the oracle reads the FP32 orbitals promoted exactly to FP64, so the
-    difference is compute error only): 1e-10 relative;
-  * each reduced precision against the same oracle sample at its energy
-    tolerance, and against the full FP64 GPU path for E_x and Vx psi;
+  * every precision's pair energies against the oracle on a seeded sample of
+    pairs, diagonals included (the oracle reads the FP32 orbitals promoted
+    exactly to FP64, so the difference is compute error only): FP64 and the
+    mixed path's energies at 1e-10 relative per pair, the others at the
+    FP32-class tolerance per pair;
+  * Vx psi of one orbital from the FP64 path against the oracle (FP64
+    arithmetic, FP32 output: 1e-6), and of three orbitals from every other
+    precision against the FP64 path;
+  * E_x of every precision against the FP64 path;
   * the compressed exchange built from the FP64 path's Vx psi reproduces it
     on the orbitals (V_ACE psi_j = (Vx psi)_j, FP32-rounded xi: 1e-6).
 """
@@ -21,61 +25,86 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 TOL64 = 1e-10
 TOL32_FIELD = 1e-5
 TOL32_ENERGY = 1e-6
+VX_ORBITAL = 131
 
 
 def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def test_periodic144_f32_storage_sampled():
+@pytest.fixture(scope="module")
+def large():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2406_16998_amd import kx
-
     name = "periodic144_erfc_f32"
     print(f"generating {name}", flush=True)
     w, psi, occ = make_workload(name)
     assert psi.dtype == np.float32
-    psi_d = torch.from_numpy(psi).cuda()
-    g = kx.Grid(w.n, w.h, w.order, w.bc)
-
     rng = np.random.default_rng(5)
-    sample = [(0, 0), (255, 255)] + [tuple(sorted(rng.choice(w.norb, 2, replace=False)))
-                                     for _ in range(8)]
+    sample = [(0, 0), (131, 131), (255, 255)] + [tuple(sorted(rng.choice(w.norb, 2, replace=False)))
+                                                 for _ in range(9)]
     grid = orc.make_grid(w.n, w.h, w.order, w.bc)
     F = orc.kernel_values(grid.lam_sum(), w.kernel, w.omega)
     ref = np.array([orc.pair_energy(psi[i].astype(np.float64), psi[j].astype(np.float64), grid,
                                     w.kernel, w.omega, F) for i, j in sample])
-    emax = float(np.max(np.abs(ref)))
     print("oracle sample done", flush=True)
-
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    psi_d = torch.from_numpy(psi).cuda()
     vx64 = g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec="fp64")
     ex64 = g.exchange_energy()
     pe64 = g.pair_energies(sample)
     print(f"fp64 E_x={ex64!r}", flush=True)
-    for e, r in zip(pe64, ref):
-        assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * emax
+    yield dict(w=w, psi=psi, occ=occ, grid=grid, sample=sample, ref=ref, g=g, psi_d=psi_d,
+               vx64=vx64, ex64=ex64, pe64=pe64)
+    g.close()
+
+
+def test_periodic144_fp64_against_oracle(large):
+    import torch
+    L = large
+    w, psi = L["w"], L["psi"]
+    for e, r in zip(L["pe64"], L["ref"]):
+        assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * float(np.max(np.abs(L["ref"])))
+    # Vx psi of one orbital: oracle over all 256 partners, FP64 promoted inputs
+    ref = orc.vx_orbital(psi.astype(np.float64), L["occ"], VX_ORBITAL, L["grid"], w.kernel, w.omega)
+    got = L["vx64"][VX_ORBITAL].cpu().numpy().astype(np.float64)
+    err = _rel(got, ref)
+    print(f"fp64 Vx psi[{VX_ORBITAL}] rel err {err:.2e}", flush=True)
+    assert err <= 1e-6  # FP32 output rounding
     # compressed exchange from the FP64 path's Vx psi (FP32 fields, FP64
     # arithmetic): V_ACE psi_j = (Vx psi)_j to FP32 rounding of xi
+    g, psi_d, vx64 = L["g"], L["psi_d"], L["vx64"]
     xi = g.ace_build(psi_d, vx64)
     vace = g.ace_apply(xi, psi_d)
     torch.cuda.synchronize()
     for j in (0, 131, 255):
         assert _rel(vace[j].cpu().numpy(), vx64[j].cpu().numpy()) <= 1e-6, j
     del xi, vace
-    print("ace property checked", flush=True)
-    vx64 = vx64.cpu().numpy()
 
-    for prec in ("fp32", "bf16x3"):
-        vx = g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec=prec)
-        ex = g.exchange_energy()
-        pe = g.pair_energies(sample)
-        print(f"{prec} E_x={ex!r} |dE| vs fp64 = {abs(ex - ex64):.3e} Ha", flush=True)
-        assert abs(ex - ex64) <= TOL32_ENERGY * abs(ex64)
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32", "bf16x3", "fp16x3"])
+def test_periodic144_reduced_precision(large, prec):
+    L = large
+    w, g = L["w"], L["g"]
+    vx = g.apply_exchange(L["psi_d"], L["occ"], w.kernel, w.omega, prec=prec)
+    ex = g.exchange_energy()
+    pe = g.pair_energies(L["sample"])
+    ex64 = L["ex64"]
+    print(f"{prec} E_x={ex!r} |dE| vs fp64 = {abs(ex - ex64):.3e} Ha", flush=True)
+    ref = L["ref"]
+    emax = float(np.max(np.abs(ref)))
+    if prec == "mixed":  # FP64 forward pass, scaling and energies
+        assert abs(ex - ex64) <= TOL64 * abs(ex64)
         for e, r in zip(pe, ref):
-            assert abs(e - r) <= TOL32_ENERGY * emax
-        vx = vx.cpu().numpy()
-        for j in (0, 131, 255):
-            assert _rel(vx[j], vx64[j]) <= TOL32_FIELD, (prec, j)
-        del vx
-    g.close()
+            assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * emax
+    else:
+        assert abs(ex - ex64) <= TOL32_ENERGY * abs(ex64)
+        worst = max(abs(e - r) / abs(r) for e, r in zip(pe, ref))
+        print(f"{prec} worst pair-energy rel err {worst:.2e}", flush=True)
+        for e, r in zip(pe, ref):
+            assert abs(e - r) <= TOL32_ENERGY * abs(r) + 0.1 * TOL32_ENERGY * emax
+    vx = vx.cpu().numpy()
+    vx64 = L["vx64"].cpu().numpy()
+    for j in (0, VX_ORBITAL, 255):
+        assert _rel(vx[j], vx64[j]) <= TOL32_FIELD, (prec, j)

@@ -191,6 +191,19 @@ def test_exchange_bitwise_deterministic(torch_cuda):
     g.close()
 
 
+# orbitals whose Vx psi every full-size test compares with the oracle
+VX_ORBITALS = (0, 40, 77, 127)
+_VX_REF = {}
+
+
+def _vx_ref_96(psi, occ, w, j):
+    """Oracle (Vx psi)_j of the 96^3 workload, computed once per session."""
+    if j not in _VX_REF:
+        grid = orc.make_grid(w.n, w.h, w.order, w.bc)
+        _VX_REF[j] = orc.vx_orbital(psi, occ, j, grid, w.kernel, w.omega)
+    return _VX_REF[j]
+
+
 @pytest.mark.slow
 def test_exchange_production_size_sampled(torch_cuda):
     """128 orbitals on 96^3 periodic, erfc: E_x over all 8256 pairs and a
@@ -210,11 +223,9 @@ def test_exchange_production_size_sampled(torch_cuda):
     assert abs(ex - gold["E_x"]) <= TOL64 * abs(gold["E_x"])
     for e, r in zip(pe, gold["pair_energies"]):
         assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * abs(gold["E_x"])
-    grid = orc.make_grid(w.n, w.h, w.order, w.bc)
-    for j in (0, 77):
-        ref = orc.vx_orbital(psi, occ, j, grid, w.kernel, w.omega)
+    for j in VX_ORBITALS:
         got = vx[j].cpu().numpy()
-        assert _rel(got, ref) <= TOL64, j
+        assert _rel(got, _vx_ref_96(psi, occ, w, j)) <= TOL64, j
     g.close()
 
 
@@ -238,10 +249,12 @@ def test_exchange_production_size_reduced_precision(torch_cuda, prec):
     tol_e = TOL64 if prec == "mixed" else TOL32_ENERGY
     assert abs(ex - gold["E_x"]) <= tol_e * abs(gold["E_x"])
     emax = max(abs(r) for r in gold["pair_energies"])
+    worst = max(abs(e - r) / abs(r) for e, r in zip(pe, gold["pair_energies"]))
+    print(f"{prec} worst sampled pair-energy rel err {worst:.2e}", flush=True)
     for e, r in zip(pe, gold["pair_energies"]):
-        assert abs(e - r) <= tol_e * emax
-    ref = orc.vx_orbital(psi, occ, 5, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
-    assert _rel(vx[5].cpu().numpy(), ref) <= TOL32_FIELD
+        assert abs(e - r) <= tol_e * abs(r) + 0.1 * tol_e * emax
+    for j in VX_ORBITALS:
+        assert _rel(vx[j].cpu().numpy(), _vx_ref_96(psi, occ, w, j)) <= TOL32_FIELD, j
     g.close()
 
 
@@ -273,10 +286,10 @@ def test_exchange_production_size_tuned(torch_cuda, prec):
         assert abs(ex - gold["E_x"]) <= TOL32_ENERGY * abs(gold["E_x"])
         emax = max(abs(r) for r in gold["pair_energies"])
         for e, r in zip(pe, gold["pair_energies"]):
-            assert abs(e - r) <= TOL32_ENERGY * emax
-    ref = orc.vx_orbital(psi, occ, 40, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
+            assert abs(e - r) <= TOL32_ENERGY * abs(r) + 0.1 * TOL32_ENERGY * emax
     tol_f = TOL64 if prec == "fp64" else TOL32_FIELD
-    assert _rel(vx[40].cpu().numpy(), ref) <= tol_f
+    for j in VX_ORBITALS:
+        assert _rel(vx[j].cpu().numpy(), _vx_ref_96(psi, occ, w, j)) <= tol_f, j
     g.close()
 
 
