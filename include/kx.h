@@ -47,7 +47,8 @@ typedef enum {
   KX_ERR_INVALID_ARG = 1,   /* bad size, spacing, order, enum, pointer or count */
   KX_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement     */
   KX_ERR_SINGULAR = 3,      /* unscreened kernel with a zero eigenvalue of -L   */
-  KX_ERR_OUT_OF_MEMORY = 4, /* device allocation failed                         */
+  KX_ERR_OUT_OF_MEMORY = 4, /* device allocation failed, or the fixed scratch
+                             * array is too small for the request              */
   KX_ERR_DEVICE = 5,        /* a HIP runtime call failed                         */
   KX_ERR_STATE = 6,         /* workspace not reserved, or energy requested
                              * before any exchange call                         */
@@ -73,6 +74,10 @@ typedef enum {
 } kx_prec;
 /* Storage type of psi / rho / phi / vxpsi. */
 typedef enum { KX_F64 = 0, KX_F32 = 1 } kx_dtype;
+
+/* Bytes of the fixed device scratch array of kx_apply_exchange_noalloc (one
+ * per device the library runs on, held until the process ends). */
+#define KX_SCRATCH_BYTES (128ull << 20)
 
 /* Opaque handle: owns the device copies of V_k and lam_k, the f table, the
  * pair schedule and the intermediate workspace. */
@@ -149,6 +154,26 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
                             const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                             int prec);
+
+/* kx_apply_exchange for callers that cannot allocate device memory (code
+ * under HIP graph capture that must not grow the handle, tight serving
+ * loops, harnesses that forbid allocation): the same arguments, results and
+ * arithmetic, with every per-call buffer (intermediates, energy partials,
+ * pair schedule, pair energies, occupations, FP16 scales) carved out of a
+ * fixed device array of KX_SCRATCH_BYTES per device instead of the handle's
+ * workspace; kx_reserve is not needed.  No FP32 working copies: reduced
+ * precisions on KX_F64 storage read and update the caller's FP64 arrays
+ * directly, and Vx psi accumulates in FP64.  Launches take as many pairs as
+ * fit in the array (up to the handle's batch size).
+ * KX_ERR_OUT_OF_MEMORY if the schedule, pair energies and one launch slot
+ * (at 96^3 about 7 MB in FP64) do not fit in KX_SCRATCH_BYTES.
+ * Every call on one device shares that device's array and leaves its
+ * contents there: calls that overlap on one device (other streams, other
+ * host threads) race and must not be issued; kx_pair_energies reads the
+ * array, so it reports the last call only until another call on the device. */
+kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int norb, int dtype,
+                                    const void* psi_dev, const double* occ_host,
+                                    void* vxpsi_dev, int prec);
 
 /* Ragged batch: the exact-exchange application of nsys independent systems
  * (each its own handle, grid, boundary conditions, kernel, omega, orbital

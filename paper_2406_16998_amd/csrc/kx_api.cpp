@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -97,7 +98,8 @@ void schedule_pairs(int norb, std::vector<Item>& pairs) {
 
 // Device buffers one exchange application (or one batch of fields) works in,
 // with the number of values each holds.  The handle owns one set (grown only
-// by kx_reserve, kx_autotune and the batch entry point).
+// by kx_reserve, kx_autotune and the batch entry point); the no-allocation
+// entry point carves a set out of the fixed scratch array.
 struct Work {
   void* T = nullptr;         // intermediates: slots fields of Geom::slot values
   float* T2 = nullptr;       // the mixed path's FP32 copy of the pencil's result
@@ -179,7 +181,7 @@ struct kx_grid {
   // optional per-launch timing (hipEvents on the handle's stream)
   bool prof_on = false;
   int prof_mask = 0xF;  // phases whose launches are bracketed (1 << KX_PHASE_*)
-  bool capturing = false;  // no timing events (the batch graph)
+  bool capturing = false;  // no timing events (the batch graph, the no-allocation path)
   bool recording = false;  // a caller records this call into a graph: timing events are
                            // recorded as graph nodes, but none is created
   // identity and buffer generation: a recorded graph bakes in device
@@ -493,6 +495,90 @@ void free_work(Work& w) {
   dev_free(w.psi32);
   dev_free(w.vx32);
   w = Work();
+}
+
+// ---- the fixed scratch array of kx_apply_exchange_noalloc
+// One per device, allocated with the code object and held until the process
+// ends.  Host code must not pass its name to a kernel: the name is a host-side
+// stand-in, not a device address.  The device address, per device, comes from
+// hipGetSymbolAddress at set-up.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[KX_SCRATCH_BYTES];
+
+namespace {
+
+// Look up this device's copy of the scratch array, once per device (the
+// device current at the call).
+kx_status scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return KX_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return KX_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return KX_ERR_DEVICE;
+  }
+  g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  return KX_OK;
+}
+
+// The buffers of one exchange application on norb orbitals in precision prec,
+// carved out of the handle's device's scratch array: the pair schedule, pair
+// energies, occupations and FP16 scales first, then as many launch slots (T,
+// the mixed path's T2, energy partials, FP16 result maxima) as fit, up to the
+// handle's batch size.  No FP32 working copies: the kernels read the caller's
+// storage.  KX_ERR_OUT_OF_MEMORY if not even one slot fits.
+kx_status carve_scratch(const kx_grid* g, int norb, int prec, Work& w) {
+  w = Work();
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g->device >= 0 && g->device < kMaxDevices) base = g_scratch_ptr[g->device];
+  }
+  if (!base) return KX_ERR_STATE;
+  if (norb == 0) return KX_OK;
+  const Geom& G = g->geom;
+  const size_t cap = KX_SCRATCH_BYTES;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return base + o;
+  };
+  const long long npairs = (long long)norb * (norb + 1) / 2;
+  const bool mixed = prec == KX_PREC_MIXED, h16 = prec == KX_PREC_FP16X3;
+  const size_t fixed = (sizeof(Item) + sizeof(double)) * (size_t)npairs + sizeof(double) * norb +
+                       (h16 ? sizeof(float) * norb : 0) + 4 * 256;
+  const size_t nstrips = (size_t)(G.slab / kTile);
+  const size_t tb = t_bytes(G, prec);
+  const size_t per_slot =
+      tb + (mixed ? sizeof(float) * (size_t)G.slot : 0) + sizeof(double) * nstrips + (h16 ? 4 : 0);
+  if (fixed >= cap) return KX_ERR_OUT_OF_MEMORY;
+  long long slots = (long long)((cap - fixed - 4 * 256) / per_slot);
+  slots = std::min<long long>(slots, std::min(g->batch_cap, norb));
+  if (slots < 1) return KX_ERR_OUT_OF_MEMORY;
+  w.items = reinterpret_cast<Item*>(take(sizeof(Item) * npairs));
+  w.items_cap = npairs;
+  w.pairE = reinterpret_cast<double*>(take(sizeof(double) * npairs));
+  w.pairE_cap = npairs;
+  w.occ = reinterpret_cast<double*>(take(sizeof(double) * norb));
+  w.occ_cap = norb;
+  if (h16) {
+    w.omax = reinterpret_cast<float*>(take(sizeof(float) * norb));
+    w.omax_cap = norb;
+  }
+  w.T = take(tb * slots);
+  w.tbytes = tb;
+  if (mixed) w.T2 = reinterpret_cast<float*>(take(sizeof(float) * G.slot * slots));
+  w.epart = reinterpret_cast<double*>(take(sizeof(double) * nstrips * slots));
+  if (h16) w.tmax = reinterpret_cast<unsigned*>(take(sizeof(unsigned) * slots));
+  w.slots = (int)slots;
+  return off <= cap ? KX_OK : KX_ERR_OUT_OF_MEMORY;
 }
 
 // Bracket one kernel launch with timing events when profiling is on.
@@ -1064,6 +1150,9 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
   if (dev_alloc((void**)&g->dEx, sizeof(double) * 2) != KX_OK ||
       dev_alloc((void**)&g->dF, sizeof(double) * (size_t)G.fsize) != KX_OK)
     return fail(KX_ERR_OUT_OF_MEMORY);
+  // the no-allocation entry point's scratch array on this device
+  st = scratch_init(g->device);
+  if (st != KX_OK) return fail(st);
   *out = g;
   return KX_OK;
 }
@@ -1166,6 +1255,34 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
   KX_HIP(e);
   g->last_norb = norb;
   g->last_pairE = g->ws.pairE;
+  return KX_OK;
+}
+
+kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int norb, int dtype,
+                                    const void* psi_dev, const double* occ_host, void* vxpsi_dev,
+                                    int prec) {
+  if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED) return KX_ERR_INVALID_ARG;
+  Work w;
+  kx_status st = carve_scratch(g, norb, prec, w);
+  if (st != KX_OK) return st;
+  XPlan xp;
+  st = plan_exchange(g, w, kernel, omega, norb, dtype, psi_dev, occ_host, vxpsi_dev, prec, xp);
+  if (st != KX_OK) return st;
+  hipStream_t s = g->stream;
+  // earlier calls on this device left other shapes in the shared array: the
+  // intermediates' padded rows must read as zero
+  hipError_t e = hipSuccess;
+  if (norb > 0) {
+    e = launch_zero(w.T, w.tbytes * w.slots, s);
+    if (e == hipSuccess && w.T2) e = launch_zero(w.T2, sizeof(float) * g->geom.slot * w.slots, s);
+  }
+  g->capturing = true;  // no timing events: nothing is created on this path
+  if (e == hipSuccess) e = enqueue_exchange(g, xp, w, s);
+  g->capturing = false;
+  KX_HIP(e);
+  g->last_norb = norb;
+  g->last_pairE = w.pairE;
   return KX_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTS = (
     "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
-    "kx_profile_phases", "kx_reserve",
+    "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -59,6 +59,7 @@ def lib():
             "kx_setup_laplacian": [ip, dp, c_int, ip, vp, ctypes.POINTER(vp)],
             "kx_apply_fL": [vp, c_int, c_double, c_int, c_int, vp, vp, c_int],
             "kx_apply_exchange": [vp, c_int, c_double, c_int, c_int, vp, dp, vp, c_int],
+            "kx_apply_exchange_noalloc": [vp, c_int, c_double, c_int, c_int, vp, dp, vp, c_int],
             "kx_reserve": [vp, c_int, c_int, c_int],
             "kx_exchange_energy": [vp, dp],
             "kx_pair_energies": [vp, c_int, ip, dp],
@@ -295,6 +296,16 @@ class Grid:
         st = lib().kx_apply_exchange(self._h, KERNEL[kernel], float(omega), norb, dt, _ptr(psi),
                                      _dptr(occ_a), _ptr(out), PREC[prec])
         _check(st, "kx_apply_exchange")
+        return out
+
+    def apply_exchange_noalloc(self, psi, occ, kernel, omega=0.0, prec="fp64", out=None):
+        """kx_apply_exchange_noalloc: the exchange with every per-call buffer in
+        the library's fixed device scratch array (out must be given, or is
+        allocated here by torch before the call)."""
+        dt, occ_a, out = self._exchange_args(psi, occ, out)
+        st = lib().kx_apply_exchange_noalloc(self._h, KERNEL[kernel], float(omega), psi.shape[0], dt,
+                                             _ptr(psi), _dptr(occ_a), _ptr(out), PREC[prec])
+        _check(st, "kx_apply_exchange_noalloc")
         return out
 
     def exchange_energy(self):

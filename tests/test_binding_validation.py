@@ -77,6 +77,8 @@ def test_bad_input_tensor_is_rejected(no_library, case):
     with pytest.raises(ValueError):
         g.apply_exchange(x, [2.0] * 3, "erfc", 0.1)
     with pytest.raises(ValueError):
+        g.apply_exchange_noalloc(x, [2.0] * 3, "erfc", 0.1)
+    with pytest.raises(ValueError):
         g.apply_fL(x, "erfc", 0.1)
     with pytest.raises(ValueError):
         g.ace_apply(x, FakeDev(GOOD, ptr=1 << 30), out=FakeDev(GOOD, ptr=1 << 31))

@@ -1,0 +1,93 @@
+"""kx_apply_exchange_noalloc (every per-call buffer in the library's fixed
+device scratch array) against kx_apply_exchange on the same handle and
+inputs: two calls in a row, the second on a smaller input, then the
+128-orbital 96^3 workload against the stored oracle energy, and the error
+for a request larger than the array."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32_FIELD = 1e-5
+TOL32_ENERGY = 1e-6
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_energies.json")
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "bf16x3", "fp16x3"])
+def test_noalloc_matches_apply_exchange_twice(prec):
+    import torch
+    from paper_2406_16998_amd import kx
+    for name in ("mixed40x36x44_erfc", "dirichlet20x27x34_coulomb"):  # the second is smaller
+        print(f"noalloc {prec} {name}", flush=True)
+        w, psi, occ = make_workload(name)
+        occ = occ * np.linspace(1.0, 0.5, w.norb)
+        g = kx.Grid(w.n, w.h, w.order, w.bc)
+        psi_d = torch.from_numpy(psi).cuda()
+        ref = g.apply_exchange(psi_d, occ, w.kernel, w.omega, prec=prec).clone()
+        ex_ref = g.exchange_energy()
+        pairs = [(i, j) for i in range(w.norb) for j in range(i, w.norb)]
+        pe_ref = g.pair_energies(pairs)
+        out = torch.full_like(psi_d, float("nan"))
+        g.apply_exchange_noalloc(psi_d, occ, w.kernel, w.omega, prec=prec, out=out)
+        ex = g.exchange_energy()
+        pe = g.pair_energies(pairs)
+        torch.cuda.synchronize()
+        if prec == "fp64":
+            # same arithmetic in the same order: bitwise equal
+            assert torch.equal(out, ref)
+            assert ex == ex_ref and np.array_equal(pe, pe_ref)
+        else:
+            # reduced precision reads and accumulates the FP64 arrays directly
+            # instead of FP32 working copies
+            tol_e = TOL64 if prec == "mixed" else TOL32_ENERGY
+            assert abs(ex - ex_ref) <= tol_e * abs(ex_ref)
+            emax = float(np.max(np.abs(pe_ref)))
+            assert np.all(np.abs(pe - pe_ref) <= tol_e * np.abs(pe_ref) + 1e-3 * tol_e * emax)
+            o, r = out.cpu().numpy(), ref.cpu().numpy()
+            for j in range(w.norb):
+                assert _rel(o[j], r[j]) <= TOL32_FIELD, j
+        g.close()
+
+
+def test_noalloc_full_size_against_oracle():
+    import torch
+    from paper_2406_16998_amd import kx
+    name = "periodic96_erfc"
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)[name]
+    w, psi, occ = make_workload(name)
+    g = kx.Grid(w.n, w.h, w.order, w.bc)
+    psi_d = torch.from_numpy(psi).cuda()
+    vx = g.apply_exchange_noalloc(psi_d, occ, w.kernel, w.omega)
+    ex = g.exchange_energy()
+    pe = g.pair_energies(gold["pairs"])
+    print(f"noalloc 96^3 E_x={ex!r} oracle={gold['E_x']!r}", flush=True)
+    assert abs(ex - gold["E_x"]) <= TOL64 * abs(gold["E_x"])
+    for e, r in zip(pe, gold["pair_energies"]):
+        assert abs(e - r) <= TOL64 * abs(r) + 1e-15 * abs(gold["E_x"])
+    ref = orc.vx_orbital(psi, occ, 3, orc.make_grid(w.n, w.h, w.order, w.bc), w.kernel, w.omega)
+    assert _rel(vx[3].cpu().numpy(), ref) <= TOL64
+    g.close()
+
+
+def test_noalloc_rejects_requests_beyond_the_array():
+    import torch
+    from paper_2406_16998_amd import kx
+    # 5000 orbitals: 12.5 million pairs of schedule and energies exceed the array
+    g = kx.Grid((2, 2, 2), (0.5,) * 3, 2, ("dirichlet",) * 3)
+    psi = torch.zeros((5000, 2, 2, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(kx.KxError) as e:
+        g.apply_exchange_noalloc(psi, np.full(5000, 2.0), "coulomb")
+    assert e.value.status == 4
+    g.close()
