@@ -9,6 +9,7 @@ from .kx_oracle import (  # noqa: F401
     Grid,
     ace_apply,
     ace_build,
+    apply_coulomb_multipole,
     apply_fL,
     exchange,
     fd_weights,
@@ -16,6 +17,10 @@ from .kx_oracle import (  # noqa: F401
     kernel_values,
     laplacian_1d,
     make_grid,
+    multipole_moments,
+    multipole_potential,
+    multipole_rhs_correction,
+    node_coords,
     pair_energy,
     pair_potential,
     vx_orbital,

@@ -292,3 +292,105 @@ def ace_apply(xi, phi, dV):
     F = phi.reshape(nvec, -1)
     G = dV * (X @ F.T)          # (xi_k, phi_v)_h
     return (-(G.T @ X)).reshape(phi.shape)
+
+
+# --------------------------------------------------------------------------
+# Sec. IV: isolated systems.  The unscreened problem on an all-Dirichlet grid
+# takes its boundary values from the multipole expansion of the Coulomb
+# kernel, enforced by modifying the right-hand side.
+# --------------------------------------------------------------------------
+def node_coords(n, h):
+    """Coordinates of the grid nodes along each axis: x_i = i h (i = 0..n-1)."""
+    return tuple(np.arange(n[k], dtype=np.float64) * h[k] for k in range(3))
+
+
+def _spherical(x, y, z):
+    r = np.sqrt(x * x + y * y + z * z)
+    cos_t = np.where(r > 0.0, z / np.where(r > 0.0, r, 1.0), 1.0)
+    phi = np.arctan2(y, x)
+    return r, cos_t, phi
+
+
+def multipole_moments(rho, grid, centre, lmax):
+    """Moments of a charge density (n3, n2, n1) about `centre`:
+      A[l, m] = dV sum_r rho(r) |r-c|^l P_l^m(cos t) cos(m p),
+      B[l, m] = dV sum_r rho(r) |r-c|^l P_l^m(cos t) sin(m p),   0 <= m <= l <= lmax,
+    with (|r-c|, t, p) the spherical coordinates of r - c and P_l^m the
+    associated Legendre function (scipy.special.lpmv)."""
+    from scipy.special import lpmv
+    x1, x2, x3 = node_coords(grid.n, grid.h)
+    Z, Y, X = np.meshgrid(x3 - centre[2], x2 - centre[1], x1 - centre[0], indexing="ij")
+    r, ct, ph = _spherical(X, Y, Z)
+    A = np.zeros((lmax + 1, lmax + 1))
+    B = np.zeros((lmax + 1, lmax + 1))
+    rho = np.asarray(rho, dtype=np.float64)
+    for l in range(lmax + 1):
+        rl = r ** l
+        for m in range(l + 1):
+            P = lpmv(m, l, ct)
+            A[l, m] = grid.dV * float(np.sum(rho * rl * P * np.cos(m * ph)))
+            B[l, m] = grid.dV * float(np.sum(rho * rl * P * np.sin(m * ph)))
+    return A, B
+
+
+def multipole_potential(A, B, points, centre):
+    """The Coulomb potential of the expanded charge at points (..., 3) outside
+    the charge, by the addition theorem for 1/|r - r'|:
+      phi(r) = sum_l sum_m (2 - delta_m0) (l-m)!/(l+m)! P_l^m(cos t) / |r-c|^(l+1)
+                          * (A[l, m] cos(m p) + B[l, m] sin(m p))."""
+    from scipy.special import lpmv
+    pts = np.asarray(points, dtype=np.float64)
+    r, ct, ph = _spherical(pts[..., 0] - centre[0], pts[..., 1] - centre[1],
+                           pts[..., 2] - centre[2])
+    lmax = A.shape[0] - 1
+    out = np.zeros(r.shape)
+    for l in range(lmax + 1):
+        inv = 1.0 / r ** (l + 1)
+        for m in range(l + 1):
+            ratio = math.factorial(l - m) / math.factorial(l + m)
+            w = (1.0 if m == 0 else 2.0) * ratio
+            out += w * lpmv(m, l, ct) * inv * (A[l, m] * np.cos(m * ph) + B[l, m] * np.sin(m * ph))
+    return out
+
+
+def multipole_rhs_correction(rho, grid, centre, lmax):
+    """c (n3, n2, n1): for every node, the stencil weights that reach nodes
+    outside the grid times the expanded potential there,
+      c(x) = sum_k sum_{p: x + p e_k outside} (w_|p| / h_k^2) phi_ext(x + p e_k),
+    so that the full stencil at x reads (L_D phi)(x) + c(x).  Requires
+    Dirichlet on every axis."""
+    if any(b != "dirichlet" for b in grid.bc):
+        raise ValueError("the multipole boundary values are for all-Dirichlet grids")
+    A, B = multipole_moments(rho, grid, centre, lmax)
+    w = [float(v) for v in fd_weights(grid.order)]
+    mrad = grid.order // 2
+    x1, x2, x3 = node_coords(grid.n, grid.h)
+    axes = (x1, x2, x3)
+    n1, n2, n3 = grid.n
+    c = np.zeros((n3, n2, n1))
+    for k in range(3):
+        nk, hk = grid.n[k], grid.h[k]
+        for i in range(nk):
+            for p in range(1, mrad + 1):
+                for j in (i - p, i + p):
+                    if 0 <= j < nk:
+                        continue
+                    # the outside node: axis k at index j, the other axes on the grid
+                    coords = [axes[0], axes[1], axes[2]]
+                    coords[k] = np.array([j * hk])
+                    Z, Y, X = np.meshgrid(coords[2], coords[1], coords[0], indexing="ij")
+                    pts = np.stack([X, Y, Z], axis=-1)
+                    val = (w[p] / (hk * hk)) * multipole_potential(A, B, pts, centre)
+                    sl = [slice(None)] * 3
+                    sl[2 - k] = slice(i, i + 1)
+                    c[tuple(sl)] += val
+    return c
+
+
+def apply_coulomb_multipole(rho, grid, centre, lmax):
+    """phi = (-L_D)^{-1} (4 pi rho + c) for one density (n3, n2, n1): the
+    unscreened problem with boundary values from the multipole expansion,
+    through the same Kronecker solve as apply_fL (f = 4 pi / lam applied to
+    rho + c / (4 pi))."""
+    c = multipole_rhs_correction(rho, grid, centre, lmax)
+    return apply_fL(np.asarray(rho, dtype=np.float64) + c / FOUR_PI, grid, "coulomb")
