@@ -100,8 +100,9 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
 /* Reserve the workspace of later kx_apply_fL and kx_apply_exchange calls
  * (the apply calls allocate nothing).  Grows the handle's buffers so that
  *   norb > 0:  kx_apply_exchange on up to norb orbitals, and
- *   norb == 0: kx_apply_fL on batches of fields (any batch size; fields are
- *              processed in launches of at most the handle's batch size),
+ *   norb == 0: kx_apply_fL and kx_apply_fL_multipole on batches of fields
+ *              (any batch size; fields are processed in launches of at most
+ *              the handle's batch size),
  * in precision prec on storage dtype; earlier reservations are kept (a call
  * never shrinks them).  Per launch slot the intermediates take 8 bytes per
  * value of the padded grid (plus 4 for KX_PREC_MIXED); an exchange reservation
@@ -125,6 +126,26 @@ kx_status kx_reserve(kx_grid* g, int norb, int prec, int dtype);
  * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic. */
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
                       const void* rho_dev, void* phi_dev, int prec);
+
+/* phi = (-L_D)^{-1} (4 pi rho + c) for a batch of charge densities on a grid
+ * with vacuum on every side: the unscreened problem with Dirichlet values
+ * from the multipole expansion of the Coulomb kernel, enforced through the
+ * right-hand side (Sec. IV, isolated systems).  For every field, the moments
+ *   A_lm + i B_lm = dV sum_r rho(r) |d|^l P_l^m(cos t) e^{i m p},  d = r - centre,
+ * give the potential outside the grid,
+ *   phi_ext(r) = sum_{l <= lmax} sum_{m <= l} (2 - [m = 0]) (l-m)!/(l+m)!
+ *                  P_l^m(cos t) (A_lm cos m p + B_lm sin m p) / |d|^(l+1),
+ * and c(x) = sum over the stencil weights w_|p| / h_k^2 that reach a node
+ * outside the grid of phi_ext there.  Node i of axis k sits at i h_k.
+ *   rho_dev      batch*N densities (read only)
+ *   phi_dev      batch*N potentials (overwritten; not aliasing rho_dev)
+ *   dtype, prec  as for kx_apply_fL; the moments and c are FP64 in every mode
+ *   lmax         0 .. 6
+ *   centre[3]    expansion centre (host, bohr), finite
+ * KX_ERR_UNSUPPORTED unless every axis is Dirichlet.  Enqueues kernels only
+ * (KX_ERR_STATE if kx_reserve(g, 0, prec, dtype) was not called). */
+kx_status kx_apply_fL_multipole(kx_grid* g, int batch, int dtype, const void* rho_dev,
+                                void* phi_dev, int prec, int lmax, const double centre[3]);
 
 /* Exact-exchange operator on norb real orbitals (Sec. II, Eqs. (3), (8)):
  *   (Vx psi)_j = - sum_i occ_i phi_ij psi_i,   phi_ij = f(-L)(psi_i psi_j),
@@ -215,7 +236,8 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
 
 /* The launch shapes in use for prec (a test and reporting hook):
  * fwd_out[6] = {parity split, z-slabs, waves, chunk rows, V in LDS, LDS bytes},
- * pen_out[2] = {waves, LDS bytes}, inv_out[6] like fwd_out (parity split 1). */
+ * pen_out[3] = {waves, LDS bytes, items per wave of the pipelined pencil
+ * (0: one item per wave)}, inv_out[6] like fwd_out (parity split 1). */
 kx_status kx_get_plan(kx_grid* g, int prec, int* fwd_out, int* pen_out, int* inv_out);
 
 /* E_x of the last kx_apply_exchange on this handle.  Synchronises the stream.

@@ -106,6 +106,8 @@ struct Work {
   double* epart = nullptr;   // per-strip energy partials, slots * nstrips
   unsigned* tmax = nullptr;  // split-FP16 per-item result maxima, slots
   Item* fitems = nullptr;    // (b, -1), b < slots: the items of a batch of fields
+  double* mpart = nullptr;   // multipole moment partials (all-Dirichlet grids), per slot
+  double* mmom = nullptr;    // multipole moments, per slot
   int slots = 0;             // items per launch
   size_t tbytes = 0;         // bytes per slot of T (8- or 4-byte values)
   Item* items = nullptr;     // pair schedule
@@ -320,6 +322,10 @@ std::vector<short> split3_f16(const std::vector<double>& a, int n) {
 
 size_t elem_size(int dtype) { return dtype == KX_F64 ? sizeof(double) : sizeof(float); }
 
+bool all_dirichlet(const kx_grid* g) {
+  return g->bc[0] == KX_BC_DIRICHLET && g->bc[1] == KX_BC_DIRICHLET && g->bc[2] == KX_BC_DIRICHLET;
+}
+
 bool all_periodic(const kx_grid* g) {
   return g->bc[0] == KX_BC_PERIODIC && g->bc[1] == KX_BC_PERIODIC && g->bc[2] == KX_BC_PERIODIC;
 }
@@ -394,9 +400,13 @@ kx_status reserve_slots(kx_grid* g, int slots, bool t2, bool aux16) {
     dev_free(w.T);
     dev_free(w.epart);
     dev_free(w.fitems);
+    dev_free(w.mpart);
+    dev_free(w.mmom);
     w.T = nullptr;
     w.epart = nullptr;
     w.fitems = nullptr;
+    w.mpart = nullptr;
+    w.mmom = nullptr;
     w.slots = 0;
     const size_t tb = sizeof(double) * (size_t)G.slot * ns;
     kx_status st = dev_alloc(&w.T, tb);
@@ -408,6 +418,13 @@ kx_status reserve_slots(kx_grid* g, int slots, bool t2, bool aux16) {
     st = dev_alloc((void**)&w.fitems, sizeof(Item) * ns);
     if (st != KX_OK) return st;
     KX_HIP(launch_field_items(ns, w.fitems, g->stream));
+    if (all_dirichlet(g)) {  // multipole boundary values of batches of fields
+      const size_t K = (size_t)(kMaxMultipoleL + 1) * (kMaxMultipoleL + 1);
+      st = dev_alloc((void**)&w.mpart, sizeof(double) * K * multipole_groups(G.N) * ns);
+      if (st != KX_OK) return st;
+      st = dev_alloc((void**)&w.mmom, sizeof(double) * K * ns);
+      if (st != KX_OK) return st;
+    }
     w.slots = ns;
     w.tbytes = sizeof(double) * (size_t)G.slot;
   }
@@ -483,6 +500,8 @@ kx_status reserve(kx_grid* g, int norb, int prec, int dtype) {
 }
 
 void free_work(Work& w) {
+  dev_free(w.mpart);
+  dev_free(w.mmom);
   dev_free(w.T);
   dev_free(w.T2);
   dev_free(w.epart);
@@ -1241,6 +1260,50 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   return KX_OK;
 }
 
+kx_status kx_apply_fL_multipole(kx_grid* g, int batch, int dtype, const void* rho_dev,
+                                void* phi_dev, int prec, int lmax, const double centre[3]) {
+  if (!g || batch < 0 || !centre) return KX_ERR_INVALID_ARG;
+  if (lmax < 0 || lmax > kMaxMultipoleL) return KX_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(centre[k])) return KX_ERR_INVALID_ARG;
+  if (!all_dirichlet(g)) return KX_ERR_UNSUPPORTED;
+  kx_status st = check_kernel_args(g, KX_KERNEL_COULOMB, 0.0);
+  if (st != KX_OK) return st;
+  st = check_types(g, dtype, prec);
+  if (st != KX_OK) return st;
+  if (batch == 0) return KX_OK;
+  if (!rho_dev || !phi_dev || rho_dev == phi_dev) return KX_ERR_INVALID_ARG;
+  if ((double)batch * (double)g->geom.N > 4.0e18) return KX_ERR_INVALID_ARG;
+  const Work& w = g->ws;
+  if (w.slots < 1 || !w.mpart || (prec == KX_PREC_MIXED && !w.T2) ||
+      (prec == KX_PREC_FP16X3 && (!w.tmax || w.omax_cap < w.slots)))
+    return KX_ERR_STATE;
+
+  double wfd[13];
+  fd_weights_closed_form(g->order, wfd);
+  hipStream_t s = g->stream;
+  g->recording = stream_capturing(s);
+  hipError_t e = fill_ftable(g, KX_KERNEL_COULOMB, 0.0, s);
+  const int chunk = std::min(batch, w.slots);
+  const size_t fb = elem_size(dtype) * (size_t)g->geom.N;
+  for (int b0 = 0; b0 < batch && e == hipSuccess; b0 += chunk) {
+    const int nb = std::min(chunk, batch - b0);
+    const void* src = static_cast<const char*>(rho_dev) + fb * b0;
+    void* dst = static_cast<char*>(phi_dev) + fb * b0;
+    // rho + c / (4 pi) into the output fields, then the solve in place
+    e = launch_multipole_rhs(dtype, src, dst, nb, g->geom, g->h, centre, wfd, g->order / 2, lmax,
+                             w.mpart, w.mmom, s);
+    if (e == hipSuccess && prec == KX_PREC_FP16X3)
+      e = launch_absmax(dst, dtype, (long long)g->geom.N, nb, w.omax, s);
+    if (e == hipSuccess)
+      e = run_batch(g, w, s, 0, prec, dtype, dst, w.fitems, nb, dtype, nullptr, nullptr, dst, 0,
+                    0.0);
+  }
+  g->recording = false;
+  KX_HIP(e);
+  return KX_OK;
+}
+
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
                             const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                             int prec) {
@@ -1412,10 +1475,10 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
     lds = 64 * 1024;
   }
   char key[256];
-  std::snprintf(key, sizeof key, "kx-tune-v1 %d %d %d %d %d %d %d %d %s %d", G.n1, G.n2, G.n3,
+  std::snprintf(key, sizeof key, "kx-tune-v2 %d %d %d %d %d %d %d %d %s %d", G.n1, G.n2, G.n3,
                 g->bc[0], g->bc[1], g->bc[2], kind, dtype_w, prop.gcnArchName,
                 prop.multiProcessorCount);
-  // cached result: "<key> | fwd qsplit slabs waves kc vlds lds | pen waves lds | inv slabs waves kc vlds lds"
+  // cached result: "<key> | fwd qsplit slabs waves kc vlds lds | pen waves lds per | inv slabs waves kc vlds lds"
   if (cache_path && !verify) {
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[512];
@@ -1427,9 +1490,9 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
         PencilPlan pn;
         int fv = 0, ivv = 0;
         unsigned long long fl = 0, pl = 0, il = 0;
-        if (std::sscanf(line + kl, " | fwd %d %d %d %d %d %llu | pen %d %llu | inv %d %d %d %d %llu",
+        if (std::sscanf(line + kl, " | fwd %d %d %d %d %d %llu | pen %d %llu %d | inv %d %d %d %d %llu",
                         &fw.qsplit, &fw.slabs, &fw.waves, &fw.kc, &fv, &fl, &pn.waves, &pl,
-                        &iv.slabs, &iv.waves, &iv.kc, &ivv, &il) == 13) {
+                        &pn.per, &iv.slabs, &iv.waves, &iv.kc, &ivv, &il) == 14) {
           fw.vlds = fv != 0;
           fw.lds_bytes = fl;
           pn.lds_bytes = pl;
@@ -1446,7 +1509,8 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
           bool okf = false, okp = false, oki = false;
           for (auto& c : cf) okf = okf || same(c, fw);
           for (auto& c : ci) oki = oki || same(c, iv);
-          for (auto& c : cp) okp = okp || (c.waves == pn.waves && c.lds_bytes == pn.lds_bytes);
+          for (auto& c : cp)
+            okp = okp || (c.waves == pn.waves && c.lds_bytes == pn.lds_bytes && c.per == pn.per);
           if (okf && okp && oki) {
             plan.fwd = fw;
             plan.pen = pn;
@@ -1656,10 +1720,11 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
   ++g->gen;  // recorded graphs carry the old launch shapes
   if (cache_path && !verify) {
     if (FILE* f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "%s | fwd %d %d %d %d %d %llu | pen %d %llu | inv %d %d %d %d %llu\n", key,
+      std::fprintf(f, "%s | fwd %d %d %d %d %d %llu | pen %d %llu %d | inv %d %d %d %d %llu\n", key,
                    bf.qsplit, bf.slabs, bf.waves, bf.kc, bf.vlds ? 1 : 0,
                    (unsigned long long)bf.lds_bytes, bp.waves, (unsigned long long)bp.lds_bytes,
-                   bi.slabs, bi.waves, bi.kc, bi.vlds ? 1 : 0, (unsigned long long)bi.lds_bytes);
+                   bp.per, bi.slabs, bi.waves, bi.kc, bi.vlds ? 1 : 0,
+                   (unsigned long long)bi.lds_bytes);
       std::fclose(f);
     }
   }
@@ -1675,11 +1740,11 @@ kx_status kx_get_plan(kx_grid* g, int prec, int* fwd_out, int* pen_out, int* inv
   if (prec == KX_PREC_MIXED) p.inv = g->plan_s.inv;
   const int f[6] = {p.fwd.qsplit, p.fwd.slabs, p.fwd.waves, p.fwd.kc, p.fwd.vlds ? 1 : 0,
                     (int)p.fwd.lds_bytes};
-  const int q[2] = {p.pen.waves, (int)p.pen.lds_bytes};
+  const int q[3] = {p.pen.waves, (int)p.pen.lds_bytes, p.pen.per};
   const int v[6] = {1, p.inv.slabs, p.inv.waves, p.inv.kc, p.inv.vlds ? 1 : 0,
                     (int)p.inv.lds_bytes};
   std::copy(f, f + 6, fwd_out);
-  std::copy(q, q + 2, pen_out);
+  std::copy(q, q + 3, pen_out);
   std::copy(v, v + 6, inv_out);
   return KX_OK;
 }

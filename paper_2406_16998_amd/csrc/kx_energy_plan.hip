@@ -382,6 +382,18 @@ void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPl
         pen.push_back(p);
       }
     }
+    // the pipelined pencil (V3 in LDS, two waves per SIMD, several items per wave)
+    if (!split && ntz <= kPipeMaxNT && vb <= max_lds) {
+      for (int w : {4, 8}) {
+        for (int per : {2, 4, 8, 16}) {
+          PencilPlan p;
+          p.waves = w;
+          p.lds_bytes = vb;
+          p.per = per;
+          pen.push_back(p);
+        }
+      }
+    }
   }
   {
     const int maxw = inv_mt(nty) / 64;

@@ -142,7 +142,9 @@ struct SlabPlan {
 struct PencilPlan {
   int waves = 8;
   size_t lds_bytes = 0;  // 0: V3 blocks read from global memory
+  int per = 0;           // > 0: pipelined kernel, `per` items per wave (tiles <= kPipeMaxNT)
 };
+constexpr int kPipeMaxNT = 3;  // the pipelined pencil's register budget (two waves per SIMD)
 struct Plan {
   SlabPlan fwd, inv;
   PencilPlan pen;
@@ -234,6 +236,19 @@ hipError_t launch_pair_energy(const double* epart, int nstrips, const Item* item
 // E_x = -1/4 sum_{i<=j} m_ij occ_i occ_j pair_e, m = 1 (i == j) or 2
 hipError_t launch_exchange_energy(const double* pair_e, const double* occ, int norb, double* ex,
                                   hipStream_t s);
+
+// ---- multipole boundary values (kx_multipole.hip)
+constexpr int kMaxMultipoleL = 6;        // largest expansion order
+constexpr int kMaxMultipoleGroups = 256;  // point groups per field of the moment reduction
+// point groups of the moment reduction of an N-point field
+int multipole_groups(long long N);
+// dst[b] = rho[b] + c_b / (4 pi) for nb fields (storage KX_F64 / KX_F32): c_b
+// from the multipole expansion (order lmax, about centre) of field b's charge,
+// evaluated at the nodes outside the grid that the stencil w[0..m] reaches.
+// part: nb * multipole_groups(N) * (lmax+1)^2 doubles; mom: nb * (lmax+1)^2.
+hipError_t launch_multipole_rhs(int storage, const void* rho, void* dst, int nb, const Geom& g,
+                                const double h[3], const double centre[3], const double* w, int m,
+                                int lmax, double* part, double* mom, hipStream_t s);
 
 // ---- compressed exchange algebra (kx_ace.hip); fields are rows of N values
 // point-range groups for a gram of na x nb (partials <= 128 MB)

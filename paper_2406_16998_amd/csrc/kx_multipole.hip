@@ -1,0 +1,253 @@
+// Dirichlet boundary values from the multipole expansion of the Coulomb
+// kernel for isolated systems (Sec. IV: the unscreened problem on a grid with
+// vacuum on every side takes its boundary values from the expansion, enforced
+// by modifying the right-hand side).
+//
+// With the stencil split into the nodes inside the grid (L_D) and those
+// outside, -L phi = 4 pi rho at node x reads
+//   -(L_D phi)(x) = 4 pi rho(x) + c(x),
+//   c(x) = sum_k sum_{p: x + p e_k outside} (w_|p| / h_k^2) phi_ext(x + p e_k),
+// so phi = f(-L_D)(rho + c / (4 pi)) with f = 4 pi / lam.  phi_ext is the
+// expansion about a centre C of the field's charge,
+//   phi_ext(r) = sum_{l <= lmax} sum_{m=0}^{l} (2 - [m = 0]) (l-m)!/(l+m)!
+//                  (A_lm R^c_lm(d) + B_lm R^s_lm(d)) / |d|^(2l+1),   d = r - C,
+//   A_lm + i B_lm = dV sum_r rho(r) (R^c_lm + i R^s_lm)(r - C),
+// with the regular solid harmonics R^c_lm + i R^s_lm = Q_l^m(z, |d|^2) (x + i y)^m
+// (r^l P_l^m(cos t) e^{i m p}), Q by the three-term recursion in l.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "kx_internal.h"
+
+namespace kx {
+namespace {
+
+constexpr int kMomThreads = 256;
+constexpr int kMomPoints = 16;  // points per thread per group
+
+// moment index of (l, m, part): l^2 + 2 m - (m > 0) + part, part 0 = cos, 1 = sin
+// (m = 0 has no sine part): (lmax + 1)^2 values in all
+__host__ __device__ inline int mom_index(int l, int m, int part) {
+  return l * l + (m == 0 ? 0 : 2 * m - 1 + part);
+}
+
+// R^c_lm, R^s_lm of d for l <= L into out[mom_index]
+template <int L>
+__device__ __forceinline__ void solid_harmonics(double x, double y, double z, double* out) {
+  const double r2 = x * x + y * y + z * z;
+  double cm = 1.0, sm = 0.0;  // (x + i y)^m
+  double dfac = 1.0;          // (2m - 1)!!
+#pragma unroll
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) {
+      const double c2 = x * cm - y * sm, s2 = y * cm + x * sm;
+      cm = c2;
+      sm = s2;
+      dfac *= (double)(2 * m - 1);
+    }
+    double q2 = 0.0, q1 = dfac;  // Q_{m-1}^m = 0, Q_m^m = (2m-1)!!
+#pragma unroll
+    for (int l = m; l <= L; ++l) {
+      double q = q1;
+      if (l > m) {
+        q = ((double)(2 * l - 1) * z * q1 - (double)(l + m - 1) * r2 * q2) / (double)(l - m);
+        q2 = q1;
+        q1 = q;
+      }
+      out[mom_index(l, m, 0)] = q * cm;
+      if (m > 0) out[mom_index(l, m, 1)] = q * sm;
+    }
+  }
+}
+
+struct Coords {
+  double h[3];  // spacings
+  double c[3];  // expansion centre
+};
+
+// partial moments of points [g * span, (g + 1) * span) of field b
+template <class S, int L>
+__global__ void __launch_bounds__(kMomThreads)
+moments_partial(const S* __restrict__ rho, Geom g, Coords cc, long long span,
+                double* __restrict__ part) {
+  constexpr int K = (L + 1) * (L + 1);
+  __shared__ double red[kMomThreads / 64][K];
+  const int grp = blockIdx.x, b = blockIdx.y, ngrp = gridDim.x;
+  const S* __restrict__ f = rho + (long long)b * g.N;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  const long long p0 = (long long)grp * span, p1 = p0 + span < g.N ? p0 + span : g.N;
+  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const int i1 = (int)(p % g.n1);
+    const int i2 = (int)((p / g.n1) % g.n2);
+    const int i3 = (int)(p / ((long long)g.n1 * g.n2));
+    const double v = (double)f[p];
+    double R[K];
+    solid_harmonics<L>(i1 * cc.h[0] - cc.c[0], i2 * cc.h[1] - cc.c[1], i3 * cc.h[2] - cc.c[2], R);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += v * R[k];
+  }
+  // fixed-shape reduction: wave trees, then the waves in index order
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < kMomThreads / 64; ++w) s += red[w][k];
+    part[((long long)b * ngrp + grp) * K + k] = s;
+  }
+}
+
+// moments[b][k] = dV * sum over groups in order
+__global__ void __launch_bounds__(64) moments_reduce(const double* __restrict__ part, int ngrp,
+                                                     int K, double dV, double* __restrict__ mom) {
+  const int b = blockIdx.x;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < ngrp; ++q) s += part[((long long)b * ngrp + q) * K + k];
+    mom[(long long)b * K + k] = dV * s;
+  }
+}
+
+struct Stencil {
+  double w[13];  // w_0 .. w_m of the second-derivative stencil
+  int m;
+  double wl[(kMaxMultipoleL + 1) * (kMaxMultipoleL + 2) / 2];  // (2 - [m=0]) (l-m)!/(l+m)!
+};
+
+template <int L>
+__device__ __forceinline__ double expanded_potential(const double* __restrict__ mom,
+                                                     const Stencil& st, double x, double y,
+                                                     double z) {
+  constexpr int K = (L + 1) * (L + 1);
+  double R[K];
+  solid_harmonics<L>(x, y, z, R);
+  const double r2 = x * x + y * y + z * z;
+  const double ir2 = 1.0 / r2, ir = sqrt(ir2);
+  double phi = 0.0, scale = ir;  // 1 / |d|^(2l+1)
+  int t = 0;
+#pragma unroll
+  for (int l = 0; l <= L; ++l) {
+    double sl = 0.0;
+#pragma unroll
+    for (int m = 0; m <= l; ++m, ++t) {
+      double term = mom[mom_index(l, m, 0)] * R[mom_index(l, m, 0)];
+      if (m > 0) term += mom[mom_index(l, m, 1)] * R[mom_index(l, m, 1)];
+      sl += st.wl[t] * term;
+    }
+    phi += sl * scale;
+    scale *= ir2;
+  }
+  return phi;
+}
+
+// dst = rho + c / (4 pi) for every node of field b (c from the field's moments)
+template <class S, int L>
+__global__ void __launch_bounds__(256)
+boundary_rhs(const S* __restrict__ rho, S* __restrict__ dst, Geom g, Coords cc, Stencil st,
+             const double* __restrict__ moments) {
+  constexpr int K = (L + 1) * (L + 1);
+  const int b = blockIdx.y;
+  const double* __restrict__ mom = moments + (long long)b * K;
+  const S* __restrict__ f = rho + (long long)b * g.N;
+  S* __restrict__ o = dst + (long long)b * g.N;
+  const int n[3] = {g.n1, g.n2, g.n3};
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < g.N;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int idx[3] = {(int)(p % g.n1), (int)((p / g.n1) % g.n2),
+                        (int)(p / ((long long)g.n1 * g.n2))};
+    double c = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const int i = idx[k];
+      const int lo = st.m - i, hi = i + st.m - (n[k] - 1);  // outside reach below / above
+      if (lo <= 0 && hi <= 0) continue;
+      const double ih2 = 1.0 / (cc.h[k] * cc.h[k]);
+      for (int pp = 1; pp <= st.m; ++pp) {
+        for (int side = 0; side < 2; ++side) {
+          const int j = side == 0 ? i - pp : i + pp;
+          if (j >= 0 && j < n[k]) continue;
+          double xyz[3] = {idx[0] * cc.h[0] - cc.c[0], idx[1] * cc.h[1] - cc.c[1],
+                           idx[2] * cc.h[2] - cc.c[2]};
+          xyz[k] = j * cc.h[k] - cc.c[k];
+          c += st.w[pp] * ih2 * expanded_potential<L>(mom, st, xyz[0], xyz[1], xyz[2]);
+        }
+      }
+    }
+    o[p] = (S)((double)f[p] + c * (1.0 / (4.0 * M_PI)));
+  }
+}
+
+template <class S, int L>
+hipError_t launch_typed(const S* rho, S* dst, int nb, const Geom& g, const Coords& cc,
+                        const Stencil& st, double dV, double* part, int ngrp, double* mom,
+                        hipStream_t s) {
+  constexpr int K = (L + 1) * (L + 1);
+  const long long span = (g.N + ngrp - 1) / ngrp;
+  hipLaunchKernelGGL((moments_partial<S, L>), dim3(ngrp, nb), dim3(kMomThreads), 0, s, rho, g, cc,
+                     span, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(moments_reduce, dim3(nb), dim3(64), 0, s, part, ngrp, K, dV, mom);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long blocks = std::min<long long>((g.N + 255) / 256, 4096);
+  hipLaunchKernelGGL((boundary_rhs<S, L>), dim3((unsigned)blocks, nb), dim3(256), 0, s, rho, dst,
+                     g, cc, st, mom);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int multipole_groups(long long N) {
+  long long grp = (N + (long long)kMomThreads * kMomPoints - 1) / ((long long)kMomThreads * kMomPoints);
+  if (grp > kMaxMultipoleGroups) grp = kMaxMultipoleGroups;
+  return grp < 1 ? 1 : (int)grp;
+}
+
+hipError_t launch_multipole_rhs(int storage, const void* rho, void* dst, int nb, const Geom& g,
+                                const double h[3], const double centre[3], const double* w, int m,
+                                int lmax, double* part, double* mom, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (lmax < 0 || lmax > kMaxMultipoleL || m < 1 || m > 12) return hipErrorInvalidValue;
+  Coords cc;
+  Stencil st;
+  for (int k = 0; k < 3; ++k) {
+    cc.h[k] = h[k];
+    cc.c[k] = centre[k];
+  }
+  for (int p = 0; p <= 12; ++p) st.w[p] = p <= m ? w[p] : 0.0;
+  st.m = m;
+  int t = 0;
+  for (int l = 0; l <= kMaxMultipoleL; ++l)
+    for (int mm = 0; mm <= l; ++mm, ++t) {
+      // (l - mm)! / (l + mm)! as a product, then the factor 2 for mm > 0
+      double ratio = 1.0;
+      for (int q = l - mm + 1; q <= l + mm; ++q) ratio /= (double)q;
+      st.wl[t] = (mm == 0 ? 1.0 : 2.0) * ratio;
+    }
+  const double dV = h[0] * h[1] * h[2];
+  const int ngrp = multipole_groups(g.N);
+#define KX_L(LL)                                                                               \
+  case LL:                                                                                     \
+    return storage == KX_F64                                                                   \
+               ? launch_typed<double, LL>((const double*)rho, (double*)dst, nb, g, cc, st, dV, \
+                                          part, ngrp, mom, s)                                  \
+               : launch_typed<float, LL>((const float*)rho, (float*)dst, nb, g, cc, st, dV,    \
+                                         part, ngrp, mom, s);
+  switch (lmax) {
+    KX_L(0) KX_L(1) KX_L(2) KX_L(3) KX_L(4) KX_L(5) KX_L(6)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef KX_L
+}
+
+}  // namespace kx

@@ -28,7 +28,7 @@ EXPORTS = (
     "kx_pair_energies", "kx_get_eigensystem", "kx_destroy", "kx_status_string",
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
-    "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc",
+    "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc", "kx_apply_fL_multipole",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -61,6 +61,7 @@ def lib():
             "kx_apply_exchange": [vp, c_int, c_double, c_int, c_int, vp, dp, vp, c_int],
             "kx_apply_exchange_noalloc": [vp, c_int, c_double, c_int, c_int, vp, dp, vp, c_int],
             "kx_reserve": [vp, c_int, c_int, c_int],
+            "kx_apply_fL_multipole": [vp, c_int, c_int, vp, vp, c_int, c_int, dp],
             "kx_exchange_energy": [vp, dp],
             "kx_pair_energies": [vp, c_int, ip, dp],
             "kx_get_eigensystem": [vp, c_int, dp, dp],
@@ -276,6 +277,27 @@ class Grid:
         _check(st, "kx_apply_fL")
         return out
 
+    def apply_fL_multipole(self, rho, centre=None, lmax=6, prec="fp64", out=None, reserve=True):
+        """phi = (-L_D)^{-1} (4 pi rho + c): the unscreened potential of the
+        densities rho (batch, n3, n2, n1) with Dirichlet values from the
+        multipole expansion about centre (default: the grid's centre, node i
+        of axis k at i h_k)."""
+        import numpy as np
+        import torch
+        dt = check_fields(rho, self.shape3, self.device, "rho")
+        if out is None:
+            out = torch.empty_like(rho)
+        check_out(out, rho)
+        if centre is None:
+            centre = [(self.n[k] - 1) * self.h[k] / 2 for k in range(3)]
+        c = np.ascontiguousarray(np.asarray(centre, dtype=np.float64).reshape(3))
+        if reserve:
+            self.reserve(0, prec, "f64" if dt == DTYPE["f64"] else "f32")
+        st = lib().kx_apply_fL_multipole(self._h, rho.shape[0], dt, _ptr(rho), _ptr(out), PREC[prec],
+                                         int(lmax), _dptr(c))
+        _check(st, "kx_apply_fL_multipole")
+        return out
+
     def _exchange_args(self, psi, occ, out):
         import torch
         dt = check_fields(psi, self.shape3, self.device, "psi")
@@ -362,10 +384,10 @@ class Grid:
 
     def plan(self, prec="fp64"):
         """Launch shapes in use: dicts for the forward, pencil and inverse passes."""
-        f, p, v = (ctypes.c_int * 6)(), (ctypes.c_int * 2)(), (ctypes.c_int * 6)()
+        f, p, v = (ctypes.c_int * 6)(), (ctypes.c_int * 3)(), (ctypes.c_int * 6)()
         _check(lib().kx_get_plan(self._h, PREC[prec], f, p, v), "kx_get_plan")
         keys = ("qsplit", "slabs", "waves", "kc", "vlds", "lds_bytes")
-        return (dict(zip(keys, list(f))), {"waves": p[0], "lds_bytes": p[1]},
+        return (dict(zip(keys, list(f))), {"waves": p[0], "lds_bytes": p[1], "per": p[2]},
                 dict(zip(keys, list(v))))
 
     def profile(self, enable=True):

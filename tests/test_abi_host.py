@@ -102,6 +102,8 @@ def test_null_handle_and_host_helper_validation():
     assert L.kx_ace_build(None, 4, 0, None, None, None) == 1
     assert L.kx_ace_apply(None, 4, 0, None, 1, None, None) == 1
     assert L.kx_profile_phases(None, 1) == 1
+    assert L.kx_apply_fL_multipole(None, 1, 0, None, None, 0, 2, dp) == 1
+    assert L.kx_reserve(None, 4, 0, 0) == 1
     assert L.kx_destroy(None) == 0
     assert L.kx_fd_weights(13, dp) == 1 and L.kx_fd_weights(12, None) == 1
     assert L.kx_laplacian_1d(0, 0.3, 12, 0, dp) == 1

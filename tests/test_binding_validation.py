@@ -44,6 +44,7 @@ def _grid():
     g = kx.Grid.__new__(kx.Grid)
     g._h = None
     g.n = (SHAPE3[2], SHAPE3[1], SHAPE3[0])
+    g.h = (0.3, 0.3, 0.3)
     g.shape3 = SHAPE3
     g.device = 0
     g.N = int(np.prod(SHAPE3))
@@ -80,6 +81,8 @@ def test_bad_input_tensor_is_rejected(no_library, case):
         g.apply_exchange_noalloc(x, [2.0] * 3, "erfc", 0.1)
     with pytest.raises(ValueError):
         g.apply_fL(x, "erfc", 0.1)
+    with pytest.raises(ValueError):
+        g.apply_fL_multipole(x, lmax=2)
     with pytest.raises(ValueError):
         g.ace_apply(x, FakeDev(GOOD, ptr=1 << 30), out=FakeDev(GOOD, ptr=1 << 31))
 

@@ -61,7 +61,7 @@ def test_cache_file_round_trip(kx, tmp_path):
     g1 = kx.Grid(n, (0.3,) * 3, 12, bc)
     g1.autotune(prec="bf16x3", dtype="f32", items=16, cache_path=str(path))
     lines = path.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("kx-tune-v1 48 48 48")
+    assert len(lines) == 1 and lines[0].startswith("kx-tune-v2 48 48 48")
     g2 = kx.Grid(n, (0.3,) * 3, 12, bc)
     g2.autotune(prec="bf16x3", dtype="f32", items=16, cache_path=str(path))
     assert len(path.read_text().splitlines()) == 1  # read, not tuned again
