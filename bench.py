@@ -326,6 +326,45 @@ def measure_ace(g, psi_d, vx, w, reps=5):
             "build_GBps": 4 * field / (build_ms * 1e-3) / 1e9}
 
 
+def measure_multipole(nfields=64, lmax=6, reps=5):
+    """Single solves on an isolated-system grid (80^3 Dirichlet, h = 0.3,
+    order 12, the grid of the ragged batch's third system): kx_apply_fL with
+    homogeneous Dirichlet values against kx_apply_fL_multipole (boundary
+    values from the multipole expansion to lmax), FP64, on the pair densities
+    psi_0 psi_j of that system's orbitals; mean of `reps` calls after one
+    warm-up, HIP events on the library's stream."""
+    import numpy as np
+    import torch
+
+    from paper_2406_16998_amd import kx
+    from synth import make_workload
+    w, psi, _ = make_workload("ragged_c_dirichlet80")
+    k = min(nfields, w.norb)
+    rho = torch.from_numpy(np.ascontiguousarray(psi[0:1] * psi[:k])).cuda()
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    g = kx.Grid(w.n, w.h, w.order, w.bc, stream=stream)
+    out = torch.empty_like(rho)
+    res = {}
+    for name, call in (("homogeneous", lambda: g.apply_fL(rho, "coulomb", out=out)),
+                       ("multipole", lambda: g.apply_fL_multipole(rho, lmax=lmax, out=out))):
+        call()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            start.record(stream)
+            for _ in range(reps):
+                call()
+            stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / reps
+        res[name] = {"ms_per_call": ms, "solves_per_s": k / (ms * 1e-3)}
+    g.close()
+    res.update({"grid": list(w.n), "fields": k, "lmax": lmax, "prec": "fp64"})
+    return res
+
+
 def bench_ragged(args):
     """The six-system ragged batch through kx_batch_apply_exchange (one graph
     replay per step).  The call synchronises, so steps are timed on the host
@@ -395,6 +434,8 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner result file: read if it holds this grid, else appended")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-multipole", action="store_true",
+                    help="skip the isolated-system single-solve timing")
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of replays of a recorded graph")
     args = ap.parse_args()
@@ -486,6 +527,8 @@ def main():
             None if not split_ok else
             {p: runs[p]["value"] / runs["fp64"]["value"] for p in split_ok})
     result["ace"] = measure_ace(g, psi_d, vx, w)
+    if not args.no_multipole:
+        result["multipole"] = measure_multipole()
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, psi, occ)

@@ -382,6 +382,16 @@ void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPl
         pen.push_back(p);
       }
     }
+    // split pencils: the pre-split V3 planes in LDS
+    if (split && spen_vbytes(g) <= max_lds) {
+      for (int w : {2, 4, 8, 16}) {
+        if (w > maxw) continue;
+        PencilPlan p;
+        p.waves = w;
+        p.lds_bytes = spen_vbytes(g);
+        pen.push_back(p);
+      }
+    }
     // the pipelined pencil (V3 in LDS, two waves per SIMD, several items per wave)
     if (!split && ntz <= kPipeMaxNT && vb <= max_lds) {
       for (int w : {4, 8}) {

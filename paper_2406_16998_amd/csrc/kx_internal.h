@@ -90,6 +90,13 @@ __host__ __device__ inline size_t sinv_vbytes(const Geom& g) {
   const size_t b = 2 * 3 * ((size_t)g.pe2 * sinv_ld(g.pe2) + (size_t)g.po2 * sinv_ld(g.po2));
   return (b + 15) / 16 * 16;
 }
+// Split pencil with its V3 blocks in LDS: row padding (bf16 elements) and the
+// bytes of the three planes of both blocks in both orientations.
+__host__ __device__ inline int spen_pad() { return 4; }
+__host__ __device__ inline size_t spen_vbytes(const Geom& g) {
+  return (size_t)2 * 3 * 2 *
+         ((size_t)g.pe3 * (g.pe3 + spen_pad()) + (size_t)g.po3 * (g.po3 + spen_pad()));
+}
 // Elements (of the operand type) of LDS per z-slab of an inverse launch: two
 // staged chunks of kc rows, reused afterwards for the output: the slab's phi
 // plane (n1 x n2), or one output band (2 kTile rows of n1) at a time.

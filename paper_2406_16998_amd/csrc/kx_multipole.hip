@@ -149,39 +149,66 @@ __device__ __forceinline__ double expanded_potential(const double* __restrict__ 
   return phi;
 }
 
-// dst = rho + c / (4 pi) for every node of field b (c from the field's moments)
+// dst = rho for every node of the fields (c is added afterwards, one axis at a
+// time)
+template <class S>
+__global__ void __launch_bounds__(256)
+copy_fields(const S* __restrict__ rho, S* __restrict__ dst, long long n) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    dst[k] = rho[k];
+}
+
+// dst += c_k / (4 pi) for axis k: one thread per grid line along axis k of
+// field b.  It evaluates the expansion at the m nodes beyond each end of its
+// line, once each, then adds to every node x of the line within reach
+//   sum_{p: x - q outside, q = x + p} (w_q / h_k^2) phi_ext(-p)        (low end)
+// + sum_{p: x + q outside, q = n_k - 1 - x + p} (w_q / h_k^2) phi_ext(n_k - 1 + p).
+// One launch per axis, so that lines of different axes never update a node
+// at the same time.
 template <class S, int L>
 __global__ void __launch_bounds__(256)
-boundary_rhs(const S* __restrict__ rho, S* __restrict__ dst, Geom g, Coords cc, Stencil st,
-             const double* __restrict__ moments) {
+boundary_axis(S* __restrict__ dst, Geom g, Coords cc, Stencil st,
+              const double* __restrict__ moments, int k) {
   constexpr int K = (L + 1) * (L + 1);
   const int b = blockIdx.y;
   const double* __restrict__ mom = moments + (long long)b * K;
-  const S* __restrict__ f = rho + (long long)b * g.N;
-  S* __restrict__ o = dst + (long long)b * g.N;
   const int n[3] = {g.n1, g.n2, g.n3};
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < g.N;
-       p += (long long)gridDim.x * blockDim.x) {
-    const int idx[3] = {(int)(p % g.n1), (int)((p / g.n1) % g.n2),
-                        (int)(p / ((long long)g.n1 * g.n2))};
-    double c = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      const int i = idx[k];
-      const int lo = st.m - i, hi = i + st.m - (n[k] - 1);  // outside reach below / above
-      if (lo <= 0 && hi <= 0) continue;
-      const double ih2 = 1.0 / (cc.h[k] * cc.h[k]);
-      for (int pp = 1; pp <= st.m; ++pp) {
-        for (int side = 0; side < 2; ++side) {
-          const int j = side == 0 ? i - pp : i + pp;
-          if (j >= 0 && j < n[k]) continue;
-          double xyz[3] = {idx[0] * cc.h[0] - cc.c[0], idx[1] * cc.h[1] - cc.c[1],
-                           idx[2] * cc.h[2] - cc.c[2]};
-          xyz[k] = j * cc.h[k] - cc.c[k];
-          c += st.w[pp] * ih2 * expanded_potential<L>(mom, st, xyz[0], xyz[1], xyz[2]);
-        }
-      }
+  const int ka = k == 0 ? 1 : 0, kb = k == 2 ? 1 : 2;  // the other two axes
+  const long long lines = (long long)n[ka] * n[kb];
+  const long long line = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= lines) return;
+  int idx[3];
+  idx[ka] = (int)(line % n[ka]);
+  idx[kb] = (int)(line / n[ka]);
+  idx[k] = 0;
+  const long long stride = k == 0 ? 1 : (k == 1 ? (long long)g.n1 : (long long)g.n1 * g.n2);
+  const long long base = idx[0] + (long long)g.n1 * (idx[1] + (long long)g.n2 * idx[2]);
+  double xyz[3] = {idx[0] * cc.h[0] - cc.c[0], idx[1] * cc.h[1] - cc.c[1],
+                   idx[2] * cc.h[2] - cc.c[2]};
+  const int m = st.m, nk = n[k];
+  double lo[13], hi[13];  // phi_ext at -p and at n_k - 1 + p, p = 1..m
+#pragma unroll 1
+  for (int p = 1; p <= m; ++p) {
+    xyz[k] = -p * cc.h[k] - cc.c[k];
+    lo[p] = expanded_potential<L>(mom, st, xyz[0], xyz[1], xyz[2]);
+    xyz[k] = (nk - 1 + p) * cc.h[k] - cc.c[k];
+    hi[p] = expanded_potential<L>(mom, st, xyz[0], xyz[1], xyz[2]);
+  }
+  const double scale = 1.0 / (cc.h[k] * cc.h[k] * 4.0 * M_PI);
+  S* __restrict__ o = dst + (long long)b * g.N + base;
+#pragma unroll 1
+  for (int x = 0; x < nk; ++x) {
+    const int dl = x, dh = nk - 1 - x;  // distances to the two ends
+    if (dl >= m && dh >= m) {
+      x = nk - m - 1;  // skip to the first node the high end reaches
+      continue;
     }
-    o[p] = (S)((double)f[p] + c * (1.0 / (4.0 * M_PI)));
+    double c = 0.0;
+    for (int p = 1; p + dl <= m; ++p) c += st.w[p + dl] * lo[p];
+    for (int p = 1; p + dh <= m; ++p) c += st.w[p + dh] * hi[p];
+    S* q = o + x * stride;
+    *q = (S)((double)*q + c * scale);
   }
 }
 
@@ -198,10 +225,18 @@ hipError_t launch_typed(const S* rho, S* dst, int nb, const Geom& g, const Coord
   hipLaunchKernelGGL(moments_reduce, dim3(nb), dim3(64), 0, s, part, ngrp, K, dV, mom);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long long blocks = std::min<long long>((g.N + 255) / 256, 4096);
-  hipLaunchKernelGGL((boundary_rhs<S, L>), dim3((unsigned)blocks, nb), dim3(256), 0, s, rho, dst,
-                     g, cc, st, mom);
-  return hipGetLastError();
+  const long long tot = (long long)nb * g.N;
+  const long long blocks = std::min<long long>((tot + 255) / 256, 8192);
+  hipLaunchKernelGGL(copy_fields<S>, dim3((unsigned)blocks), dim3(256), 0, s, rho, dst, tot);
+  e = hipGetLastError();
+  const int n[3] = {g.n1, g.n2, g.n3};
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    const long long lines = (long long)n[k == 0 ? 1 : 0] * n[k == 2 ? 1 : 2];
+    hipLaunchKernelGGL((boundary_axis<S, L>), dim3((unsigned)((lines + 255) / 256), nb), dim3(256),
+                       0, s, dst, g, cc, st, mom, k);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace

@@ -359,7 +359,11 @@ split_forward(Geom g, EigS e, const S* __restrict__ src, const Item* __restrict_
 // ================================================================ pencil
 // tmax (FP16): per item, the largest magnitude of the result (float bits,
 // raised with atomic maxima; zero before the launch).
-template <class H, int NT, bool OFULL, int MT>
+// VL: the three planes of the pre-split V3 blocks (both orientations) are
+// copied into LDS once per workgroup, rows padded by spen_pad elements so that
+// the 16 rows an operand read touches start in different banks; otherwise
+// every MFMA group reads them from global memory (L2).
+template <class H, int NT, bool OFULL, bool VL, int MT>
 __global__ void __launch_bounds__(MT)
 split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T,
              double* __restrict__ epart, unsigned* __restrict__ tmax) {
@@ -376,6 +380,44 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
   const int it = blockIdx.y;
   float* __restrict__ Tb = T + (long long)it * g.slot + q0;
   const int pe = g.pe3, po = g.po3;
+  // operand sources: global (row stride pe / po, plane stride pe^2 / po^2) or LDS
+  const short* sET = e.ET[2];
+  const short* sOT = e.OT[2];
+  const short* sE = e.E[2];
+  const short* sO = e.O[2];
+  int lde = pe, ldo = po, pse = pe * pe, pso = po * po;
+  if constexpr (VL) {
+    short* lds = reinterpret_cast<short*>(kx_split_lds);
+    lde = pe + spen_pad();
+    ldo = po + spen_pad();
+    pse = pe * lde;
+    pso = po * ldo;
+    short* dET = lds;
+    short* dOT = dET + 3 * pse;
+    short* dE = dOT + 3 * pso;
+    short* dO = dE + 3 * pse;
+    // 4 bf16 (8 bytes) a thread per step; rows are multiples of 4 elements
+    for (int idx = tid; idx < 3 * pe * pe / 4; idx += blockDim.x) {
+      const int pl = idx / (pe * pe / 4), rem = idx - pl * (pe * pe / 4);
+      const int row = rem / (pe / 4), col = (rem - row * (pe / 4)) * 4;
+      *reinterpret_cast<s4*>(dET + pl * pse + row * lde + col) =
+          *reinterpret_cast<const s4*>(e.ET[2] + pl * pe * pe + row * pe + col);
+      *reinterpret_cast<s4*>(dE + pl * pse + row * lde + col) =
+          *reinterpret_cast<const s4*>(e.E[2] + pl * pe * pe + row * pe + col);
+    }
+    for (int idx = tid; idx < 3 * po * po / 4; idx += blockDim.x) {
+      const int pl = idx / (po * po / 4), rem = idx - pl * (po * po / 4);
+      const int row = rem / (po / 4), col = (rem - row * (po / 4)) * 4;
+      *reinterpret_cast<s4*>(dOT + pl * pso + row * ldo + col) =
+          *reinterpret_cast<const s4*>(e.OT[2] + pl * po * po + row * po + col);
+      *reinterpret_cast<s4*>(dO + pl * pso + row * ldo + col) =
+          *reinterpret_cast<const s4*>(e.O[2] + pl * po * po + row * po + col);
+    }
+    sET = dET;
+    sOT = dOT;
+    sE = dE;
+    sO = dO;
+  }
 
   // folded column values, k-step t (z' = 16 t + 4 lg + e)
   Split4 be[NT], bo[NT];
@@ -418,6 +460,7 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
     }
   }
   const float un3 = 1.f / (H::kVScale * sc3);
+  if constexpr (VL) __syncthreads();
 
   // mode 3 (folded):  C[c][q] += A[c][z'] B[z'][q],  A[c][z'] = V3p[z'][c] = V3pT[c][z']
   f4 accE[NT], accO[NT];
@@ -430,13 +473,13 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
   for (int k = 0; k < NTE; ++k) {
 #pragma unroll
     for (int t = 0; t < NTE; ++t) {
-      const Split4 a = load_split(e.ET[2] + (kTile * t + li) * pe + kTile * k + 4 * lg, pe * pe);
+      const Split4 a = load_split(sET + (kTile * t + li) * lde + kTile * k + 4 * lg, pse);
       accE[t] = mma6<H>(a, be[k], accE[t]);
     }
     if (k < NTO) {
 #pragma unroll
       for (int t = 0; t < NTO; ++t) {
-        const Split4 a = load_split(e.OT[2] + (kTile * t + li) * po + kTile * k + 4 * lg, po * po);
+        const Split4 a = load_split(sOT + (kTile * t + li) * ldo + kTile * k + 4 * lg, pso);
         accO[t] = mma6<H>(a, bo[k], accO[t]);
       }
     }
@@ -483,7 +526,7 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
       const Split4 b = split4<H>(accE[t][0], accE[t][1], accE[t][2], accE[t][3], sc4);
 #pragma unroll
       for (int u = 0; u < NTE; ++u) {
-        const Split4 a = load_split(e.E[2] + (kTile * u + li) * pe + kTile * t + 4 * lg, pe * pe);
+        const Split4 a = load_split(sE + (kTile * u + li) * lde + kTile * t + 4 * lg, pse);
         outE[u] = mma6<H>(a, b, outE[u]);
       }
     }
@@ -491,7 +534,7 @@ split_pencil(Geom g, EigS e, const double* __restrict__ F, float* __restrict__ T
       const Split4 b = split4<H>(accO[t][0], accO[t][1], accO[t][2], accO[t][3], sc4);
 #pragma unroll
       for (int u = 0; u < NTO; ++u) {
-        const Split4 a = load_split(e.O[2] + (kTile * u + li) * po + kTile * t + 4 * lg, po * po);
+        const Split4 a = load_split(sO + (kTile * u + li) * ldo + kTile * t + 4 * lg, pso);
         outO[u] = mma6<H>(a, b, outO[u]);
       }
     }
@@ -757,12 +800,18 @@ hipError_t spen_launch(const Geom& g, const PencilPlan& p, const EigS& e, const 
   const dim3 grid((unsigned)((nstrips + w - 1) / w), nitems);
   const dim3 block(64 * w);
   const bool of = g.po3 == g.pe3;
+  const size_t lb = p.lds_bytes;
+  if (lb > 0 && lb < spen_vbytes(g)) return hipErrorInvalidValue;
   switch (g.pe3 / kTile) {
 #define KX_CASE(NT)                                                                      \
   case NT: {                                                                             \
     constexpr int MT = pen_mt(NT);                                                       \
-    auto k = of ? split_pencil<H, NT, true, MT> : split_pencil<H, NT, false, MT>;        \
-    hipLaunchKernelGGL(k, grid, block, 0, st, g, e, F, T, epart, tmax);                  \
+    auto k = lb > 0 ? (of ? split_pencil<H, NT, true, true, MT>                          \
+                          : split_pencil<H, NT, false, true, MT>)                        \
+                    : (of ? split_pencil<H, NT, true, false, MT>                         \
+                          : split_pencil<H, NT, false, false, MT>);                      \
+    allow_lds(k, lb);                                                                    \
+    hipLaunchKernelGGL(k, grid, block, lb, st, g, e, F, T, epart, tmax);                 \
     break;                                                                               \
   }
     KX_NT_CASES(KX_CASE)
