@@ -11,12 +11,17 @@ from .kx_oracle import (  # noqa: F401
     ace_build,
     apply_coulomb_multipole,
     apply_fL,
+    apply_fL_bloch,
+    bloch_phases,
     exchange,
+    exchange_bloch,
     fd_weights,
     forward_transform,
     kernel_values,
     laplacian_1d,
+    laplacian_1d_bloch,
     make_grid,
+    make_grid_bloch,
     multipole_moments,
     multipole_potential,
     multipole_rhs_correction,

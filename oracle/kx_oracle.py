@@ -394,3 +394,105 @@ def apply_coulomb_multipole(rho, grid, centre, lmax):
     rho + c / (4 pi))."""
     c = multipole_rhs_correction(rho, grid, centre, lmax)
     return apply_fL(np.asarray(rho, dtype=np.float64) + c / FOUR_PI, grid, "coulomb")
+
+
+# --------------------------------------------------------------------------
+# Sec. II with Brillouin-zone sampling: the Poisson problem for the pair
+# (m q, n k) carries Bloch boundary conditions at the wavevector k - q along
+# the extended (periodic) directions.  On the grid, a periodic axis of n
+# nodes then wraps its stencil with the phase u(x + n h) = e^{i theta} u(x),
+# theta = 2 pi (k - q)_a in reduced coordinates.
+# --------------------------------------------------------------------------
+def laplacian_1d_bloch(n: int, h: float, order: int, theta: float) -> np.ndarray:
+    """n x n complex Hermitian L_k: the centred stencil with every entry that
+    wraps past the end of the period multiplied by e^{+i theta} (one period
+    forward) or e^{-i theta} (one period back)."""
+    w = [float(x) for x in fd_weights(order)]
+    m = order // 2
+    L = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        for p in range(-m, m + 1):
+            j = i + p
+            wrap = j // n  # -1, 0 or +1 periods (more for tiny n)
+            L[i, j % n] += w[abs(p)] * np.exp(1j * theta * wrap)
+    return L / (h * h)
+
+
+def make_grid_bloch(n, h, order, bc, theta) -> Grid:
+    """Eigendecompositions of -L_k(theta_k) (numpy eigh, complex Hermitian on
+    periodic axes; Dirichlet axes take no phase and must have theta_k = 0)."""
+    lams, Vs = [], []
+    for k in range(3):
+        if bc[k] == "periodic":
+            A = -laplacian_1d_bloch(n[k], h[k], order, theta[k])
+        else:
+            if theta[k] != 0.0:
+                raise ValueError("a Dirichlet axis carries no Bloch phase")
+            A = -laplacian_1d(n[k], h[k], order, bc[k])
+        lam, V = np.linalg.eigh(A)
+        lams.append(lam)
+        Vs.append(V)
+    return Grid(tuple(n), tuple(h), order, tuple(bc), tuple(lams), tuple(Vs))
+
+
+def apply_fL_bloch(rho: np.ndarray, grid: Grid, kernel: str, omega: float = 0.0) -> np.ndarray:
+    """phi = f(-L) rho for complex rho (..., n3, n2, n1) with the complex
+    eigenbases of a Bloch grid: coefficients V^H rho mode by mode, the Hadamard
+    product with f of the summed eigenvalues, then V back (Eqs. (17)-(21))."""
+    V1, V2, V3 = grid.V
+    F = kernel_values(grid.lam_sum(), kernel, omega)
+    T = _mode(np.asarray(rho, dtype=np.complex128), V1.conj(), -1)
+    T = _mode(T, V2.conj(), -2)
+    T = _mode(T, V3.conj(), -3)
+    T = F * T
+    T = _mode(T, V1.T, -1)
+    T = _mode(T, V2.T, -2)
+    T = _mode(T, V3.T, -3)
+    return T
+
+
+def bloch_phases(kq, bc):
+    """theta per axis for the reduced wavevector difference kq (3,): 2 pi kq_a on
+    periodic axes, 0 on Dirichlet axes (which must have kq_a = 0)."""
+    out = []
+    for a in range(3):
+        if bc[a] == "periodic":
+            out.append(2.0 * math.pi * float(kq[a]))
+        else:
+            if float(kq[a]) != 0.0:
+                raise ValueError("a Dirichlet axis carries no wavevector component")
+            out.append(0.0)
+    return tuple(out)
+
+
+def exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, kernel, omega=0.0):
+    """Exact exchange with Brillouin-zone sampling for one spin channel,
+    Sec. II, Eqs. (Vx:Poisson), (Ex:Poisson), (Poisson):
+      (Vx psi)_{nk} = - sum_{m q} w_q occ_{mq} psi_{mq} phi_{mq,nk},
+      -L phi_{mq,nk} = 4 pi conj(psi_{mq}) psi_{nk}  (Bloch at k - q),
+      E_x = -1/4 sum_{nk, mq} w_k w_q occ_{nk} occ_{mq} (rho_{mq,nk}, phi_{mq,nk})_h
+    with rho_{mq,nk} = conj(psi_{mq}) psi_{nk} and (u, v)_h = dV sum conj(u) v
+    (the spin-summed convention of `exchange`: occ = 2 g for a closed shell,
+    occ = g per spin channel, whose energy is then half the channel's E_X).
+    psi: (K, norb, n3, n2, n1) complex grid values; kpts (K, 3) reduced;
+    wk (K,) weights; occ (K, norb).  Every ordered pair is solved."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    K, norb = psi.shape[:2]
+    dV = h[0] * h[1] * h[2]
+    grids = {}
+    vx = np.zeros_like(psi)
+    ex = 0.0
+    for ki in range(K):
+        for qi in range(K):
+            th = bloch_phases(np.asarray(kpts[ki]) - np.asarray(kpts[qi]), bc)
+            if th not in grids:
+                grids[th] = make_grid_bloch(n, h, order, bc, th)
+            grid = grids[th]
+            for nb in range(norb):
+                for mb in range(norb):
+                    rho = np.conj(psi[qi, mb]) * psi[ki, nb]
+                    phi = apply_fL_bloch(rho, grid, kernel, omega)
+                    vx[ki, nb] -= wk[qi] * occ[qi][mb] * psi[qi, mb] * phi
+                    e = dV * complex(np.sum(np.conj(rho) * phi))
+                    ex -= 0.25 * wk[ki] * wk[qi] * occ[ki][nb] * occ[qi][mb] * e.real
+    return vx, ex

@@ -14,3 +14,4 @@ from .orbitals import (  # noqa: F401
     orthonormalise_cgs2,
     random_fields,
 )
+from .bloch import bloch_orbitals, orthonormalise_cgs2_complex  # noqa: F401
