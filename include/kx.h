@@ -196,6 +196,55 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
                                     const void* psi_dev, const double* occ_host,
                                     void* vxpsi_dev, int prec);
 
+/* ---- Brillouin-zone sampling (Sec. II: the pair (m q, n k) satisfies Bloch
+ * boundary conditions at the wavevector k - q on the periodic axes).
+ * A periodic axis of n nodes with the phase theta wraps its stencil as
+ * u(x + n h) = e^{i theta} u(x); -L(theta) is Hermitian and f(-L(theta)) is
+ * applied in the real eigenbasis of the theta = 0 grid, where it couples the
+ * even and odd mode of each frequency (2 x 2 blocks per axis).  Complex
+ * fields are interleaved (re, im) doubles, layout [field][n3][n2][n1].
+ * Only KX_PREC_FP64 is implemented (other precisions: KX_ERR_UNSUPPORTED).
+ * Node i of an axis sits at i h. */
+
+/* Reserve the buffers of the Bloch calls below: nk == 0 for
+ * kx_apply_fL_bloch alone, else for kx_apply_exchange_bloch on nk k-points of
+ * norb bands (and kx_apply_fL_bloch).  Builds, once per handle, the map of
+ * coupled modes from the eigenvectors (synchronises; KX_ERR_NUMERIC if the
+ * eigenbasis does not split into such pairs).  Grows buffers as kx_reserve
+ * does: a launch's fields and spectra (16 bytes per padded-grid value per
+ * item, 32 items), and for the exchange 32 bytes per grid point per state
+ * (ramp-free copies of psi and Vx psi) plus 8 per state pair.
+ *   nk  0 .. 64;  nk * norb <= 65535 */
+kx_status kx_reserve_bloch(kx_grid* g, int nk, int norb);
+
+/* phi = f(-L(theta)) rho for a batch of complex fields with the Bloch
+ * phases theta[3] (host, radians, one per axis; 0 on Dirichlet axes, else
+ * KX_ERR_INVALID_ARG).  rho_dev, phi_dev: batch interleaved complex fields
+ * (not aliasing).  KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is
+ * periodic with theta a multiple of 2 pi.  Enqueues kernels only
+ * (KX_ERR_STATE without kx_reserve_bloch). */
+kx_status kx_apply_fL_bloch(kx_grid* g, int kernel, double omega, int batch, const double theta[3],
+                            const void* rho_dev, void* phi_dev, int prec);
+
+/* Exact exchange with k-point sampling for one spin channel (Sec. II):
+ *   (Vx psi)_nk = - sum_{m q} w_q occ_mq psi_mq phi_{mq,nk},
+ *   -L(2 pi (k - q)) phi_{mq,nk} = 4 pi conj(psi_mq) psi_nk   (f for erfc),
+ *   E_x = -1/4 sum_{nk, mq} w_k w_q occ_nk occ_mq (rho_{mq,nk}, phi_{mq,nk})_h,
+ * solved once per unordered pair of states (phi_{nk,mq} = conj(phi_{mq,nk})).
+ *   nk               1 .. 64 k-points; kpts_host[nk][3] reduced coordinates
+ *                    (0 on Dirichlet axes); wk_host[nk] weights
+ *   norb             bands per k-point; occ_host[nk][norb] occupations
+ *   psi_dev          [nk][norb] interleaved complex fields psi_nk(x)
+ *   vxpsi_dev        the same layout, overwritten with (Vx psi)_nk
+ * Spin: one call per channel with that channel's occupations.  E_x is read
+ * with kx_exchange_energy (kx_pair_energies then holds no pairs).  Results
+ * do not depend on the handle's batch size.  Enqueues kernels only
+ * (KX_ERR_STATE without kx_reserve_bloch for at least nk * norb states). */
+kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, int norb,
+                                  const double* kpts_host, const double* wk_host,
+                                  const double* occ_host, const void* psi_dev, void* vxpsi_dev,
+                                  int prec);
+
 /* Ragged batch: the exact-exchange application of nsys independent systems
  * (each its own handle, grid, boundary conditions, kernel, omega, orbital
  * count), recorded once into one HIP graph with one branch per system and

@@ -164,6 +164,30 @@ struct kx_grid {
   double* dF = nullptr;
   // workspace (grown by kx_reserve) and results
   Work ws;
+  // Brillouin-zone sampling: the coupled mode of every folded eigenvector
+  // (built once) and the buffers of the Bloch entry points (grown by
+  // kx_reserve_bloch); capacities in elements
+  struct Bloch {
+    int* part = nullptr;  // 3 * pmax
+    int pmax = 0;
+    bool mapped = false;
+    double* Z = nullptr;  // fields / spectra of a launch
+    long long z_cap = 0;
+    double* epart = nullptr;  // coupling-kernel energy partials
+    long long epart_cap = 0;
+    double* tab = nullptr;  // coupling tables per class
+    long long tab_cap = 0;
+    double* kq = nullptr;  // reduced k-points (or phases / 2 pi)
+    long long kq_cap = 0;
+    double* occw = nullptr;  // w_k occ_nk per state
+    long long occw_cap = 0;
+    double* U = nullptr;  // ramp-free orbitals, planar
+    long long u_cap = 0;
+    double* W = nullptr;  // ramp-free Vx psi accumulators, planar
+    long long w_cap = 0;
+    double* pairE = nullptr;
+    long long pairE_cap = 0;
+  } bl;
   int max_slots = 64;   // largest batch of pairs / fields per launch
   int batch_cap = 64;   // pairs per launch of the exchange schedule (<= max_slots)
   double* dEx = nullptr;
@@ -847,6 +871,190 @@ void release_batch_graph(kx_grid* g, bool all) {
   b.origin = nullptr;
 }
 
+// ---- Brillouin-zone sampling (Sec. II)
+
+// The coupled mode of every folded eigenvector under a Bloch phase, per
+// periodic axis: the real part of V^T M(theta0) V must be diagonal and its
+// imaginary part must couple each mode to at most one mode of the other
+// parity (theta0 = 0.9, a generic phase).  Built once per handle from the
+// device blocks; synchronises.  KX_ERR_NUMERIC if the structure is not found.
+kx_status bloch_map(kx_grid* g) {
+  auto& B = g->bl;
+  if (B.mapped) return KX_OK;
+  const Geom& G = g->geom;
+  const int ns[3] = {G.n1, G.n2, G.n3}, mes[3] = {G.me1, G.me2, G.me3},
+            mos[3] = {G.mo1, G.mo2, G.mo3}, pes[3] = {G.pe1, G.pe2, G.pe3},
+            pos[3] = {G.po1, G.po2, G.po3};
+  const int pmax = std::max(G.p1, std::max(G.p2, G.p3));
+  std::vector<int> part((size_t)3 * pmax, -1);
+  double w[kMaxStencil + 1];
+  fd_weights_closed_form(g->order, w);
+  const int m = g->order / 2;
+  for (int a = 0; a < 3; ++a) {
+    if (g->bc[a] != KX_BC_PERIODIC) continue;
+    const int n = ns[a], me = mes[a], mo = mos[a], pe = pes[a], po = pos[a];
+    std::vector<double> VE((size_t)pe * pe), VO((size_t)po * po);
+    KX_HIP(hipStreamSynchronize(g->stream));
+    KX_HIP(hipMemcpy(VE.data(), g->dVE[a], sizeof(double) * VE.size(), hipMemcpyDeviceToHost));
+    if (po > 0)
+      KX_HIP(hipMemcpy(VO.data(), g->dVO[a], sizeof(double) * VO.size(), hipMemcpyDeviceToHost));
+    // full vectors of the valid blocked indices
+    std::vector<int> ids;
+    std::vector<std::vector<double>> v;
+    for (int idx = 0; idx < pe + po; ++idx) {
+      const bool even = idx < pe;
+      if (even ? idx >= me : idx - pe >= mo) continue;
+      std::vector<double> x(n, 0.0);
+      for (int i = 0; i < n; ++i) {
+        if (even) {
+          const int j = i < me ? i : n - 1 - i;
+          x[i] = VE[(size_t)j * pe + idx];
+        } else if (i < mo) {
+          x[i] = VO[(size_t)i * po + (idx - pe)];
+        } else if (i >= n - mo) {
+          x[i] = -VO[(size_t)(n - 1 - i) * po + (idx - pe)];
+        }
+      }
+      ids.push_back(idx);
+      v.push_back(std::move(x));
+    }
+    const double th = 0.9, h2 = g->h[a] * g->h[a];
+    double scale = 0.0;
+    std::vector<double> cr(2 * m + 1), ci(2 * m + 1);
+    for (int p = -m; p <= m; ++p) {
+      const double wp = w[std::abs(p)] / h2;
+      cr[p + m] = -wp * std::cos(th * p / n);
+      ci[p + m] = -wp * std::sin(th * p / n);
+      scale += std::fabs(wp);
+    }
+    const double tol = 1e-10 * scale;
+    const int nv = (int)ids.size();
+    std::vector<double> R((size_t)nv * nv), I((size_t)nv * nv);
+    std::vector<double> yr(n), yi(n);
+    for (int c = 0; c < nv; ++c) {
+      for (int i = 0; i < n; ++i) {
+        double sr = 0.0, si = 0.0;
+        for (int p = -m; p <= m; ++p) {
+          const int j = ((i + p) % n + n) % n;
+          sr += cr[p + m] * v[c][j];
+          si += ci[p + m] * v[c][j];
+        }
+        yr[i] = sr;
+        yi[i] = si;
+      }
+      for (int r = 0; r < nv; ++r) {
+        double dr = 0.0, di = 0.0;
+        for (int i = 0; i < n; ++i) {
+          dr += v[r][i] * yr[i];
+          di += v[r][i] * yi[i];
+        }
+        R[(size_t)r * nv + c] = dr;
+        I[(size_t)r * nv + c] = di;
+      }
+    }
+    std::vector<int> pr(nv, -1);
+    for (int r = 0; r < nv; ++r) {
+      int best = -1;
+      for (int c = 0; c < nv; ++c) {
+        if (c != r && std::fabs(R[(size_t)r * nv + c]) > tol) return KX_ERR_NUMERIC;
+        if (std::fabs(I[(size_t)r * nv + c]) > tol) {
+          if (best >= 0) return KX_ERR_NUMERIC;  // coupled to two modes
+          best = c;
+        }
+      }
+      pr[r] = best;
+    }
+    for (int r = 0; r < nv; ++r) {
+      const int c = pr[r];
+      if (c < 0) continue;
+      if (pr[c] != r || (ids[r] < pe) == (ids[c] < pe)) return KX_ERR_NUMERIC;
+      part[(size_t)a * pmax + ids[r]] = ids[c];
+    }
+  }
+  kx_status st = dev_alloc((void**)&B.part, sizeof(int) * part.size());
+  if (st != KX_OK) return st;
+  KX_HIP(hipMemcpy(B.part, part.data(), sizeof(int) * part.size(), hipMemcpyHostToDevice));
+  B.pmax = pmax;
+  B.mapped = true;
+  return KX_OK;
+}
+
+BlochAxes bloch_axes(const kx_grid* g) {
+  const Geom& G = g->geom;
+  BlochAxes B;
+  const int ns[3] = {G.n1, G.n2, G.n3}, mes[3] = {G.me1, G.me2, G.me3},
+            mos[3] = {G.mo1, G.mo2, G.mo3}, pes[3] = {G.pe1, G.pe2, G.pe3},
+            pos[3] = {G.po1, G.po2, G.po3};
+  for (int a = 0; a < 3; ++a) {
+    BlochAxis& A = B.ax[a];
+    A.n = ns[a];
+    A.me = mes[a];
+    A.mo = mos[a];
+    A.pe = pes[a];
+    A.po = pos[a];
+    A.periodic = g->bc[a] == KX_BC_PERIODIC ? 1 : 0;
+    A.h = g->h[a];
+    A.VE = g->dVE[a];
+    A.VO = g->dVO[a];
+    A.lamE = g->dLamE[a];
+    A.lamO = g->dLamO[a];
+    A.part = g->bl.part + (size_t)a * g->bl.pmax;
+  }
+  for (int p = 0; p <= kMaxStencil; ++p) B.w[p] = 0.0;
+  fd_weights_closed_form(g->order, B.w);
+  B.m = g->order / 2;
+  return B;
+}
+
+// complex items (pairs, or fields) per launch of the Bloch path
+int bloch_batch(const kx_grid* g) { return g->ws.slots / 2; }
+long long bloch_field_stride(const Geom& G) { return std::max(G.N, G.fsize); }
+
+// One launch of nb complex items whose ramp-free real / imaginary parts are
+// in Z (fields 2 t, 2 t + 1, stride N): forward modes 1, 2 and the forward
+// mode-3 product into spectra (Z, stride fsize), the coupling (energy
+// partials into epart), the inverse mode-3 product and the inverse modes 2, 1
+// back into Z (stride N).
+hipError_t bloch_solve(kx_grid* g, int kernel, double omega, const PairMap& pm, int nb,
+                       hipStream_t s) {
+  const Geom& G = g->geom;
+  const EigR<double> E = eig_of(g);
+  double* T = (double*)g->ws.T;
+  double* Z = g->bl.Z;
+  hipError_t e = timed(g, s, KX_PHASE_FORWARD, [&] {
+    return launch_forward_d(KX_F64, 0, G, g->plan_d.fwd, E, Z, g->ws.fitems, 2 * nb, T, s);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(g, s, KX_PHASE_PENCIL, [&] {
+    hipError_t r = launch_pencil_half(0, G, E, 2 * nb, T, Z, s);
+    if (r == hipSuccess)
+      r = launch_bloch_couple(bloch_axes(g), G, g->bl.tab, g->bl.pmax, kernel, omega, pm, nb, Z,
+                              g->bl.epart, s);
+    if (r == hipSuccess) r = launch_pencil_half(1, G, E, 2 * nb, T, Z, s);
+    return r;
+  });
+  if (e != hipSuccess) return e;
+  return timed(g, s, KX_PHASE_INVERSE, [&] {
+    return launch_inverse_d(KX_F64, 0, G, g->plan_d.inv, E, T, g->ws.fitems, 2 * nb, nullptr,
+                            nullptr, Z, s);
+  });
+}
+
+// the reserved Bloch buffers hold nk k-points of norb bands (nk == 0: fields)
+bool bloch_reserved(const kx_grid* g, int nk, int norb) {
+  const auto& B = g->bl;
+  const Geom& G = g->geom;
+  const int nb = bloch_batch(g);
+  if (!B.mapped || nb < 1) return false;
+  const int K = std::max(nk, 2);
+  const long long M = (long long)nk * norb;
+  return B.z_cap >= 2LL * nb * bloch_field_stride(G) &&
+         B.epart_cap >= (long long)nb * bloch_couple_blocks(G) &&
+         B.tab_cap >= (long long)K * K * 3 * 2 * B.pmax && B.kq_cap >= 3LL * K &&
+         B.occw_cap >= M && B.u_cap >= 2 * M * G.N && B.w_cap >= 2 * M * G.N &&
+         B.pairE_cap >= M * (M + 1) / 2;
+}
+
 }  // namespace
 
 // ============================================================ C ABI
@@ -1201,6 +1409,15 @@ kx_status kx_destroy(kx_grid* g) {
     dev_free(g->hVOT[k]);
   }
   free_work(g->ws);
+  dev_free(g->bl.part);
+  dev_free(g->bl.Z);
+  dev_free(g->bl.epart);
+  dev_free(g->bl.tab);
+  dev_free(g->bl.kq);
+  dev_free(g->bl.occw);
+  dev_free(g->bl.U);
+  dev_free(g->bl.W);
+  dev_free(g->bl.pairE);
   dev_free(g->dF);
   dev_free(g->dEx);
   dev_free(g->dAcePart);
@@ -1346,6 +1563,150 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
   KX_HIP(e);
   g->last_norb = norb;
   g->last_pairE = w.pairE;
+  return KX_OK;
+}
+
+kx_status kx_reserve_bloch(kx_grid* g, int nk, int norb) {
+  if (!g || nk < 0 || nk > kMaxKpoints || norb < 0 || (nk == 0 && norb != 0))
+    return KX_ERR_INVALID_ARG;
+  const long long M = (long long)nk * norb;
+  if (M > 65535 || (double)M * (double)g->geom.N > 1.0e18) return KX_ERR_INVALID_ARG;
+  kx_status st = bloch_map(g);
+  if (st != KX_OK) return st;
+  st = reserve_slots(g, g->max_slots, false, false);
+  if (st != KX_OK) return st;
+  auto& B = g->bl;
+  const Geom& G = g->geom;
+  const int nb = bloch_batch(g);
+  if (nb < 1) return KX_ERR_STATE;
+  const int K = std::max(nk, 2);
+  st = grow(g, &B.Z, &B.z_cap, 2LL * nb * bloch_field_stride(G));
+  if (st == KX_OK) st = grow(g, &B.epart, &B.epart_cap, (long long)nb * bloch_couple_blocks(G));
+  if (st == KX_OK) st = grow(g, &B.tab, &B.tab_cap, (long long)K * K * 3 * 2 * B.pmax);
+  if (st == KX_OK) st = grow(g, &B.kq, &B.kq_cap, 3LL * K);
+  if (st == KX_OK && M > 0) st = grow(g, &B.occw, &B.occw_cap, M);
+  if (st == KX_OK && M > 0) st = grow(g, &B.U, &B.u_cap, 2 * M * G.N);
+  if (st == KX_OK && M > 0) st = grow(g, &B.W, &B.w_cap, 2 * M * G.N);
+  if (st == KX_OK && M > 0) st = grow(g, &B.pairE, &B.pairE_cap, M * (M + 1) / 2);
+  return st;
+}
+
+kx_status kx_apply_fL_bloch(kx_grid* g, int kernel, double omega, int batch, const double theta[3],
+                            const void* rho_dev, void* phi_dev, int prec) {
+  if (!g || batch < 0 || !theta) return KX_ERR_INVALID_ARG;
+  if (kernel != KX_KERNEL_COULOMB && kernel != KX_KERNEL_ERFC) return KX_ERR_INVALID_ARG;
+  if (kernel == KX_KERNEL_ERFC && !(std::isfinite(omega) && omega > 0.0)) return KX_ERR_INVALID_ARG;
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED) return KX_ERR_INVALID_ARG;
+  BlochT th;
+  bool zero_mode = true;  // the spectrum of -L(theta) contains 0
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(theta[a])) return KX_ERR_INVALID_ARG;
+    th.t[a] = theta[a] / (2.0 * M_PI);
+    if (g->bc[a] != KX_BC_PERIODIC) {
+      if (theta[a] != 0.0) return KX_ERR_INVALID_ARG;
+      zero_mode = false;
+    } else if (th.t[a] != std::rint(th.t[a])) {
+      zero_mode = false;
+    }
+  }
+  if (kernel == KX_KERNEL_COULOMB && zero_mode) return KX_ERR_SINGULAR;
+  if (prec != KX_PREC_FP64) return KX_ERR_UNSUPPORTED;
+  if (batch == 0) return KX_OK;
+  if (!rho_dev || !phi_dev || rho_dev == phi_dev) return KX_ERR_INVALID_ARG;
+  if ((double)batch * (double)g->geom.N > 1.0e18) return KX_ERR_INVALID_ARG;
+  if (!bloch_reserved(g, 0, 0)) return KX_ERR_STATE;
+
+  const Geom& G = g->geom;
+  hipStream_t s = g->stream;
+  g->recording = stream_capturing(s);
+  // class 1 of a two-point table: theta = 2 pi (kq[0] - kq[1]) with kq[1] = 0
+  const double kq[6] = {th.t[0], th.t[1], th.t[2], 0.0, 0.0, 0.0};
+  hipError_t e = launch_put_doubles(kq, 6, g->bl.kq, s);
+  if (e == hipSuccess)
+    e = launch_bloch_table(bloch_axes(g), g->bl.kq, 2, g->bl.pmax, g->bl.tab, s);
+  const int chunk = bloch_batch(g);
+  const size_t fb = 2 * sizeof(double) * (size_t)G.N;
+  const PairMap pm{0, 0, 1, 2, 1};
+  for (int b0 = 0; b0 < batch && e == hipSuccess; b0 += chunk) {
+    const int nb = std::min(chunk, batch - b0);
+    const double* src = (const double*)((const char*)rho_dev + fb * b0);
+    double* dst = (double*)((char*)phi_dev + fb * b0);
+    e = launch_bloch_fields(0, G, th, nb, src, g->bl.Z, s);
+    if (e == hipSuccess) e = bloch_solve(g, kernel, omega, pm, nb, s);
+    if (e == hipSuccess) e = launch_bloch_fields(1, G, th, nb, g->bl.Z, dst, s);
+  }
+  g->recording = false;
+  KX_HIP(e);
+  return KX_OK;
+}
+
+kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, int norb,
+                                  const double* kpts_host, const double* wk_host,
+                                  const double* occ_host, const void* psi_dev, void* vxpsi_dev,
+                                  int prec) {
+  if (!g || nk < 1 || nk > kMaxKpoints || norb < 0) return KX_ERR_INVALID_ARG;
+  kx_status st = check_kernel_args(g, kernel, omega);
+  if (st != KX_OK) return st;
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_MIXED) return KX_ERR_INVALID_ARG;
+  if (!kpts_host || !wk_host || (norb > 0 && !occ_host)) return KX_ERR_INVALID_ARG;
+  const long long M = (long long)nk * norb;
+  if (M > 65535) return KX_ERR_INVALID_ARG;
+  std::vector<double> kq(3 * (size_t)std::max(nk, 2), 0.0), occw((size_t)M);
+  for (int k = 0; k < nk; ++k) {
+    if (!std::isfinite(wk_host[k])) return KX_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a) {
+      const double v = kpts_host[3 * k + a];
+      if (!std::isfinite(v)) return KX_ERR_INVALID_ARG;
+      if (g->bc[a] != KX_BC_PERIODIC && v != 0.0) return KX_ERR_INVALID_ARG;
+      kq[3 * (size_t)k + a] = v;
+    }
+    for (int n = 0; n < norb; ++n) {
+      const double o = occ_host[(size_t)k * norb + n];
+      if (!std::isfinite(o)) return KX_ERR_INVALID_ARG;
+      occw[(size_t)k * norb + n] = wk_host[k] * o;
+    }
+  }
+  if (prec != KX_PREC_FP64) return KX_ERR_UNSUPPORTED;
+  hipStream_t s = g->stream;
+  if (M == 0) {
+    KX_HIP(launch_zero(g->dEx, sizeof(double), s));
+    g->last_norb = 0;
+    g->last_pairE = nullptr;
+    return KX_OK;
+  }
+  if (!psi_dev || !vxpsi_dev || psi_dev == vxpsi_dev) return KX_ERR_INVALID_ARG;
+  if (!bloch_reserved(g, nk, norb)) return KX_ERR_STATE;
+
+  const Geom& G = g->geom;
+  auto& B = g->bl;
+  g->recording = stream_capturing(s);
+  hipError_t e = launch_put_doubles(kq.data(), 3 * nk, B.kq, s);
+  if (e == hipSuccess) e = launch_put_doubles(occw.data(), (int)M, B.occw, s);
+  if (e == hipSuccess) e = launch_bloch_table(bloch_axes(g), B.kq, nk, B.pmax, B.tab, s);
+  if (e == hipSuccess)
+    e = launch_bloch_orbitals(0, G, (int)M, norb, B.kq, (const double*)psi_dev, B.U, B.W, s);
+  const long long np = M * (M + 1) / 2;
+  const int chunk = bloch_batch(g);
+  const int nblk = bloch_couple_blocks(G);
+  const double dV = g->h[0] * g->h[1] * g->h[2];
+  for (long long t0 = 0; t0 < np && e == hipSuccess; t0 += chunk) {
+    const int nb = (int)std::min<long long>(chunk, np - t0);
+    const PairMap pm{t0, (int)M, norb, nk, 0};
+    e = launch_bloch_products(G, B.U, pm, nb, B.Z, s);
+    if (e == hipSuccess) e = bloch_solve(g, kernel, omega, pm, nb, s);
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_ENERGY, [&] {
+        return launch_bloch_pair_sums(B.epart, nblk, nb, t0, dV, B.pairE, s);
+      });
+    if (e == hipSuccess) e = launch_bloch_update(G, B.U, B.Z, pm, nb, B.occw, B.W, s);
+  }
+  if (e == hipSuccess)
+    e = launch_bloch_orbitals(1, G, (int)M, norb, B.kq, nullptr, (double*)vxpsi_dev, B.W, s);
+  if (e == hipSuccess) e = launch_bloch_energy(B.pairE, (int)M, B.occw, g->dEx, s);
+  g->recording = false;
+  KX_HIP(e);
+  g->last_norb = 0;  // kx_pair_energies covers real orbitals only
+  g->last_pairE = nullptr;
   return KX_OK;
 }
 

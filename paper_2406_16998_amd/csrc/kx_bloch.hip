@@ -1,0 +1,484 @@
+// Brillouin-zone sampling (Sec. II): the pair problem of (m q, n k) carries
+// Bloch boundary conditions at the wavevector k - q along the periodic axes.
+//
+// On a periodic axis of n nodes with the Bloch phase theta, the stencil
+// operator factors as L(theta) = D M(theta) D^H, D = diag(e^{i theta x / n})
+// (x the node index) and M(theta) the circulant whose entry p off the
+// diagonal is w_p e^{i theta p / n} / h^2.  M(theta) commutes with the
+// periodic Laplacian, so in its real eigenbasis (the folded even/odd blocks
+// of the theta = 0 problem) -M(theta) is block diagonal: the even and the odd
+// mode of one frequency couple through a 2 x 2 Hermitian block
+//   [ A    i b ]
+//   [ -i b  A  ]  = A I + b s,   s = [[0, i], [-i, 0]],
+// and every other mode is a 1 x 1 block.  In three dimensions f(-L) then acts
+// on groups of at most 2 x 2 x 2 spectral coefficients; with P(+-) = (I +- s)/2
+// the projectors of s,
+//   f = sum_{signs} f(sum_a A_a +- b_a) prod_a P_a(+-)
+//     = sum_{S subset of the paired axes} c_S prod_{a in S} s_a,
+//   c_S = 2^-d sum_{signs} f(...) prod_{a in S} sign_a,
+// which the coupling kernel applies to the FP64 spectra of the real and the
+// imaginary part of D^H rho.  The orbitals enter in the ramp-free form
+// u_nk = e^{-2 pi i k.x / n} psi_nk, for which conj(u_mq) u_nk is exactly
+// D^H conj(psi_mq) psi_nk at theta = 2 pi (k - q), and the update of Vx psi
+// is accumulated in the same form.
+#include <cmath>
+
+#include "kx_internal.h"
+
+namespace kx {
+namespace {
+
+__device__ __forceinline__ double f_of(int kernel, double omega, double lam) {
+  if (kernel == KX_KERNEL_COULOMB) return 4.0 * M_PI / lam;
+  const double x = lam / (4.0 * omega * omega);
+  const double gx = (x == 0.0) ? 1.0 : -expm1(-x) / x;
+  return (M_PI / (omega * omega)) * gx;
+}
+
+// full eigenvector `idx` (blocked index) of an axis at node i, from its upper half
+__device__ __forceinline__ double vget(const BlochAxis& A, int idx, int i) {
+  if (idx < A.pe) {
+    const int j = i < A.me ? i : A.n - 1 - i;
+    return A.VE[(size_t)j * A.pe + idx];
+  }
+  const int b = idx - A.pe;
+  if (i < A.mo) return A.VO[(size_t)i * A.po + b];
+  if (i >= A.n - A.mo) return -A.VO[(size_t)(A.n - 1 - i) * A.po + b];
+  return 0.0;  // the middle node of odd n
+}
+
+__device__ __forceinline__ bool valid_idx(const BlochAxis& A, int idx) {
+  return idx < A.pe ? idx < A.me : (idx - A.pe < A.mo && idx < A.pe + A.po);
+}
+
+// v1^T C v2 for the circulant C with C[i, (i + p) mod n] += c[p + m]
+__device__ double circ_form(const BlochAxis& A, int i1, int i2, const double* c, int m) {
+  double acc = 0.0;
+  for (int i = 0; i < A.n; ++i) {
+    const double a = vget(A, i1, i);
+    if (a == 0.0) continue;
+    double s = 0.0;
+    for (int p = -m; p <= m; ++p) {
+      int j = (i + p) % A.n;
+      if (j < 0) j += A.n;
+      s += c[p + m] * vget(A, i2, j);
+    }
+    acc += a * s;
+  }
+  return acc;
+}
+
+// Per class (theta = 2 pi (kq[ki] - kq[qi]), class = ki * K + qi) and axis:
+// A[idx] (the diagonal of -M in the folded basis) and b[idx] at the even
+// member of each coupled pair.
+__global__ void bloch_table_kernel(BlochAxes B, const double* __restrict__ kq, int K, int pmax,
+                                   double* __restrict__ tab) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y, cls = blockIdx.z;
+  if (idx >= pmax) return;
+  const BlochAxis& A = B.ax[a];
+  double* tA = tab + ((size_t)cls * 3 + a) * 2 * pmax;
+  double* tB = tA + pmax;
+  double av = 0.0, bv = 0.0;
+  if (valid_idx(A, idx)) {
+    if (!A.periodic) {
+      av = idx < A.pe ? A.lamE[idx] : A.lamO[idx - A.pe];
+    } else {
+      const int ki = cls / K, qi = cls - ki * K;
+      const double d = kq[ki * 3 + a] - kq[qi * 3 + a];  // theta / (2 pi)
+      double cr[2 * kMaxStencil + 1], ci[2 * kMaxStencil + 1];
+      const double ih2 = 1.0 / (A.h * A.h);
+      for (int p = -B.m; p <= B.m; ++p) {
+        double sn, cs;
+        sincospi(2.0 * d * p / A.n, &sn, &cs);
+        const double w = B.w[p < 0 ? -p : p];
+        cr[p + B.m] = -w * cs * ih2;
+        ci[p + B.m] = -w * sn * ih2;
+      }
+      av = circ_form(A, idx, idx, cr, B.m);
+      const int o = A.part[idx];
+      if (o >= 0 && idx < A.pe) bv = circ_form(A, idx, o, ci, B.m);
+    }
+  }
+  tA[idx] = av;
+  tB[idx] = bv;
+}
+
+// (P1, P2), P1 <= P2, of pair t in the row-major upper triangle of M states
+__device__ __forceinline__ void pair_of(long long t, int M, int& P1, int& P2) {
+  const double b = 2.0 * M + 1.0;
+  long long r = (long long)((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > M - 1) r = M - 1;
+  auto start = [&](long long q) { return q * M - q * (q - 1) / 2; };
+  while (r + 1 <= M - 1 && start(r + 1) <= t) ++r;
+  while (r > 0 && start(r) > t) --r;
+  P1 = (int)r;
+  P2 = (int)(r + (t - start(r)));
+}
+
+__device__ __forceinline__ int class_of(const PairMap& pm, int item) {
+  if (pm.M == 0) return pm.cls0;
+  int P1, P2;
+  pair_of(pm.t0 + item, pm.M, P1, P2);
+  return (P2 / pm.norb) * pm.K + (P1 / pm.norb);  // k of the second state, q of the first
+}
+
+constexpr int kCoupleThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+  return s;
+}
+
+// Y = f(-M) X on every coupled group of the spectra of item `blockIdx.y`
+// (real part in S[2 item], imaginary part in S[2 item + 1], fsize values
+// each), in place, with Re sum conj(X) Y per workgroup into part.
+__global__ void __launch_bounds__(kCoupleThreads)
+bloch_couple_kernel(BlochAxes B, Geom g, const double* __restrict__ tab, int pmax, int kernel,
+                    double omega, PairMap pm, double* __restrict__ S, double* __restrict__ part) {
+  __shared__ double red[kCoupleThreads / 64];
+  const int item = blockIdx.y;
+  const long long pos = (long long)blockIdx.x * kCoupleThreads + threadIdx.x;
+  double e = 0.0;
+  if (pos < g.fsize) {
+    const int ib = (int)(pos % g.p2);
+    const int ia = (int)((pos / g.p2) % g.p1);
+    const int ic = (int)(pos / g.slab);
+    const int idx[3] = {ia, ib, ic};
+    int prt[3];
+    bool rep = true;
+    int pmask = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const BlochAxis& A = B.ax[a];
+      if (!valid_idx(A, idx[a])) rep = false;
+      prt[a] = rep ? A.part[idx[a]] : -1;
+      if (prt[a] >= 0) {
+        if (idx[a] >= A.pe) rep = false;  // the odd member: handled by its even partner
+        pmask |= 1 << a;
+      }
+    }
+    if (rep) {
+      const double* tb = tab + (size_t)class_of(pm, item) * 3 * 2 * pmax;
+      double Aa[3], Ba[3];
+      double asum = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double* tA = tb + (size_t)a * 2 * pmax;
+        if (prt[a] >= 0) {
+          Aa[a] = 0.5 * (tA[idx[a]] + tA[prt[a]]);
+          Ba[a] = tA[pmax + idx[a]];
+        } else {
+          Aa[a] = tA[idx[a]];
+          Ba[a] = 0.0;
+        }
+        asum += Aa[a];
+      }
+      double* Sr = S + (size_t)(2 * item) * g.fsize;
+      double* Si = Sr + g.fsize;
+      long long off[8];
+      double xr[8], xi[8], f[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t & ~pmask) continue;
+        const int ja = (t & 1) ? prt[0] : ia, jb = (t & 2) ? prt[1] : ib, jc = (t & 4) ? prt[2] : ic;
+        off[t] = (long long)jc * g.slab + (long long)ja * g.p2 + jb;
+        xr[t] = Sr[off[t]];
+        xi[t] = Si[off[t]];
+        // sign vector t: bit set = the A - b eigenvalue on that axis
+        double lam = asum;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          if ((pmask >> a) & 1) lam += ((t >> a) & 1) ? -Ba[a] : Ba[a];
+        f[t] = f_of(kernel, omega, lam);
+      }
+      const int d = __builtin_popcount(pmask);
+      const double scale = 1.0 / (double)(1 << d);
+      double c[8];
+#pragma unroll
+      for (int Sm = 0; Sm < 8; ++Sm) {
+        if (Sm & ~pmask) continue;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (t & ~pmask) continue;
+          acc += (__builtin_popcount(t & Sm) & 1) ? -f[t] : f[t];
+        }
+        c[Sm] = acc * scale;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t & ~pmask) continue;
+        double yr = 0.0, yi = 0.0;
+#pragma unroll
+        for (int Sm = 0; Sm < 8; ++Sm) {
+          if (Sm & ~pmask) continue;
+          // prod over a in Sm of (i if t_a = 0 else -i) = i^|Sm| (-1)^|t & Sm|
+          double cr = c[Sm], ci = 0.0;
+          const int q = __builtin_popcount(Sm) & 3;
+          if (q == 1) { ci = cr; cr = 0.0; }
+          else if (q == 2) { cr = -cr; }
+          else if (q == 3) { ci = -cr; cr = 0.0; }
+          if (__builtin_popcount(t & Sm) & 1) { cr = -cr; ci = -ci; }
+          const int src = t ^ Sm;
+          yr += cr * xr[src] - ci * xi[src];
+          yi += cr * xi[src] + ci * xr[src];
+        }
+        e += xr[t] * yr + xi[t] * yi;
+        Sr[off[t]] = yr;
+        Si[off[t]] = yi;
+      }
+    }
+  }
+  const double s = block_sum(e, red);
+  if (threadIdx.x == 0) part[(size_t)item * gridDim.x + blockIdx.x] = s;
+}
+
+// e^{-2 pi i s} for s = sum_a t_a x_a / n_a, reduced to [-1/2, 1/2] first
+__device__ __forceinline__ void ramp(const double* t, const Geom& g, long long x, double& c,
+                                     double& sn) {
+  const long long i1 = x % g.n1, i2 = (x / g.n1) % g.n2, i3 = x / ((long long)g.n1 * g.n2);
+  double s = t[0] * (double)i1 / g.n1 + t[1] * (double)i2 / g.n2 + t[2] * (double)i3 / g.n3;
+  s -= rint(s);
+  double ss, cc;
+  sincospi(2.0 * s, &ss, &cc);
+  c = cc;
+  sn = -ss;
+}
+
+// Z[2 b] + i Z[2 b + 1] = e^{-i theta.x / n} rho_b (rho interleaved complex)
+__global__ void field_in_kernel(const double* __restrict__ rho, int nb, Geom g, BlochT th,
+                                double* __restrict__ Z) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.N) return;
+  double c, s;
+  ramp(th.t, g, x, c, s);
+  for (int b = 0; b < nb; ++b) {
+    const double r = rho[2 * ((size_t)b * g.N + x)], i = rho[2 * ((size_t)b * g.N + x) + 1];
+    Z[(size_t)(2 * b) * g.N + x] = c * r - s * i;
+    Z[(size_t)(2 * b + 1) * g.N + x] = c * i + s * r;
+  }
+}
+
+// phi_b = e^{+i theta.x / n} (Z[2 b] + i Z[2 b + 1]), interleaved complex
+__global__ void field_out_kernel(const double* __restrict__ Z, int nb, Geom g, BlochT th,
+                                 double* __restrict__ phi) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.N) return;
+  double c, s;
+  ramp(th.t, g, x, c, s);
+  s = -s;
+  for (int b = 0; b < nb; ++b) {
+    const double r = Z[(size_t)(2 * b) * g.N + x], i = Z[(size_t)(2 * b + 1) * g.N + x];
+    phi[2 * ((size_t)b * g.N + x)] = c * r - s * i;
+    phi[2 * ((size_t)b * g.N + x) + 1] = c * i + s * r;
+  }
+}
+
+// u_P = e^{-2 pi i k(P).x / n} psi_P into planar U (re, im fields per state);
+// W = 0.  State P = k-point P / norb, band P % norb.
+__global__ void orbitals_in_kernel(const double* __restrict__ psi, int M, int norb, Geom g,
+                                   const double* __restrict__ kq, double* __restrict__ U,
+                                   double* __restrict__ W) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.N) return;
+  for (int P = 0; P < M; ++P) {
+    double c, s;
+    ramp(kq + 3 * (P / norb), g, x, c, s);
+    const double r = psi[2 * ((size_t)P * g.N + x)], i = psi[2 * ((size_t)P * g.N + x) + 1];
+    U[(size_t)(2 * P) * g.N + x] = c * r - s * i;
+    U[(size_t)(2 * P + 1) * g.N + x] = c * i + s * r;
+    W[(size_t)(2 * P) * g.N + x] = 0.0;
+    W[(size_t)(2 * P + 1) * g.N + x] = 0.0;
+  }
+}
+
+// (Vx psi)_P = e^{+2 pi i k(P).x / n} W_P, interleaved complex
+__global__ void vx_out_kernel(const double* __restrict__ W, int M, int norb, Geom g,
+                              const double* __restrict__ kq, double* __restrict__ vx) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.N) return;
+  for (int P = 0; P < M; ++P) {
+    double c, s;
+    ramp(kq + 3 * (P / norb), g, x, c, s);
+    s = -s;
+    const double r = W[(size_t)(2 * P) * g.N + x], i = W[(size_t)(2 * P + 1) * g.N + x];
+    vx[2 * ((size_t)P * g.N + x)] = c * r - s * i;
+    vx[2 * ((size_t)P * g.N + x) + 1] = c * i + s * r;
+  }
+}
+
+// Z[2 t] + i Z[2 t + 1] = conj(u_P1) u_P2 for the pairs t0 + t, t < nb
+__global__ void products_kernel(const double* __restrict__ U, PairMap pm, int nb, Geom g,
+                                double* __restrict__ Z) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.N) return;
+  for (int t = 0; t < nb; ++t) {
+    int P1, P2;
+    pair_of(pm.t0 + t, pm.M, P1, P2);
+    const double ar = U[(size_t)(2 * P1) * g.N + x], ai = U[(size_t)(2 * P1 + 1) * g.N + x];
+    const double br = U[(size_t)(2 * P2) * g.N + x], bi = U[(size_t)(2 * P2 + 1) * g.N + x];
+    Z[(size_t)(2 * t) * g.N + x] = ar * br + ai * bi;
+    Z[(size_t)(2 * t + 1) * g.N + x] = ar * bi - ai * br;
+  }
+}
+
+// For the pairs t0 + t in order, with phi' = Z[2 t] + i Z[2 t + 1]:
+//   W_P2 -= occw_P1 u_P1 phi',  and for P1 != P2  W_P1 -= occw_P2 u_P2 conj(phi').
+// Each thread owns one grid point of every state, so the updates of a state
+// arrive in the global pair order whatever the batches; the first state of a
+// row is held in registers while its row lasts (the same sequence of
+// operations as through memory).
+__global__ void update_kernel(const double* __restrict__ U, const double* __restrict__ Z,
+                              PairMap pm, int nb, Geom g, const double* __restrict__ occw,
+                              double* __restrict__ W) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.N) return;
+  const size_t N = (size_t)g.N;
+  int cur = -1;
+  double wr = 0.0, wi = 0.0, ur = 0.0, ui = 0.0, oc = 0.0;
+  for (int t = 0; t < nb; ++t) {
+    int P1, P2;
+    pair_of(pm.t0 + t, pm.M, P1, P2);
+    if (P1 != cur) {
+      if (cur >= 0) {
+        W[2 * cur * N + x] = wr;
+        W[(2 * cur + 1) * N + x] = wi;
+      }
+      cur = P1;
+      wr = W[2 * cur * N + x];
+      wi = W[(2 * cur + 1) * N + x];
+      ur = U[2 * cur * N + x];
+      ui = U[(2 * cur + 1) * N + x];
+      oc = occw[cur];
+    }
+    const double pr = Z[(size_t)(2 * t) * N + x], pi = Z[(size_t)(2 * t + 1) * N + x];
+    // W_P2 -= occw_P1 u_P1 phi'
+    const double tr = oc * (ur * pr - ui * pi), ti = oc * (ur * pi + ui * pr);
+    if (P2 == cur) {
+      wr -= tr;
+      wi -= ti;
+      continue;
+    }
+    W[2 * (size_t)P2 * N + x] -= tr;
+    W[(2 * (size_t)P2 + 1) * N + x] -= ti;
+    // W_P1 -= occw_P2 u_P2 conj(phi')
+    const double vr = U[2 * (size_t)P2 * N + x], vi = U[(2 * (size_t)P2 + 1) * N + x];
+    const double o2 = occw[P2];
+    wr -= o2 * (vr * pr + vi * pi);
+    wi -= o2 * (vi * pr - vr * pi);
+  }
+  if (cur >= 0) {
+    W[2 * cur * N + x] = wr;
+    W[(2 * cur + 1) * N + x] = wi;
+  }
+}
+
+// pairE[t0 + t] = dV * sum of the coupling kernel's partials of item t (in order)
+__global__ void __launch_bounds__(256) pair_sum_kernel(const double* __restrict__ part, int nblk,
+                                                      long long t0, double dV,
+                                                      double* __restrict__ pairE) {
+  __shared__ double red[4];
+  const int t = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) s += part[(size_t)t * nblk + k];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) pairE[t0 + t] = dV * s;
+}
+
+// E = -1/4 sum over ordered pairs of occw_P1 occw_P2 (rho, phi)_h: the
+// unordered pairs P1 < P2 count twice
+__global__ void __launch_bounds__(256) bloch_energy_kernel(const double* __restrict__ pairE, int M,
+                                                          const double* __restrict__ occw,
+                                                          double* __restrict__ ex) {
+  __shared__ double red[4];
+  const long long np = (long long)M * (M + 1) / 2;
+  double s = 0.0;
+  for (long long t = threadIdx.x; t < np; t += blockDim.x) {
+    int P1, P2;
+    pair_of(t, M, P1, P2);
+    s += (P1 == P2 ? 1.0 : 2.0) * occw[P1] * occw[P2] * pairE[t];
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *ex = -0.25 * s;
+}
+
+inline dim3 pts_grid(const Geom& g) { return dim3((unsigned)((g.N + 255) / 256)); }
+
+}  // namespace
+
+int bloch_couple_blocks(const Geom& g) { return (int)((g.fsize + kCoupleThreads - 1) / kCoupleThreads); }
+
+hipError_t launch_bloch_table(const BlochAxes& B, const double* kq, int K, int pmax, double* tab,
+                              hipStream_t s) {
+  const dim3 grid((unsigned)((pmax + 63) / 64), 3, (unsigned)(K * K));
+  hipLaunchKernelGGL(bloch_table_kernel, grid, dim3(64), 0, s, B, kq, K, pmax, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_bloch_couple(const BlochAxes& B, const Geom& g, const double* tab, int pmax,
+                               int kernel, double omega, const PairMap& pm, int nitems, double* S,
+                               double* part, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 grid((unsigned)bloch_couple_blocks(g), (unsigned)nitems);
+  hipLaunchKernelGGL(bloch_couple_kernel, grid, dim3(kCoupleThreads), 0, s, B, g, tab, pmax,
+                     kernel, omega, pm, S, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_bloch_fields(int dir, const Geom& g, const BlochT& th, int nb, const double* in,
+                               double* out, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (dir == 0)
+    hipLaunchKernelGGL(field_in_kernel, pts_grid(g), dim3(256), 0, s, in, nb, g, th, out);
+  else
+    hipLaunchKernelGGL(field_out_kernel, pts_grid(g), dim3(256), 0, s, in, nb, g, th, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bloch_orbitals(int dir, const Geom& g, int M, int norb, const double* kq,
+                                 const double* in, double* U, double* W, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  if (dir == 0)
+    hipLaunchKernelGGL(orbitals_in_kernel, pts_grid(g), dim3(256), 0, s, in, M, norb, g, kq, U, W);
+  else
+    hipLaunchKernelGGL(vx_out_kernel, pts_grid(g), dim3(256), 0, s, (const double*)W, M, norb, g,
+                       kq, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_bloch_products(const Geom& g, const double* U, const PairMap& pm, int nb,
+                                 double* Z, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(products_kernel, pts_grid(g), dim3(256), 0, s, U, pm, nb, g, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_bloch_update(const Geom& g, const double* U, const double* Z, const PairMap& pm,
+                               int nb, const double* occw, double* W, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(update_kernel, pts_grid(g), dim3(256), 0, s, U, Z, pm, nb, g, occw, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_bloch_pair_sums(const double* part, int nblk, int nitems, long long t0,
+                                  double dV, double* pairE, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pair_sum_kernel, dim3(nitems), dim3(256), 0, s, part, nblk, t0, dV, pairE);
+  return hipGetLastError();
+}
+
+hipError_t launch_bloch_energy(const double* pairE, int M, const double* occw, double* ex,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(bloch_energy_kernel, dim3(1), dim3(256), 0, s, pairE, M, occw, ex);
+  return hipGetLastError();
+}
+
+}  // namespace kx

@@ -19,6 +19,11 @@ hipError_t launch_pencil_d(const Geom& g, const PencilPlan& p, const EigR<double
                : pen_launch<double, double>(g, p, e, F, nitems, T, T, epart, s);
 }
 
+hipError_t launch_pencil_half(int dir, const Geom& g, const EigR<double>& e, int nitems, double* T,
+                              double* S, hipStream_t s) {
+  return half_launch(dir, g, e, nitems, T, S, s);
+}
+
 hipError_t launch_inverse_d(int storage, int mode, const Geom& g, const SlabPlan& p,
                                const EigR<double>& e, const double* T, const Item* items, int nitems,
                                const void* psi, const double* occ, void* dst, hipStream_t s) {

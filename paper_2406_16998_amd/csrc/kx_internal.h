@@ -188,6 +188,11 @@ hipError_t launch_forward_d(int storage, int mode, const Geom& g, const SlabPlan
 hipError_t launch_pencil_d(const Geom& g, const PencilPlan& p, const EigR<double>& e,
                            const double* F, int nitems, double* T, double* epart, hipStream_t s,
                            float* out_f = nullptr);
+// the two halves of the FP64 pencil pass around a spectral coupling step:
+// dir 0: T (nitems slots) -> mode-3 coefficients S (nitems * fsize, [c][a][b]);
+// dir 1: S -> T
+hipError_t launch_pencil_half(int dir, const Geom& g, const EigR<double>& e, int nitems, double* T,
+                              double* S, hipStream_t s);
 hipError_t launch_inverse_d(int storage, int mode, const Geom& g, const SlabPlan& p,
                             const EigR<double>& e, const double* T, const Item* items, int nitems,
                             const void* psi, const double* occ, void* dst, hipStream_t s);
@@ -256,6 +261,61 @@ int multipole_groups(long long N);
 hipError_t launch_multipole_rhs(int storage, const void* rho, void* dst, int nb, const Geom& g,
                                 const double h[3], const double centre[3], const double* w, int m,
                                 int lmax, double* part, double* mom, hipStream_t s);
+
+// ---- Brillouin-zone sampling (kx_bloch.hip), FP64
+constexpr int kMaxStencil = 12;  // largest stencil half width (order 24)
+constexpr int kMaxKpoints = 64;  // largest k-point count of one exchange application
+// one axis of the folded eigenbasis, for the Bloch coupling tables
+struct BlochAxis {
+  int n, me, mo, pe, po, periodic;
+  double h;
+  const double* VE;  // [i][a] pe x pe, as EigR
+  const double* VO;
+  const double* lamE;
+  const double* lamO;
+  const int* part;   // per blocked index: the coupled mode of the other parity, or -1
+};
+struct BlochAxes {
+  BlochAxis ax[3];
+  double w[kMaxStencil + 1];  // centred second-derivative weights w_0 .. w_m
+  int m;
+};
+// reduced phases theta_a / (2 pi) of a batch of fields, per axis
+struct BlochT {
+  double t[3];
+};
+// The items of one coupling / update launch: pairs t0 + item of the row-major
+// upper triangle of M states (k-point P / norb, band P % norb), whose class is
+// k(P2) * K + k(P1); or, with M == 0, fields of class cls0.
+struct PairMap {
+  long long t0;
+  int M, norb, K, cls0;
+};
+// workgroups of one item of the coupling kernel (its energy partials per item)
+int bloch_couple_blocks(const Geom& g);
+// tab[((cls * 3 + axis) * 2 + {0: A, 1: b}) * pmax + idx] for the K * K
+// classes theta = 2 pi (kq[ki] - kq[qi]), cls = ki * K + qi
+hipError_t launch_bloch_table(const BlochAxes& B, const double* kq, int K, int pmax, double* tab,
+                              hipStream_t s);
+// the spectral coupling of nitems complex items (real / imaginary spectra in
+// S[2 item], S[2 item + 1], fsize each), in place; energy partials per item
+hipError_t launch_bloch_couple(const BlochAxes& B, const Geom& g, const double* tab, int pmax,
+                               int kernel, double omega, const PairMap& pm, int nitems, double* S,
+                               double* part, hipStream_t s);
+// dir 0: interleaved complex fields -> ramp-free planar pairs; dir 1: back
+hipError_t launch_bloch_fields(int dir, const Geom& g, const BlochT& th, int nb, const double* in,
+                               double* out, hipStream_t s);
+// dir 0: psi (interleaved) -> planar u, W = 0; dir 1: W -> Vx psi (interleaved, into U)
+hipError_t launch_bloch_orbitals(int dir, const Geom& g, int M, int norb, const double* kq,
+                                 const double* in, double* U, double* W, hipStream_t s);
+hipError_t launch_bloch_products(const Geom& g, const double* U, const PairMap& pm, int nb,
+                                 double* Z, hipStream_t s);
+hipError_t launch_bloch_update(const Geom& g, const double* U, const double* Z, const PairMap& pm,
+                               int nb, const double* occw, double* W, hipStream_t s);
+hipError_t launch_bloch_pair_sums(const double* part, int nblk, int nitems, long long t0,
+                                  double dV, double* pairE, hipStream_t s);
+hipError_t launch_bloch_energy(const double* pairE, int M, const double* occw, double* ex,
+                               hipStream_t s);
 
 // ---- compressed exchange algebra (kx_ace.hip); fields are rows of N values
 // point-range groups for a gram of na x nb (partials <= 128 MB)

@@ -29,6 +29,7 @@ EXPORTS = (
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
     "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc", "kx_apply_fL_multipole",
+    "kx_reserve_bloch", "kx_apply_fL_bloch", "kx_apply_exchange_bloch",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -62,6 +63,10 @@ def lib():
             "kx_apply_exchange_noalloc": [vp, c_int, c_double, c_int, c_int, vp, dp, vp, c_int],
             "kx_reserve": [vp, c_int, c_int, c_int],
             "kx_apply_fL_multipole": [vp, c_int, c_int, vp, vp, c_int, c_int, dp],
+            "kx_reserve_bloch": [vp, c_int, c_int],
+            "kx_apply_fL_bloch": [vp, c_int, c_double, c_int, dp, vp, vp, c_int],
+            "kx_apply_exchange_bloch": [vp, c_int, c_double, c_int, c_int, dp, dp, dp, vp, vp,
+                                        c_int],
             "kx_exchange_energy": [vp, dp],
             "kx_pair_energies": [vp, c_int, ip, dp],
             "kx_get_eigensystem": [vp, c_int, dp, dp],
@@ -122,6 +127,24 @@ def check_fields(t, shape3, device, name, batch_dims=1):
     if t.dim() != 3 + batch_dims or tuple(t.shape[batch_dims:]) != tuple(shape3):
         raise ValueError(f"{name}: shape {tuple(t.shape)} is not (batch,) + {tuple(shape3)}")
     return DTYPE["f64" if t.dtype == torch.float64 else "f32"]
+
+
+def check_complex_fields(t, shape3, device, name, batch_dims=1):
+    """As check_fields, for complex128 tensors of shape batch + (n3, n2, n1)
+    (interleaved real and imaginary parts)."""
+    import torch
+    if not isinstance(getattr(t, "dtype", None), torch.dtype):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor, got one on {t.device}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name}: on cuda:{t.device.index}, the handle was set up on cuda:{device}")
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{name}: dtype must be complex128, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.dim() != 3 + batch_dims or tuple(t.shape[batch_dims:]) != tuple(shape3):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} is not batch + {tuple(shape3)}")
 
 
 def check_out(out, src, name="out"):
@@ -256,6 +279,13 @@ class Grid:
         except Exception:
             pass
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def reserve(self, norb, prec="fp64", dtype="f64"):
         """kx_reserve: workspace for later calls on up to norb orbitals (0:
         batches of fields) in precision prec on storage dtype."""
@@ -296,6 +326,53 @@ class Grid:
         st = lib().kx_apply_fL_multipole(self._h, rho.shape[0], dt, _ptr(rho), _ptr(out), PREC[prec],
                                          int(lmax), _dptr(c))
         _check(st, "kx_apply_fL_multipole")
+        return out
+
+    def reserve_bloch(self, nk=0, norb=0):
+        """kx_reserve_bloch: buffers of the Bloch calls (nk = 0: fields only)."""
+        _check(lib().kx_reserve_bloch(self._h, int(nk), int(norb)), "kx_reserve_bloch")
+
+    def apply_fL_bloch(self, rho, theta, kernel, omega=0.0, prec="fp64", out=None, reserve=True):
+        """phi = f(-L(theta)) rho for complex128 rho (batch, n3, n2, n1) with
+        the Bloch phases theta (radians per axis, 0 on Dirichlet axes)."""
+        import numpy as np
+        import torch
+        check_complex_fields(rho, self.shape3, self.device, "rho")
+        if out is None:
+            out = torch.empty_like(rho)
+        check_out(out, rho)
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(3))
+        if reserve:
+            self.reserve_bloch(0, 0)
+        st = lib().kx_apply_fL_bloch(self._h, KERNEL[kernel], float(omega), rho.shape[0], _dptr(th),
+                                     _ptr(rho), _ptr(out), PREC[prec])
+        _check(st, "kx_apply_fL_bloch")
+        return out
+
+    def apply_exchange_bloch(self, psi, kpts, wk, occ, kernel, omega=0.0, prec="fp64", out=None,
+                             reserve=True):
+        """(Vx psi)_nk for complex128 psi (nk, norb, n3, n2, n1), reduced
+        k-points kpts (nk, 3), weights wk (nk,) and occupations occ (nk, norb)
+        (host sequences) of one spin channel.  E_x: exchange_energy()."""
+        import numpy as np
+        import torch
+        check_complex_fields(psi, self.shape3, self.device, "psi", batch_dims=2)
+        nk, norb = psi.shape[0], psi.shape[1]
+        k = np.ascontiguousarray(np.asarray(kpts, dtype=np.float64))
+        w = np.ascontiguousarray(np.asarray(wk, dtype=np.float64))
+        o = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        if k.shape != (nk, 3) or w.shape != (nk,) or o.shape != (nk, norb):
+            raise ValueError(f"kpts, wk, occ: shapes {k.shape}, {w.shape}, {o.shape} are not "
+                             f"({nk}, 3), ({nk},), ({nk}, {norb})")
+        if out is None:
+            out = torch.empty_like(psi)
+        check_out(out, psi)
+        if reserve:
+            self.reserve_bloch(nk, norb)
+        st = lib().kx_apply_exchange_bloch(self._h, KERNEL[kernel], float(omega), nk, norb,
+                                           _dptr(k), _dptr(w), _dptr(o), _ptr(psi), _ptr(out),
+                                           PREC[prec])
+        _check(st, "kx_apply_exchange_bloch")
         return out
 
     def _exchange_args(self, psi, occ, out):

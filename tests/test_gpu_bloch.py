@@ -1,0 +1,179 @@
+"""Brillouin-zone sampling on the GPU against the oracle (Sec. II: Bloch
+boundary conditions at k - q): f(-L(theta)) on complex fields for several
+grids, orders, boundary mixes and phases; the k-point exchange operator and
+energy for one spin channel; its reduction to the real exchange at the
+Gamma point; error statuses."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import bloch_orbitals
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def kx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_16998_amd import kx as _kx
+    _kx.lib()
+    return _kx
+
+
+def _cfields(n, batch, seed):
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = n
+    return rng.standard_normal((batch, n3, n2, n1)) + 1j * rng.standard_normal((batch, n3, n2, n1))
+
+
+P3 = ("periodic",) * 3
+SLAB = ("periodic", "periodic", "dirichlet")
+WIRE = ("dirichlet", "periodic", "dirichlet")
+
+# (n, h, order, bc, theta, kernel, omega, batch)
+FIELD_CASES = [
+    ((12, 10, 9), (0.5, 0.45, 0.4), 2, P3, (0.7, -1.9, 2.5), "erfc", 0.3, 3),
+    ((16, 16, 16), (0.4, 0.4, 0.4), 12, P3, (math.pi, math.pi / 2, 0.0), "erfc", 0.2, 2),
+    ((20, 17, 22), (0.4, 0.35, 0.3), 8, SLAB, (1.1, -0.4, 0.0), "coulomb", 0.0, 2),
+    ((9, 31, 14), (0.5, 0.3, 0.45), 4, WIRE, (0.0, 2.9, 0.0), "coulomb", 0.0, 1),
+    ((33, 18, 25), (0.3, 0.3, 0.3), 12, P3, (4.0, -7.0, 0.3), "erfc", 0.25, 1),
+    # theta beyond one period and a batch with a ragged last launch
+    ((10, 11, 12), (0.5, 0.5, 0.5), 6, P3, (0.3, 2 * math.pi + 0.2, -0.5), "erfc", 0.3, 37),
+]
+
+
+@pytest.mark.parametrize("n,h,order,bc,theta,kernel,omega,batch", FIELD_CASES)
+def test_fL_bloch_parity(kx, n, h, order, bc, theta, kernel, omega, batch):
+    import torch
+    print(f"bloch field n={n} order={order} bc={bc} theta={theta} batch={batch}", flush=True)
+    rho = _cfields(n, batch, seed=sum(n) + order)
+    ref = orc.apply_fL_bloch(rho, orc.make_grid_bloch(n, h, order, bc, theta), kernel, omega)
+    with kx.Grid(n, h, order, bc) as g:
+        out = g.apply_fL_bloch(torch.from_numpy(rho).cuda(), theta, kernel, omega)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+    assert _rel(got, ref) <= TOL
+
+
+def test_fL_bloch_zero_phase_is_the_real_solve(kx):
+    # theta = 0: the real and imaginary parts are solved independently by the
+    # real operator, so the Bloch path must agree with kx_apply_fL
+    import torch
+    n, h, order = (14, 13, 12), (0.4, 0.4, 0.4), 8
+    rho = _cfields(n, 2, seed=5)
+    with kx.Grid(n, h, order, P3) as g:
+        got = g.apply_fL_bloch(torch.from_numpy(rho).cuda(), (0.0, 0.0, 0.0), "erfc", 0.3)
+        re = g.apply_fL(torch.from_numpy(np.ascontiguousarray(rho.real)).cuda(), "erfc", 0.3)
+        im = g.apply_fL(torch.from_numpy(np.ascontiguousarray(rho.imag)).cuda(), "erfc", 0.3)
+        torch.cuda.synchronize()
+        ref = re.cpu().numpy() + 1j * im.cpu().numpy()
+        assert _rel(got.cpu().numpy(), ref) <= 1e-12
+
+
+KMESH = [(0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (0.0, 0.5, 0.25), (0.5, 0.5, -0.25)]
+
+# (n, h, order, bc, kpts, norb, kernel, omega)
+EXX_CASES = [
+    ((12, 11, 10), (0.5, 0.5, 0.5), 4, P3, KMESH, 2, "erfc", 0.25),
+    ((14, 12, 16), (0.45, 0.5, 0.4), 8, SLAB, [(0.0, 0.0, 0.0), (0.5, 0.25, 0.0), (-0.25, 0.5, 0.0)],
+     3, "coulomb", 0.0),
+    ((9, 10, 11), (0.5, 0.5, 0.5), 12, P3, [(0.1, 0.2, 0.3)], 5, "erfc", 0.3),
+]
+
+
+@pytest.mark.parametrize("n,h,order,bc,kpts,norb,kernel,omega", EXX_CASES)
+def test_exchange_bloch_parity(kx, n, h, order, bc, kpts, norb, kernel, omega):
+    import torch
+    print(f"bloch exchange n={n} order={order} bc={bc} nk={len(kpts)} norb={norb}", flush=True)
+    nk = len(kpts)
+    psi = bloch_orbitals(n, h, bc, kpts, norb, seed=sum(n), n_centres=6)
+    wk = np.linspace(1.0, 2.0, nk)
+    wk /= wk.sum()
+    occ = np.linspace(1.0, 0.4, nk * norb).reshape(nk, norb)
+    vx_ref, ex_ref = orc.exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, kernel, omega)
+    with kx.Grid(n, h, order, bc) as g:
+        vx = g.apply_exchange_bloch(torch.from_numpy(psi).cuda(), kpts, wk, occ, kernel, omega)
+        torch.cuda.synchronize()
+        got = vx.cpu().numpy()
+        ex = g.exchange_energy()
+        # a second application returns the same bits
+        vx2 = g.apply_exchange_bloch(torch.from_numpy(psi).cuda(), kpts, wk, occ, kernel, omega)
+        torch.cuda.synchronize()
+        assert np.array_equal(vx2.cpu().numpy(), got)
+    assert _rel(got, vx_ref) <= TOL
+    assert abs(ex - ex_ref) <= TOL * abs(ex_ref)
+
+
+def test_exchange_bloch_many_pairs_span_launches(kx):
+    # 4 k-points x 4 bands: 136 state pairs, several launches of the pair batch
+    import torch
+    n, h, order, bc = (10, 9, 8), (0.5, 0.5, 0.5), 6, P3
+    kpts = KMESH
+    psi = bloch_orbitals(n, h, bc, kpts, 4, seed=21, n_centres=5)
+    wk = np.full(4, 0.25)
+    occ = np.ones((4, 4))
+    vx_ref, ex_ref = orc.exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, "erfc", 0.3)
+    with kx.Grid(n, h, order, bc) as g:
+        vx = g.apply_exchange_bloch(torch.from_numpy(psi).cuda(), kpts, wk, occ, "erfc", 0.3)
+        torch.cuda.synchronize()
+        assert _rel(vx.cpu().numpy(), vx_ref) <= TOL
+        assert abs(g.exchange_energy() - ex_ref) <= TOL * abs(ex_ref)
+
+
+def test_exchange_bloch_at_gamma_is_the_real_exchange(kx):
+    # one k-point at Gamma with real orbitals: the real path's operator
+    import torch
+    from synth import make_workload
+    w, psi, occ = make_workload("dirichlet20x27x34_coulomb")
+    psi = psi[:3]
+    occ = occ[:3]
+    with kx.Grid(w.n, w.h, w.order, w.bc) as g:
+        real = g.apply_exchange(torch.from_numpy(psi).cuda(), occ, "coulomb")
+        torch.cuda.synchronize()
+        ex_real = g.exchange_energy()
+        pc = torch.from_numpy(psi.astype(np.complex128)[None]).cuda()
+        vx = g.apply_exchange_bloch(pc, [(0.0, 0.0, 0.0)], [1.0], [occ], "coulomb")
+        torch.cuda.synchronize()
+        got = vx.cpu().numpy()[0]
+        assert np.max(np.abs(got.imag)) <= 1e-12 * np.max(np.abs(got.real))
+        assert _rel(got.real, real.cpu().numpy()) <= 1e-12
+        assert abs(g.exchange_energy() - ex_real) <= 1e-12 * abs(ex_real)
+
+
+def test_bloch_errors(kx):
+    import torch
+    n, h = (8, 8, 8), (0.5, 0.5, 0.5)
+    rho = torch.from_numpy(_cfields(n, 1, seed=1)).cuda()
+    with kx.Grid(n, h, 4, SLAB) as g:
+        with pytest.raises(kx.KxError) as e:
+            g.apply_fL_bloch(rho, (0.1, 0.2, 0.0), "erfc", 0.3, reserve=False)
+        assert e.value.status == 6  # KX_ERR_STATE: not reserved
+        with pytest.raises(kx.KxError) as e:  # a phase on the Dirichlet axis
+            g.apply_fL_bloch(rho, (0.1, 0.2, 0.3), "erfc", 0.3)
+        assert e.value.status == 1
+        with pytest.raises(kx.KxError) as e:
+            g.apply_fL_bloch(rho, (0.1, 0.2, 0.0), "erfc", 0.3, prec="bf16x3")
+        assert e.value.status == 2
+        psi = torch.from_numpy(bloch_orbitals(n, h, SLAB, [(0.0, 0.0, 0.0)], 1, 3, 3)).cuda()
+        with pytest.raises(kx.KxError) as e:  # a k component on the Dirichlet axis
+            g.apply_exchange_bloch(psi, [(0.0, 0.0, 0.5)], [1.0], [[1.0]], "coulomb")
+        assert e.value.status == 1
+    with kx.Grid(n, h, 4, P3) as g:
+        with pytest.raises(kx.KxError) as e:  # the zero mode of the unscreened kernel
+            g.apply_fL_bloch(rho, (2 * math.pi, 0.0, -4 * math.pi), "coulomb")
+        assert e.value.status == 3
+        # a phase that lifts the zero mode is solvable
+        out = g.apply_fL_bloch(rho, (0.5, 0.0, 0.0), "coulomb")
+        torch.cuda.synchronize()
+        ref = orc.apply_fL_bloch(rho.cpu().numpy(), orc.make_grid_bloch(n, h, 4, P3, (0.5, 0.0, 0.0)),
+                                 "coulomb")
+        assert _rel(out.cpu().numpy(), ref) <= TOL
