@@ -365,6 +365,56 @@ def measure_multipole(nfields=64, lmax=6, reps=5):
     return res
 
 
+BLOCH_KMESH = [(a, b, c) for c in (0.0, 0.5) for b in (0.0, 0.5) for a in (0.0, 0.5)]
+
+
+def measure_bloch(norb=8, reps=3, tune=True, tune_cache=None):
+    """The k-point exchange on the headline grid (96^3 periodic, h = 0.35,
+    order 12, erfc with omega = 0.106): a 2 x 2 x 2 Gamma-centred mesh of
+    k-points with norb bands each (one spin channel, occupation 1, equal
+    weights), FP64; seeded Bloch orbitals (sums of Gaussians times the
+    k ramp).  The forward and inverse passes use the launch shapes the
+    autotuner picks for the grid.  Mean of `reps` applications after one
+    warm-up, HIP events on the library's stream."""
+    import numpy as np
+    import torch
+
+    from paper_2406_16998_amd import kx
+    from synth import WORKLOADS, bloch_orbitals
+    w = WORKLOADS["periodic96_erfc"]
+    kpts = BLOCH_KMESH
+    nk = len(kpts)
+    psi_h = bloch_orbitals(w.n, w.h, w.bc, kpts, norb, seed=11, n_centres=48)
+    psi = torch.from_numpy(psi_h).cuda()
+    del psi_h
+    wk = np.full(nk, 1.0 / nk)
+    occ = np.ones((nk, norb))
+    stream = torch.cuda.Stream()
+    g = kx.Grid(w.n, w.h, w.order, w.bc, stream=stream)
+    if tune:
+        g.autotune(prec="fp64", dtype="f64", cache_path=tune_cache)
+    out = torch.empty_like(psi)
+    call = lambda: g.apply_exchange_bloch(psi, kpts, wk, occ, w.kernel, w.omega, out=out)  # noqa: E731
+    call()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(reps):
+            call()
+        stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    M = nk * norb
+    npairs = M * (M + 1) // 2
+    ex = g.exchange_energy()
+    g.close()
+    return {"grid": list(w.n), "kpoints": nk, "bands": norb, "state_pairs": npairs,
+            "ms_per_application": ms, "state_pairs_per_s": npairs / (ms * 1e-3),
+            "E_x": ex, "prec": "fp64"}
+
+
 def bench_ragged(args):
     """The six-system ragged batch through kx_batch_apply_exchange (one graph
     replay per step).  The call synchronises, so steps are timed on the host
@@ -436,6 +486,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-multipole", action="store_true",
                     help="skip the isolated-system single-solve timing")
+    ap.add_argument("--no-bloch", action="store_true",
+                    help="skip the k-point exchange timing")
+    ap.add_argument("--bloch-only", action="store_true",
+                    help="time only the k-point exchange (for profiling)")
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of replays of a recorded graph")
     args = ap.parse_args()
@@ -454,6 +508,10 @@ def main():
     from synth import make_workload
 
     torch.cuda.set_device(0)
+    if args.bloch_only:
+        print(json.dumps({"bloch": measure_bloch(tune=not args.no_tune,
+                                                  tune_cache=args.tune_cache)}))
+        return
     if args.workload == "ragged":
         bench_ragged(args)
         return
@@ -529,6 +587,8 @@ def main():
     result["ace"] = measure_ace(g, psi_d, vx, w)
     if not args.no_multipole:
         result["multipole"] = measure_multipole()
+    if not args.no_bloch:
+        result["bloch"] = measure_bloch(tune=not args.no_tune, tune_cache=args.tune_cache)
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, psi, occ)

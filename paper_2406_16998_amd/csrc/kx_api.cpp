@@ -169,6 +169,8 @@ struct kx_grid {
   // kx_reserve_bloch); capacities in elements
   struct Bloch {
     int* part = nullptr;  // 3 * pmax
+    int* reps = nullptr;  // 3 * pmax: representative indices per axis
+    int nrep[3] = {0, 0, 0};
     int pmax = 0;
     bool mapped = false;
     double* Z = nullptr;  // fields / spectra of a launch
@@ -971,9 +973,25 @@ kx_status bloch_map(kx_grid* g) {
       part[(size_t)a * pmax + ids[r]] = ids[c];
     }
   }
+  // one coupling group per representative: the unpaired modes and the even
+  // member of every pair
+  std::vector<int> reps((size_t)3 * pmax, 0);
+  for (int a = 0; a < 3; ++a) {
+    int r = 0;
+    for (int idx = 0; idx < pes[a] + pos[a]; ++idx) {
+      const bool even = idx < pes[a];
+      if (even ? idx >= mes[a] : idx - pes[a] >= mos[a]) continue;
+      if (!even && part[(size_t)a * pmax + idx] >= 0) continue;
+      reps[(size_t)a * pmax + r++] = idx;
+    }
+    B.nrep[a] = r;
+  }
   kx_status st = dev_alloc((void**)&B.part, sizeof(int) * part.size());
   if (st != KX_OK) return st;
   KX_HIP(hipMemcpy(B.part, part.data(), sizeof(int) * part.size(), hipMemcpyHostToDevice));
+  st = dev_alloc((void**)&B.reps, sizeof(int) * reps.size());
+  if (st != KX_OK) return st;
+  KX_HIP(hipMemcpy(B.reps, reps.data(), sizeof(int) * reps.size(), hipMemcpyHostToDevice));
   B.pmax = pmax;
   B.mapped = true;
   return KX_OK;
@@ -1006,6 +1024,15 @@ BlochAxes bloch_axes(const kx_grid* g) {
   return B;
 }
 
+RepMap bloch_reps(const kx_grid* g) {
+  RepMap rm;
+  for (int a = 0; a < 3; ++a) {
+    rm.rep[a] = g->bl.reps + (size_t)a * g->bl.pmax;
+    rm.R[a] = g->bl.nrep[a];
+  }
+  return rm;
+}
+
 // complex items (pairs, or fields) per launch of the Bloch path
 int bloch_batch(const kx_grid* g) { return g->ws.slots / 2; }
 long long bloch_field_stride(const Geom& G) { return std::max(G.N, G.fsize); }
@@ -1028,8 +1055,8 @@ hipError_t bloch_solve(kx_grid* g, int kernel, double omega, const PairMap& pm, 
   e = timed(g, s, KX_PHASE_PENCIL, [&] {
     hipError_t r = launch_pencil_half(0, G, E, 2 * nb, T, Z, s);
     if (r == hipSuccess)
-      r = launch_bloch_couple(bloch_axes(g), G, g->bl.tab, g->bl.pmax, kernel, omega, pm, nb, Z,
-                              g->bl.epart, s);
+      r = launch_bloch_couple(bloch_axes(g), G, bloch_reps(g), g->bl.tab, g->bl.pmax, kernel,
+                              omega, pm, nb, Z, g->bl.epart, s);
     if (r == hipSuccess) r = launch_pencil_half(1, G, E, 2 * nb, T, Z, s);
     return r;
   });
@@ -1049,7 +1076,7 @@ bool bloch_reserved(const kx_grid* g, int nk, int norb) {
   const int K = std::max(nk, 2);
   const long long M = (long long)nk * norb;
   return B.z_cap >= 2LL * nb * bloch_field_stride(G) &&
-         B.epart_cap >= (long long)nb * bloch_couple_blocks(G) &&
+         B.epart_cap >= (long long)nb * bloch_couple_waves(bloch_reps(g)) &&
          B.tab_cap >= (long long)K * K * 3 * 2 * B.pmax && B.kq_cap >= 3LL * K &&
          B.occw_cap >= M && B.u_cap >= 2 * M * G.N && B.w_cap >= 2 * M * G.N &&
          B.pairE_cap >= M * (M + 1) / 2;
@@ -1410,6 +1437,7 @@ kx_status kx_destroy(kx_grid* g) {
   }
   free_work(g->ws);
   dev_free(g->bl.part);
+  dev_free(g->bl.reps);
   dev_free(g->bl.Z);
   dev_free(g->bl.epart);
   dev_free(g->bl.tab);
@@ -1581,7 +1609,8 @@ kx_status kx_reserve_bloch(kx_grid* g, int nk, int norb) {
   if (nb < 1) return KX_ERR_STATE;
   const int K = std::max(nk, 2);
   st = grow(g, &B.Z, &B.z_cap, 2LL * nb * bloch_field_stride(G));
-  if (st == KX_OK) st = grow(g, &B.epart, &B.epart_cap, (long long)nb * bloch_couple_blocks(G));
+  if (st == KX_OK)
+    st = grow(g, &B.epart, &B.epart_cap, (long long)nb * bloch_couple_waves(bloch_reps(g)));
   if (st == KX_OK) st = grow(g, &B.tab, &B.tab_cap, (long long)K * K * 3 * 2 * B.pmax);
   if (st == KX_OK) st = grow(g, &B.kq, &B.kq_cap, 3LL * K);
   if (st == KX_OK && M > 0) st = grow(g, &B.occw, &B.occw_cap, M);
@@ -1687,7 +1716,7 @@ kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, 
     e = launch_bloch_orbitals(0, G, (int)M, norb, B.kq, (const double*)psi_dev, B.U, B.W, s);
   const long long np = M * (M + 1) / 2;
   const int chunk = bloch_batch(g);
-  const int nblk = bloch_couple_blocks(G);
+  const int nblk = bloch_couple_waves(bloch_reps(g));
   const double dV = g->h[0] * g->h[1] * g->h[2];
   for (long long t0 = 0; t0 < np && e == hipSuccess; t0 += chunk) {
     const int nb = (int)std::min<long long>(chunk, np - t0);

@@ -125,6 +125,7 @@ __device__ __forceinline__ int class_of(const PairMap& pm, int item) {
 }
 
 constexpr int kCoupleThreads = 256;
+constexpr int kCoupleChunk = 8;  // items per thread of the coupling kernel
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -137,81 +138,93 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Y = f(-M) X on every coupled group of the spectra of item `blockIdx.y`
+// Y = f(-M) X on the coupled groups of the spectra of a chunk of items
 // (real part in S[2 item], imaginary part in S[2 item + 1], fsize values
-// each), in place, with Re sum conj(X) Y per workgroup into part.
+// each), in place.  One thread per group, the group named by its
+// representative (per axis an unpaired mode or the even member of a pair);
+// the coefficients c_S are recomputed only when the class changes along the
+// chunk.  Re sum conj(X) Y per wave and item into part[item][wave].
 __global__ void __launch_bounds__(kCoupleThreads)
-bloch_couple_kernel(BlochAxes B, Geom g, const double* __restrict__ tab, int pmax, int kernel,
-                    double omega, PairMap pm, double* __restrict__ S, double* __restrict__ part) {
-  __shared__ double red[kCoupleThreads / 64];
-  const int item = blockIdx.y;
-  const long long pos = (long long)blockIdx.x * kCoupleThreads + threadIdx.x;
-  double e = 0.0;
-  if (pos < g.fsize) {
-    const int ib = (int)(pos % g.p2);
-    const int ia = (int)((pos / g.p2) % g.p1);
-    const int ic = (int)(pos / g.slab);
-    const int idx[3] = {ia, ib, ic};
-    int prt[3];
-    bool rep = true;
-    int pmask = 0;
+bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ tab, int pmax,
+                    int kernel, double omega, PairMap pm, int nitems, double* __restrict__ S,
+                    double* __restrict__ part) {
+  const long long gi = (long long)blockIdx.x * kCoupleThreads + threadIdx.x;
+  const long long ngroups = (long long)rm.R[0] * rm.R[1] * rm.R[2];
+  const bool live = gi < ngroups;
+  const int nwaves = gridDim.x * (kCoupleThreads / 64);
+  const int wave = (int)(gi >> 6);
+  const int lane = threadIdx.x & 63;
+  int idx[3] = {0, 0, 0}, prt[3] = {-1, -1, -1}, pmask = 0;
+  long long off[8];
+  if (live) {
+    const int r2 = (int)(gi % rm.R[1]);
+    const int r1 = (int)((gi / rm.R[1]) % rm.R[0]);
+    const int r3 = (int)(gi / ((long long)rm.R[0] * rm.R[1]));
+    idx[0] = rm.rep[0][r1];
+    idx[1] = rm.rep[1][r2];
+    idx[2] = rm.rep[2][r3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const BlochAxis& A = B.ax[a];
-      if (!valid_idx(A, idx[a])) rep = false;
-      prt[a] = rep ? A.part[idx[a]] : -1;
-      if (prt[a] >= 0) {
-        if (idx[a] >= A.pe) rep = false;  // the odd member: handled by its even partner
-        pmask |= 1 << a;
-      }
+      prt[a] = B.ax[a].part[idx[a]];
+      if (prt[a] >= 0) pmask |= 1 << a;
     }
-    if (rep) {
-      const double* tb = tab + (size_t)class_of(pm, item) * 3 * 2 * pmax;
-      double Aa[3], Ba[3];
-      double asum = 0.0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double* tA = tb + (size_t)a * 2 * pmax;
-        if (prt[a] >= 0) {
-          Aa[a] = 0.5 * (tA[idx[a]] + tA[prt[a]]);
-          Ba[a] = tA[pmax + idx[a]];
-        } else {
-          Aa[a] = tA[idx[a]];
-          Ba[a] = 0.0;
+    for (int t = 0; t < 8; ++t) {
+      const int ja = (t & 1) ? prt[0] : idx[0], jb = (t & 2) ? prt[1] : idx[1];
+      const int jc = (t & 4) ? prt[2] : idx[2];
+      off[t] = (long long)jc * g.slab + (long long)ja * g.p2 + jb;
+    }
+  }
+  const int d = __builtin_popcount(pmask);
+  const double scale = 1.0 / (double)(1 << d);
+  const int i0 = blockIdx.y * kCoupleChunk;
+  const int i1 = min(nitems, i0 + kCoupleChunk);
+  int cur = -1;
+  double c[8];
+  for (int item = i0; item < i1; ++item) {
+    const int cls = class_of(pm, item);
+    double e = 0.0;
+    if (live) {
+      if (cls != cur) {
+        cur = cls;
+        const double* tb = tab + (size_t)cls * 3 * 2 * pmax;
+        double asum = 0.0, Ba[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double* tA = tb + (size_t)a * 2 * pmax;
+          if (prt[a] >= 0) {
+            asum += 0.5 * (tA[idx[a]] + tA[prt[a]]);
+            Ba[a] = tA[pmax + idx[a]];
+          } else {
+            asum += tA[idx[a]];
+            Ba[a] = 0.0;
+          }
         }
-        asum += Aa[a];
+        double f[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          // sign vector t: bit set = the A - b eigenvalue on that axis
+          double lam = asum;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            if ((pmask >> a) & 1) lam += ((t >> a) & 1) ? -Ba[a] : Ba[a];
+          f[t] = (t & ~pmask) ? 0.0 : f_of(kernel, omega, lam);
+        }
+#pragma unroll
+        for (int Sm = 0; Sm < 8; ++Sm) {
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) acc += (__builtin_popcount(t & Sm) & 1) ? -f[t] : f[t];
+          c[Sm] = (Sm & ~pmask) ? 0.0 : acc * scale;
+        }
       }
       double* Sr = S + (size_t)(2 * item) * g.fsize;
       double* Si = Sr + g.fsize;
-      long long off[8];
-      double xr[8], xi[8], f[8];
+      double xr[8], xi[8];
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        if (t & ~pmask) continue;
-        const int ja = (t & 1) ? prt[0] : ia, jb = (t & 2) ? prt[1] : ib, jc = (t & 4) ? prt[2] : ic;
-        off[t] = (long long)jc * g.slab + (long long)ja * g.p2 + jb;
-        xr[t] = Sr[off[t]];
-        xi[t] = Si[off[t]];
-        // sign vector t: bit set = the A - b eigenvalue on that axis
-        double lam = asum;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-          if ((pmask >> a) & 1) lam += ((t >> a) & 1) ? -Ba[a] : Ba[a];
-        f[t] = f_of(kernel, omega, lam);
-      }
-      const int d = __builtin_popcount(pmask);
-      const double scale = 1.0 / (double)(1 << d);
-      double c[8];
-#pragma unroll
-      for (int Sm = 0; Sm < 8; ++Sm) {
-        if (Sm & ~pmask) continue;
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          if (t & ~pmask) continue;
-          acc += (__builtin_popcount(t & Sm) & 1) ? -f[t] : f[t];
-        }
-        c[Sm] = acc * scale;
+        xr[t] = (t & ~pmask) ? 0.0 : Sr[off[t]];
+        xi[t] = (t & ~pmask) ? 0.0 : Si[off[t]];
       }
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
@@ -236,9 +249,9 @@ bloch_couple_kernel(BlochAxes B, Geom g, const double* __restrict__ tab, int pma
         Si[off[t]] = yi;
       }
     }
+    for (int o = 32; o > 0; o >>= 1) e += __shfl_down(e, o, 64);
+    if (lane == 0) part[(size_t)item * nwaves + wave] = e;
   }
-  const double s = block_sum(e, red);
-  if (threadIdx.x == 0) part[(size_t)item * gridDim.x + blockIdx.x] = s;
 }
 
 // e^{-2 pi i s} for s = sum_a t_a x_a / n_a, reduced to [-1/2, 1/2] first
@@ -414,7 +427,10 @@ inline dim3 pts_grid(const Geom& g) { return dim3((unsigned)((g.N + 255) / 256))
 
 }  // namespace
 
-int bloch_couple_blocks(const Geom& g) { return (int)((g.fsize + kCoupleThreads - 1) / kCoupleThreads); }
+int bloch_couple_waves(const RepMap& rm) {
+  const long long groups = (long long)rm.R[0] * rm.R[1] * rm.R[2];
+  return (int)((groups + kCoupleThreads - 1) / kCoupleThreads) * (kCoupleThreads / 64);
+}
 
 hipError_t launch_bloch_table(const BlochAxes& B, const double* kq, int K, int pmax, double* tab,
                               hipStream_t s) {
@@ -423,13 +439,15 @@ hipError_t launch_bloch_table(const BlochAxes& B, const double* kq, int K, int p
   return hipGetLastError();
 }
 
-hipError_t launch_bloch_couple(const BlochAxes& B, const Geom& g, const double* tab, int pmax,
-                               int kernel, double omega, const PairMap& pm, int nitems, double* S,
-                               double* part, hipStream_t s) {
+hipError_t launch_bloch_couple(const BlochAxes& B, const Geom& g, const RepMap& rm,
+                               const double* tab, int pmax, int kernel, double omega,
+                               const PairMap& pm, int nitems, double* S, double* part,
+                               hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  const dim3 grid((unsigned)bloch_couple_blocks(g), (unsigned)nitems);
-  hipLaunchKernelGGL(bloch_couple_kernel, grid, dim3(kCoupleThreads), 0, s, B, g, tab, pmax,
-                     kernel, omega, pm, S, part);
+  const dim3 grid((unsigned)(bloch_couple_waves(rm) / (kCoupleThreads / 64)),
+                  (unsigned)((nitems + kCoupleChunk - 1) / kCoupleChunk));
+  hipLaunchKernelGGL(bloch_couple_kernel, grid, dim3(kCoupleThreads), 0, s, B, g, rm, tab, pmax,
+                     kernel, omega, pm, nitems, S, part);
   return hipGetLastError();
 }
 

@@ -291,17 +291,24 @@ struct PairMap {
   long long t0;
   int M, norb, K, cls0;
 };
-// workgroups of one item of the coupling kernel (its energy partials per item)
-int bloch_couple_blocks(const Geom& g);
+// the representative blocked indices per axis (unpaired modes and the even
+// member of each coupled pair): one coupling group each, R[a] per axis
+struct RepMap {
+  const int* rep[3];
+  int R[3];
+};
+// waves of one coupling launch (its energy partials per item)
+int bloch_couple_waves(const RepMap& rm);
 // tab[((cls * 3 + axis) * 2 + {0: A, 1: b}) * pmax + idx] for the K * K
 // classes theta = 2 pi (kq[ki] - kq[qi]), cls = ki * K + qi
 hipError_t launch_bloch_table(const BlochAxes& B, const double* kq, int K, int pmax, double* tab,
                               hipStream_t s);
 // the spectral coupling of nitems complex items (real / imaginary spectra in
 // S[2 item], S[2 item + 1], fsize each), in place; energy partials per item
-hipError_t launch_bloch_couple(const BlochAxes& B, const Geom& g, const double* tab, int pmax,
-                               int kernel, double omega, const PairMap& pm, int nitems, double* S,
-                               double* part, hipStream_t s);
+hipError_t launch_bloch_couple(const BlochAxes& B, const Geom& g, const RepMap& rm,
+                               const double* tab, int pmax, int kernel, double omega,
+                               const PairMap& pm, int nitems, double* S, double* part,
+                               hipStream_t s);
 // dir 0: interleaved complex fields -> ramp-free planar pairs; dir 1: back
 hipError_t launch_bloch_fields(int dir, const Geom& g, const BlochT& th, int nb, const double* in,
                                double* out, hipStream_t s);
