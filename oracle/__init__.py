@@ -12,14 +12,20 @@ from .kx_oracle import (  # noqa: F401
     apply_coulomb_multipole,
     apply_fL,
     apply_fL_bloch,
+    apply_fL_cell,
     bloch_phases,
+    cell_metric,
+    derivative_1d_bloch,
     exchange,
     exchange_bloch,
+    exchange_cell,
     fd_weights,
+    fd_weights_d1,
     forward_transform,
     kernel_values,
     laplacian_1d,
     laplacian_1d_bloch,
+    laplacian_cell,
     make_grid,
     make_grid_bloch,
     multipole_moments,

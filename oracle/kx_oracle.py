@@ -496,3 +496,139 @@ def exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, kernel, omega=0.0):
                     e = dV * complex(np.sum(np.conj(rho) * phi))
                     ex -= 0.25 * wk[ki] * wk[qi] * occ[ki][nb] * occ[qi][mb] * e.real
     return vx, ex
+
+
+# --------------------------------------------------------------------------
+# Sec. III, closing remark: non-orthogonal cells with periodic or
+# Bloch-periodic conditions on every axis.  With unit lattice directions e_a
+# (the columns of E) and node i_a at xi_a = i_a h_a along e_a, the Laplacian
+# in lattice coordinates is sum_ab g_ab d^2/(dxi_a dxi_b), g = E^-1 E^-T: the
+# diagonal terms take the second-derivative matrices L_a, the mixed terms
+# products of first-derivative matrices D_a D_b (which share the eigenbasis
+# of L_a on a periodic axis).
+# --------------------------------------------------------------------------
+def fd_weights_d1(order: int) -> list:
+    """Centred FD weights d_1..d_m (m = order/2) for d/dx, d_{-p} = -d_p and
+    d_0 = 0, as exact rationals.
+
+    Taylor expansion of sum_p d_p f(x + p h) gives the moment conditions
+    sum_{p=-m}^{m} d_p p^(2k-1) = delta_{k,1} for k = 1..m, i.e.
+    2 sum_{p>=1} d_p p^(2k-1) = delta_{k,1}; solved by Gaussian elimination
+    over the rationals."""
+    if order < 2 or order % 2:
+        raise ValueError("order must be even and >= 2")
+    m = order // 2
+    rows = []
+    for k in range(1, m + 1):
+        row = [Fraction(2 * p ** (2 * k - 1)) for p in range(1, m + 1)]
+        row.append(Fraction(1 if k == 1 else 0))
+        rows.append(row)
+    for col in range(m):
+        piv = next(r for r in range(col, m) if rows[r][col] != 0)
+        rows[col], rows[piv] = rows[piv], rows[col]
+        pv = rows[col][col]
+        rows[col] = [x / pv for x in rows[col]]
+        for r in range(m):
+            if r != col and rows[r][col] != 0:
+                fac = rows[r][col]
+                rows[r] = [a - fac * b for a, b in zip(rows[r], rows[col])]
+    return [rows[k][m] for k in range(m)]
+
+
+def derivative_1d_bloch(n: int, h: float, order: int, theta: float) -> np.ndarray:
+    """n x n complex D_k approximating d/dx on a periodic axis with the Bloch
+    phase theta: D[i, (i + p) mod n] += sgn(p) d_|p| e^{i theta wrap} / h,
+    wrap = floor((i + p) / n) periods (as in laplacian_1d_bloch)."""
+    d = [float(x) for x in fd_weights_d1(order)]
+    m = order // 2
+    D = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        for p in range(-m, m + 1):
+            if p == 0:
+                continue
+            j = i + p
+            dp = d[p - 1] if p > 0 else -d[-p - 1]
+            D[i, j % n] += dp * np.exp(1j * theta * (j // n))
+    return D / h
+
+
+def cell_metric(lattice):
+    """lattice: 3 x 3, row a the direction of lattice axis a (any length).
+    Returns (g, jac): g = E^-1 E^-T with E the unit directions as columns,
+    and jac = |det E|, the volume of a grid cell over h1 h2 h3."""
+    A = np.asarray(lattice, dtype=np.float64)
+    E = (A / np.linalg.norm(A, axis=1)[:, None]).T
+    Ei = np.linalg.inv(E)
+    return Ei @ Ei.T, abs(float(np.linalg.det(E)))
+
+
+def laplacian_cell(n, h, order, lattice, theta) -> np.ndarray:
+    """Dense N x N (complex) Laplacian of the lattice-coordinate form on an
+    all-periodic grid with Bloch phases theta[a], field index
+    (i3 n2 + i2) n1 + i1 (axis 1 fastest):
+      L = sum_a g_aa L_a(theta_a) + sum_{a != b} g_ab D_a(theta_a) D_b(theta_b),
+    each 1-D matrix acting in its own slot of the Kronecker product."""
+    g, _ = cell_metric(lattice)
+    L1 = [laplacian_1d_bloch(n[a], h[a], order, theta[a]) for a in range(3)]
+    D1 = [derivative_1d_bloch(n[a], h[a], order, theta[a]) for a in range(3)]
+    eye = [np.eye(n[a]) for a in range(3)]
+
+    def slot(ops):
+        # ops[a] acts on axis a; axis 3 is the slowest Kronecker factor
+        return np.kron(ops[2], np.kron(ops[1], ops[0]))
+
+    N = n[0] * n[1] * n[2]
+    L = np.zeros((N, N), dtype=np.complex128)
+    for a in range(3):
+        ops = list(eye)
+        ops[a] = L1[a]
+        L += g[a, a] * slot(ops)
+    for a in range(3):
+        for b in range(3):
+            if a != b and g[a, b] != 0.0:
+                ops = list(eye)
+                ops[a] = D1[a]
+                ops[b] = D1[b]
+                L += g[a, b] * slot(ops)
+    return L
+
+
+def apply_fL_cell(rho, n, h, order, lattice, theta, kernel, omega=0.0, eig=None):
+    """phi = f(-L) rho for complex rho (..., n3, n2, n1) on a non-orthogonal
+    all-periodic cell, by the dense eigendecomposition of the Hermitian -L
+    (f(-L) = U f(lam) U^H).  eig: a precomputed (lam, U) of -L."""
+    if eig is None:
+        eig = np.linalg.eigh(-laplacian_cell(n, h, order, lattice, theta))
+    lam, U = eig
+    F = kernel_values(lam, kernel, omega)
+    r = np.asarray(rho, dtype=np.complex128)
+    flat = r.reshape(-1, n[0] * n[1] * n[2])
+    out = (U @ (F[:, None] * (U.conj().T @ flat.T))).T
+    return out.reshape(r.shape)
+
+
+def exchange_cell(psi, kpts, wk, occ, n, h, order, lattice, kernel, omega=0.0):
+    """exchange_bloch on a non-orthogonal all-periodic cell: the same sums
+    over ordered state pairs, each pair solved with the dense f(-L) of its
+    phases 2 pi (k - q), and (u, v)_h = h1 h2 h3 jac sum conj(u) v."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    K, norb = psi.shape[:2]
+    _, jac = cell_metric(lattice)
+    dV = h[0] * h[1] * h[2] * jac
+    bc = ("periodic",) * 3
+    eigs = {}
+    vx = np.zeros_like(psi)
+    ex = 0.0
+    for ki in range(K):
+        for qi in range(K):
+            th = bloch_phases(np.asarray(kpts[ki]) - np.asarray(kpts[qi]), bc)
+            if th not in eigs:
+                eigs[th] = np.linalg.eigh(-laplacian_cell(n, h, order, lattice, th))
+            for nb in range(norb):
+                for mb in range(norb):
+                    rho = np.conj(psi[qi, mb]) * psi[ki, nb]
+                    phi = apply_fL_cell(rho, n, h, order, lattice, th, kernel, omega, eigs[th])
+                    vx[ki, nb] -= wk[qi] * occ[qi][mb] * psi[qi, mb] * phi
+                    e = dV * complex(np.sum(np.conj(rho) * phi))
+                    ex -= 0.25 * wk[ki] * wk[qi] * occ[ki][nb] * occ[qi][mb] * e.real
+    return vx, ex
