@@ -206,6 +206,25 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
  * Only KX_PREC_FP64 is implemented (other precisions: KX_ERR_UNSUPPORTED).
  * Node i of an axis sits at i h. */
 
+/* Non-orthogonal cells (Sec. III, closing remark): lattice[9] holds, row a,
+ * the direction of lattice axis a (any length; node i of axis a sits at
+ * i h_a along it).  With E the unit directions as columns, the Laplacian in
+ * lattice coordinates is
+ *   sum_ab g_ab d^2/(dxi_a dxi_b),  g = E^-1 E^-T,
+ * discretised as sum_a g_aa L_a + sum_{a != b} g_ab D_a D_b with D_a the
+ * centred first-derivative matrix of the same order (weights
+ * d_p = (-1)^(p+1) (m!)^2 / (p (m-p)! (m+p)!)), and the volume element is
+ * h1 h2 h3 |det E|.  Requires periodic conditions on every axis
+ * (KX_ERR_UNSUPPORTED otherwise: D_a and L_a do not commute with Dirichlet
+ * ends).  A non-orthogonal cell is served by the Bloch entry points below
+ * (use the Gamma point, theta = 0, for real orbitals) and kx_ace_build /
+ * kx_ace_apply; kx_apply_fL and the real exchange calls return
+ * KX_ERR_UNSUPPORTED while it is set.  lattice == NULL (or orthonormal
+ * directions) restores the orthogonal cell.  KX_ERR_INVALID_ARG for
+ * non-finite, zero or (nearly) coplanar directions (|det E| <= 1e-6).
+ * Work recorded into a graph before the call must not be replayed after it. */
+kx_status kx_set_cell(kx_grid* g, const double lattice[9]);
+
 /* Reserve the buffers of the Bloch calls below: nk == 0 for
  * kx_apply_fL_bloch alone, else for kx_apply_exchange_bloch on nk k-points of
  * norb bands (and kx_apply_fL_bloch).  Builds, once per handle, the map of

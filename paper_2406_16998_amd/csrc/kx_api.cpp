@@ -41,6 +41,19 @@ void fd_weights_closed_form(int order, double* w) {
   w[0] = -2.0 * s;
 }
 
+// Closed form of the centred first-derivative weights of order 2m:
+//   d_p = (-1)^(p+1) (m!)^2 / (p (m-p)! (m+p)!),  d_{-p} = -d_p,  p = 1..m,
+// into d[1..m] (d[0] = 0); the factorial ratio accumulated as a product.
+void fd_weights_d1_closed_form(int order, double* d) {
+  const int m = order / 2;
+  d[0] = 0.0;
+  for (int p = 1; p <= m; ++p) {
+    double r = 1.0;
+    for (int j = 1; j <= p; ++j) r *= (double)(m - j + 1) / (double)(m + j);
+    d[p] = ((p % 2) ? 1.0 : -1.0) * r / p;
+  }
+}
+
 void laplacian_1d(int n, double h, int order, int bc, double* L) {
   double w[13];
   fd_weights_closed_form(order, w);
@@ -162,6 +175,11 @@ struct kx_grid {
   std::vector<double> V_host[3];
   // f table, filled for the requested kernel by every application
   double* dF = nullptr;
+  // the cell: lattice-coordinate metric and |det E| of a non-orthogonal
+  // all-periodic cell (kx_set_cell); identity and 1 otherwise
+  bool nonorth = false;
+  double cell_g[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  double cell_jac = 1.0;
   // workspace (grown by kx_reserve) and results
   Work ws;
   // Brillouin-zone sampling: the coupled mode of every folded eigenvector
@@ -774,6 +792,7 @@ kx_status plan_exchange(const kx_grid* g, const Work& w, int kernel, double omeg
                         int dtype, const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                         int prec, XPlan& xp) {
   if (!g || norb < 0 || norb > 65535) return KX_ERR_INVALID_ARG;
+  if (g->nonorth) return KX_ERR_UNSUPPORTED;  // mixed derivatives couple the real modes
   kx_status st = check_kernel_args(g, kernel, omega);
   if (st != KX_OK) return st;
   st = check_types(g, dtype, prec);
@@ -1018,11 +1037,18 @@ BlochAxes bloch_axes(const kx_grid* g) {
     A.lamO = g->dLamO[a];
     A.part = g->bl.part + (size_t)a * g->bl.pmax;
   }
-  for (int p = 0; p <= kMaxStencil; ++p) B.w[p] = 0.0;
+  for (int p = 0; p <= kMaxStencil; ++p) B.w[p] = B.d[p] = 0.0;
   fd_weights_closed_form(g->order, B.w);
+  fd_weights_d1_closed_form(g->order, B.d);
   B.m = g->order / 2;
+  B.nonorth = g->nonorth ? 1 : 0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) B.gm[a][b] = g->cell_g[a][b];
   return B;
 }
+
+// the volume element h1 h2 h3 |det E| of the cell
+double cell_dV(const kx_grid* g) { return g->h[0] * g->h[1] * g->h[2] * g->cell_jac; }
 
 RepMap bloch_reps(const kx_grid* g) {
   RepMap rm;
@@ -1077,7 +1103,7 @@ bool bloch_reserved(const kx_grid* g, int nk, int norb) {
   const long long M = (long long)nk * norb;
   return B.z_cap >= 2LL * nb * bloch_field_stride(G) &&
          B.epart_cap >= (long long)nb * bloch_couple_waves(bloch_reps(g)) &&
-         B.tab_cap >= (long long)K * K * 3 * 2 * B.pmax && B.kq_cap >= 3LL * K &&
+         B.tab_cap >= (long long)K * K * 3 * kBlochTab * B.pmax && B.kq_cap >= 3LL * K &&
          B.occw_cap >= M && B.u_cap >= 2 * M * G.N && B.w_cap >= 2 * M * G.N &&
          B.pairE_cap >= M * (M + 1) / 2;
 }
@@ -1470,6 +1496,7 @@ kx_status kx_reserve(kx_grid* g, int norb, int prec, int dtype) {
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
                       const void* rho_dev, void* phi_dev, int prec) {
   if (!g || batch < 0) return KX_ERR_INVALID_ARG;
+  if (g->nonorth) return KX_ERR_UNSUPPORTED;  // mixed derivatives couple the real modes
   kx_status st = check_kernel_args(g, kernel, omega);
   if (st != KX_OK) return st;
   st = check_types(g, dtype, prec);
@@ -1594,6 +1621,60 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
   return KX_OK;
 }
 
+kx_status kx_set_cell(kx_grid* g, const double lattice[9]) {
+  if (!g) return KX_ERR_INVALID_ARG;
+  double gm[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  double jac = 1.0;
+  bool nonorth = false;
+  if (lattice) {
+    // E: the unit lattice directions as columns
+    double E[3][3];
+    for (int a = 0; a < 3; ++a) {
+      double nrm = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        if (!std::isfinite(lattice[3 * a + i])) return KX_ERR_INVALID_ARG;
+        nrm += lattice[3 * a + i] * lattice[3 * a + i];
+      }
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) return KX_ERR_INVALID_ARG;
+      for (int i = 0; i < 3; ++i) E[i][a] = lattice[3 * a + i] / nrm;
+    }
+    const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                       E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                       E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+    if (!(std::fabs(det) > 1e-6)) return KX_ERR_INVALID_ARG;  // (nearly) flat cell
+    // E^-1 by the adjugate, then g = E^-1 E^-T
+    double Ei[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+        Ei[r][c] = (E[r1][c1] * E[r2][c2] - E[r1][c2] * E[r2][c1]) / det;
+      }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double v = 0.0;
+        for (int i = 0; i < 3; ++i) v += Ei[a][i] * Ei[b][i];
+        gm[a][b] = v;
+      }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        if (a != b && std::fabs(gm[a][b]) > 1e-14) nonorth = true;
+    if (nonorth) {
+      if (!all_periodic(g)) return KX_ERR_UNSUPPORTED;
+      jac = std::fabs(det);
+    } else {  // orthonormal directions: the orthogonal cell
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gm[a][b] = a == b ? 1.0 : 0.0;
+    }
+  }
+  g->nonorth = nonorth;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) g->cell_g[a][b] = gm[a][b];
+  g->cell_jac = jac;
+  ++g->gen;  // recorded work carries the metric in its kernel arguments
+  return KX_OK;
+}
+
 kx_status kx_reserve_bloch(kx_grid* g, int nk, int norb) {
   if (!g || nk < 0 || nk > kMaxKpoints || norb < 0 || (nk == 0 && norb != 0))
     return KX_ERR_INVALID_ARG;
@@ -1611,7 +1692,7 @@ kx_status kx_reserve_bloch(kx_grid* g, int nk, int norb) {
   st = grow(g, &B.Z, &B.z_cap, 2LL * nb * bloch_field_stride(G));
   if (st == KX_OK)
     st = grow(g, &B.epart, &B.epart_cap, (long long)nb * bloch_couple_waves(bloch_reps(g)));
-  if (st == KX_OK) st = grow(g, &B.tab, &B.tab_cap, (long long)K * K * 3 * 2 * B.pmax);
+  if (st == KX_OK) st = grow(g, &B.tab, &B.tab_cap, (long long)K * K * 3 * kBlochTab * B.pmax);
   if (st == KX_OK) st = grow(g, &B.kq, &B.kq_cap, 3LL * K);
   if (st == KX_OK && M > 0) st = grow(g, &B.occw, &B.occw_cap, M);
   if (st == KX_OK && M > 0) st = grow(g, &B.U, &B.u_cap, 2 * M * G.N);
@@ -1717,7 +1798,7 @@ kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, 
   const long long np = M * (M + 1) / 2;
   const int chunk = bloch_batch(g);
   const int nblk = bloch_couple_waves(bloch_reps(g));
-  const double dV = g->h[0] * g->h[1] * g->h[2];
+  const double dV = cell_dV(g);
   for (long long t0 = 0; t0 < np && e == hipSuccess; t0 += chunk) {
     const int nb = (int)std::min<long long>(chunk, np - t0);
     const PairMap pm{t0, (int)M, norb, nk, 0};
@@ -2213,7 +2294,7 @@ kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, con
     st = dev_alloc((void**)&g->dAceStatus, sizeof(int));
     if (st != KX_OK) return st;
   }
-  const double dV = g->h[0] * g->h[1] * g->h[2];
+  const double dV = cell_dV(g);
   // -M = -(psi, W)_h, then its Cholesky factor and the factor's inverse
   KX_HIP(launch_gram(dtype, psi_dev, norb, w_dev, norb, N, grp, g->dAcePart, -dV, g->dAceA,
                      g->stream));
@@ -2238,7 +2319,7 @@ kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int 
   const long long grp = ace_groups(N, norb, nvec);
   // buffers reserved by kx_ace_build
   if (norb > g->ace_norb || grp * nk > g->ace_part_cap || nk > g->ace_g_cap) return KX_ERR_STATE;
-  const double dV = g->h[0] * g->h[1] * g->h[2];
+  const double dV = cell_dV(g);
   // G[k][v] = (xi_k, phi_v)_h, then out_v = -sum_k G[k][v] xi_k
   KX_HIP(launch_gram(dtype, xi_dev, norb, phi_dev, nvec, N, grp, g->dAcePart, dV, g->dAceG,
                      g->stream));

@@ -68,18 +68,20 @@ __device__ double circ_form(const BlochAxis& A, int i1, int i2, const double* c,
   return acc;
 }
 
-// Per class (theta = 2 pi (kq[ki] - kq[qi]), class = ki * K + qi) and axis:
-// A[idx] (the diagonal of -M in the folded basis) and b[idx] at the even
-// member of each coupled pair.
+// Per class (theta = 2 pi (kq[ki] - kq[qi]), class = ki * K + qi) and axis,
+// in the folded basis: A[idx], the diagonal of -M, and b[idx], the imaginary
+// part of its entry (even, odd partner) at the even member; on a
+// non-orthogonal cell also, for the first-derivative circulant with entries
+// sgn(p) d_|p| e^{i theta p / n} / h, Q[idx] its (imaginary) diagonal and
+// R[idx] the real part of its entry (even, odd partner) at the even member.
 __global__ void bloch_table_kernel(BlochAxes B, const double* __restrict__ kq, int K, int pmax,
                                    double* __restrict__ tab) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y, cls = blockIdx.z;
   if (idx >= pmax) return;
   const BlochAxis& A = B.ax[a];
-  double* tA = tab + ((size_t)cls * 3 + a) * 2 * pmax;
-  double* tB = tA + pmax;
-  double av = 0.0, bv = 0.0;
+  double* tA = tab + ((size_t)cls * 3 + a) * kBlochTab * pmax;
+  double av = 0.0, bv = 0.0, qv = 0.0, rv = 0.0;
   if (valid_idx(A, idx)) {
     if (!A.periodic) {
       av = idx < A.pe ? A.lamE[idx] : A.lamO[idx - A.pe];
@@ -98,10 +100,24 @@ __global__ void bloch_table_kernel(BlochAxes B, const double* __restrict__ kq, i
       av = circ_form(A, idx, idx, cr, B.m);
       const int o = A.part[idx];
       if (o >= 0 && idx < A.pe) bv = circ_form(A, idx, o, ci, B.m);
+      if (B.nonorth) {
+        const double ih = 1.0 / A.h;
+        for (int p = -B.m; p <= B.m; ++p) {
+          double sn, cs;
+          sincospi(2.0 * d * p / A.n, &sn, &cs);
+          const double dp = p == 0 ? 0.0 : (p > 0 ? B.d[p] : -B.d[-p]);
+          cr[p + B.m] = dp * cs * ih;
+          ci[p + B.m] = dp * sn * ih;
+        }
+        qv = circ_form(A, idx, idx, ci, B.m);
+        if (o >= 0 && idx < A.pe) rv = circ_form(A, idx, o, cr, B.m);
+      }
     }
   }
   tA[idx] = av;
-  tB[idx] = bv;
+  tA[pmax + idx] = bv;
+  tA[2 * pmax + idx] = qv;
+  tA[3 * pmax + idx] = rv;
 }
 
 // (P1, P2), P1 <= P2, of pair t in the row-major upper triangle of M states
@@ -187,27 +203,42 @@ bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ t
     if (live) {
       if (cls != cur) {
         cur = cls;
-        const double* tb = tab + (size_t)cls * 3 * 2 * pmax;
-        double asum = 0.0, Ba[3];
+        const double* tb = tab + (size_t)cls * 3 * kBlochTab * pmax;
+        double Aa[3], Ba[3], Qa[3], Ra[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const double* tA = tb + (size_t)a * 2 * pmax;
-          if (prt[a] >= 0) {
-            asum += 0.5 * (tA[idx[a]] + tA[prt[a]]);
-            Ba[a] = tA[pmax + idx[a]];
-          } else {
-            asum += tA[idx[a]];
-            Ba[a] = 0.0;
+          const double* tA = tb + (size_t)a * kBlochTab * pmax;
+          const bool pr = prt[a] >= 0;
+          Aa[a] = pr ? 0.5 * (tA[idx[a]] + tA[prt[a]]) : tA[idx[a]];
+          Ba[a] = pr ? tA[pmax + idx[a]] : 0.0;
+          Qa[a] = Ra[a] = 0.0;
+          if (B.nonorth) {
+            Qa[a] = pr ? 0.5 * (tA[2 * pmax + idx[a]] + tA[2 * pmax + prt[a]])
+                       : tA[2 * pmax + idx[a]];
+            Ra[a] = pr ? tA[3 * pmax + idx[a]] : 0.0;
           }
         }
         double f[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-          // sign vector t: bit set = the A - b eigenvalue on that axis
-          double lam = asum;
+          // sign vector t: bit set = the -1 eigenvalue of s on that axis, where
+          // -M acts as A + s b and the first-derivative block as i (Q - s R)
+          double lam = 0.0;
+          if (!B.nonorth) {
 #pragma unroll
-          for (int a = 0; a < 3; ++a)
-            if ((pmask >> a) & 1) lam += ((t >> a) & 1) ? -Ba[a] : Ba[a];
+            for (int a = 0; a < 3; ++a)
+              lam += Aa[a] + (((pmask >> a) & 1) ? (((t >> a) & 1) ? -Ba[a] : Ba[a]) : 0.0);
+          } else {
+            double q[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const double sg = ((t >> a) & 1) ? -1.0 : 1.0;
+              lam += B.gm[a][a] * (Aa[a] + sg * Ba[a]);
+              q[a] = Qa[a] - sg * Ra[a];
+            }
+            lam += 2.0 * (B.gm[0][1] * q[0] * q[1] + B.gm[0][2] * q[0] * q[2] +
+                          B.gm[1][2] * q[1] * q[2]);
+          }
           f[t] = (t & ~pmask) ? 0.0 : f_of(kernel, omega, lam);
         }
 #pragma unroll

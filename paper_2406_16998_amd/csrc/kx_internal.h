@@ -278,7 +278,12 @@ struct BlochAxis {
 struct BlochAxes {
   BlochAxis ax[3];
   double w[kMaxStencil + 1];  // centred second-derivative weights w_0 .. w_m
+  double d[kMaxStencil + 1];  // centred first-derivative weights d_1 .. d_m at d[1..m]
   int m;
+  // lattice-coordinate metric g_ab of a non-orthogonal cell (nonorth = 1):
+  // -L = sum_a g_aa (-L_a) - sum_{a != b} g_ab D_a D_b
+  double gm[3][3];
+  int nonorth;
 };
 // reduced phases theta_a / (2 pi) of a batch of fields, per axis
 struct BlochT {
@@ -299,8 +304,13 @@ struct RepMap {
 };
 // waves of one coupling launch (its energy partials per item)
 int bloch_couple_waves(const RepMap& rm);
-// tab[((cls * 3 + axis) * 2 + {0: A, 1: b}) * pmax + idx] for the K * K
-// classes theta = 2 pi (kq[ki] - kq[qi]), cls = ki * K + qi
+// Coupling tables per class (theta = 2 pi (kq[ki] - kq[qi]), cls = ki * K + qi)
+// and axis, kBlochTab arrays of pmax values each at
+// tab[((cls * 3 + axis) * kBlochTab + r) * pmax + idx]: r = 0 A (diagonal of
+// -M), 1 b (its pair coupling, at the even member), 2 Q (the first-derivative
+// circulant's imaginary diagonal), 3 R (its real pair coupling, at the even
+// member); Q and R only on a non-orthogonal cell.
+constexpr int kBlochTab = 4;
 hipError_t launch_bloch_table(const BlochAxes& B, const double* kq, int K, int pmax, double* tab,
                               hipStream_t s);
 // the spectral coupling of nitems complex items (real / imaginary spectra in

@@ -29,7 +29,7 @@ EXPORTS = (
     "kx_fd_weights", "kx_laplacian_1d", "kx_pair_schedule", "kx_profile", "kx_profile_read",
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
     "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc", "kx_apply_fL_multipole",
-    "kx_reserve_bloch", "kx_apply_fL_bloch", "kx_apply_exchange_bloch",
+    "kx_reserve_bloch", "kx_apply_fL_bloch", "kx_apply_exchange_bloch", "kx_set_cell",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -64,6 +64,7 @@ def lib():
             "kx_reserve": [vp, c_int, c_int, c_int],
             "kx_apply_fL_multipole": [vp, c_int, c_int, vp, vp, c_int, c_int, dp],
             "kx_reserve_bloch": [vp, c_int, c_int],
+            "kx_set_cell": [vp, dp],
             "kx_apply_fL_bloch": [vp, c_int, c_double, c_int, dp, vp, vp, c_int],
             "kx_apply_exchange_bloch": [vp, c_int, c_double, c_int, c_int, dp, dp, dp, vp, vp,
                                         c_int],
@@ -327,6 +328,16 @@ class Grid:
                                          int(lmax), _dptr(c))
         _check(st, "kx_apply_fL_multipole")
         return out
+
+    def set_cell(self, lattice=None):
+        """kx_set_cell: lattice directions as rows (3 x 3), None for the
+        orthogonal cell."""
+        import numpy as np
+        if lattice is None:
+            _check(lib().kx_set_cell(self._h, None), "kx_set_cell")
+            return
+        a = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+        _check(lib().kx_set_cell(self._h, _dptr(a)), "kx_set_cell")
 
     def reserve_bloch(self, nk=0, norb=0):
         """kx_reserve_bloch: buffers of the Bloch calls (nk = 0: fields only)."""
