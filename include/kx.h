@@ -34,6 +34,10 @@
  * enqueued; on an error the handle and all outputs are left unchanged and a
  * status other than KX_OK is returned.  Nothing aborts or throws across the
  * ABI.
+ * Diagnostics (environment, read once): KX_LOG=1 prints one line per set-up,
+ * tuned plan, workspace growth and application on stderr; KX_ROCTX=1 makes
+ * every entry point that enqueues work a roctx range (rocprofv3
+ * --marker-trace), the roctx library being looked up at run time.
  */
 #ifndef KX_H
 #define KX_H
@@ -224,6 +228,17 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
  * non-finite, zero or (nearly) coplanar directions (|det E| <= 1e-6).
  * Work recorded into a graph before the call must not be replayed after it. */
 kx_status kx_set_cell(kx_grid* g, const double lattice[9]);
+
+/* Opt-in checks.  KX_CHECK_FINITE: kx_apply_fL, kx_apply_fL_multipole,
+ * kx_apply_exchange, kx_apply_exchange_noalloc, kx_apply_fL_bloch and
+ * kx_apply_exchange_bloch scan their input fields before enqueueing any work
+ * and return KX_ERR_NUMERIC (nothing written) if a value is NaN or infinite;
+ * after the work they scan the outputs (and E_x) and return KX_ERR_NUMERIC
+ * if one is (the outputs then hold the computed values).  With the check on
+ * these calls synchronise the stream and cannot be recorded into a graph
+ * (KX_ERR_STATE while the stream is capturing).  flags: 0 or KX_CHECK_FINITE. */
+#define KX_CHECK_FINITE 1
+kx_status kx_set_checks(kx_grid* g, int flags);
 
 /* Reserve the buffers of the Bloch calls below: nk == 0 for
  * kx_apply_fL_bloch alone, else for kx_apply_exchange_bloch on nk k-points of

@@ -1,11 +1,13 @@
 // Host side of the kx C ABI: argument validation, FD weights and 1-D
 // Laplacian assembly (Sec. III, Eq. (12)), the pair schedule, workspace
 // management and the launch sequence of the transform kernels.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -23,6 +25,61 @@ using namespace kx;
 namespace {
 
 bool valid_order(int order) { return order >= 2 && order <= 24 && order % 2 == 0; }
+
+// ---- diagnostics
+// KX_LOG=1: one line per set-up, plan, workspace growth and application on
+// stderr.  KX_ROCTX=1: every entry point that enqueues work is a roctx range
+// (visible with rocprofv3 --marker-trace); the roctx library is looked up at
+// run time, so nothing is linked when the ranges are off.
+bool env_on(const char* name) {
+  const char* v = std::getenv(name);
+  return v && v[0] && !(v[0] == '0' && v[1] == 0);
+}
+bool log_on() {
+  static const bool on = env_on("KX_LOG");
+  return on;
+}
+void kx_logf(const char* fmt, ...) {
+  if (!log_on()) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fputs("[kx] ", stderr);
+  std::vfprintf(stderr, fmt, ap);
+  std::fputc('\n', stderr);
+  va_end(ap);
+}
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+  Roctx() {
+    if (!env_on("KX_ROCTX")) return;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!push || !pop) push = nullptr, pop = nullptr;
+  }
+};
+const Roctx& roctx() {
+  static const Roctx r;
+  return r;
+}
+struct Range {
+  const bool on;
+  explicit Range(const char* name) : on(roctx().push != nullptr) {
+    if (on) roctx().push(name);
+  }
+  ~Range() {
+    if (on) roctx().pop();
+  }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+const char* prec_name(int prec) {
+  static const char* names[] = {"fp64", "fp32", "bf16x3", "fp16x3", "mixed"};
+  return prec >= 0 && prec <= 4 ? names[prec] : "?";
+}
 
 // Closed form of the centred second-derivative weights of order 2m:
 //   w_p = 2 (-1)^(p+1) (m!)^2 / (p^2 (m-p)! (m+p)!),   w_0 = -2 sum_{p>=1} w_p.
@@ -178,6 +235,9 @@ struct kx_grid {
   // the cell: lattice-coordinate metric and |det E| of a non-orthogonal
   // all-periodic cell (kx_set_cell); identity and 1 otherwise
   bool nonorth = false;
+  // opt-in checks (kx_set_checks) and their device flag
+  int checks = 0;
+  unsigned* dFlag = nullptr;
   double cell_g[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   double cell_jac = 1.0;
   // workspace (grown by kx_reserve) and results
@@ -411,6 +471,21 @@ bool stream_capturing(hipStream_t s) {
 // f(lam1_a + lam2_b + lam3_c) for the requested kernel, written by a kernel
 // into the handle's table (every application writes it, so that work
 // recorded into a graph carries its own table).
+// With KX_CHECK_FINITE set: KX_ERR_NUMERIC if any of the n values at p is
+// NaN or infinite.  Synchronises the stream.
+kx_status check_finite(kx_grid* g, const void* p, int storage, long long n) {
+  if (!(g->checks & KX_CHECK_FINITE) || n <= 0) return KX_OK;
+  KX_HIP(launch_nonfinite(p, storage, n, g->dFlag, g->stream));
+  unsigned v = 0;
+  KX_HIP(hipMemcpyAsync(&v, g->dFlag, sizeof(v), hipMemcpyDeviceToHost, g->stream));
+  KX_HIP(hipStreamSynchronize(g->stream));
+  return v ? KX_ERR_NUMERIC : KX_OK;
+}
+// checks on a stream that is being recorded would synchronise it
+bool checks_block_capture(const kx_grid* g) {
+  return (g->checks & KX_CHECK_FINITE) && stream_capturing(g->stream);
+}
+
 hipError_t fill_ftable(kx_grid* g, int kernel, double omega, hipStream_t s) {
   const double om = (kernel == KX_KERNEL_ERFC) ? omega : 0.0;
   const double* le[3] = {g->dLamE[0], g->dLamE[1], g->dLamE[2]};
@@ -471,6 +546,7 @@ kx_status reserve_slots(kx_grid* g, int slots, bool t2, bool aux16) {
     }
     w.slots = ns;
     w.tbytes = sizeof(double) * (size_t)G.slot;
+    kx_logf("workspace: %d launch slots, %.1f MB of intermediates", ns, tb / 1e6);
   }
   if (grow_t2 || (w.T2 && grow_t)) {
     dev_free(w.T2);
@@ -1163,6 +1239,7 @@ kx_status kx_pair_schedule(int norb, int max_batch, int* npairs_out, int* nbatch
 
 kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, const int bc[3],
                              void* hip_stream, kx_grid** out) {
+  const Range range("kx_setup_laplacian");
   if (!n || !h || !bc || !out) return KX_ERR_INVALID_ARG;
   for (int k = 0; k < 3; ++k) {
     if (n[k] < 1 || n[k] > kMaxN) return KX_ERR_INVALID_ARG;
@@ -1433,6 +1510,13 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order, co
   // the no-allocation entry point's scratch array on this device
   st = scratch_init(g->device);
   if (st != KX_OK) return fail(st);
+  kx_logf("setup n=(%d, %d, %d) h=(%g, %g, %g) order=%d bc=(%c, %c, %c) device=%d "
+          "fwd(slabs %d, kc %d, waves %d) pen(waves %d, lds %zu) inv(slabs %d, kc %d, waves %d)",
+          g->n[0], g->n[1], g->n[2], g->h[0], g->h[1], g->h[2], g->order,
+          g->bc[0] == KX_BC_PERIODIC ? 'P' : 'D', g->bc[1] == KX_BC_PERIODIC ? 'P' : 'D',
+          g->bc[2] == KX_BC_PERIODIC ? 'P' : 'D', g->device, g->plan_d.fwd.slabs, g->plan_d.fwd.kc,
+          g->plan_d.fwd.waves, g->plan_d.pen.waves, g->plan_d.pen.lds_bytes, g->plan_d.inv.slabs,
+          g->plan_d.inv.kc, g->plan_d.inv.waves);
   *out = g;
   return KX_OK;
 }
@@ -1462,6 +1546,7 @@ kx_status kx_destroy(kx_grid* g) {
     dev_free(g->hVOT[k]);
   }
   free_work(g->ws);
+  dev_free(g->dFlag);
   dev_free(g->bl.part);
   dev_free(g->bl.reps);
   dev_free(g->bl.Z);
@@ -1512,6 +1597,13 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   // companion array sized by the launch
   if (prec == KX_PREC_FP16X3 && w.omax_cap < w.slots) return KX_ERR_STATE;
 
+  if (checks_block_capture(g)) return KX_ERR_STATE;
+  const Range range("kx_apply_fL");
+  const long long nel = (long long)batch * g->geom.N;
+  st = check_finite(g, rho_dev, dtype, nel);
+  if (st != KX_OK) return st;
+  kx_logf("apply_fL batch=%d prec=%s storage=%s kernel=%d", batch, prec_name(prec),
+          dtype == KX_F64 ? "f64" : "f32", kernel);
   hipStream_t s = g->stream;
   g->recording = stream_capturing(s);
   hipError_t e = fill_ftable(g, kernel, omega, s);
@@ -1529,7 +1621,7 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
   }
   g->recording = false;
   KX_HIP(e);
-  return KX_OK;
+  return check_finite(g, phi_dev, dtype, nel);
 }
 
 kx_status kx_apply_fL_multipole(kx_grid* g, int batch, int dtype, const void* rho_dev,
@@ -1551,6 +1643,13 @@ kx_status kx_apply_fL_multipole(kx_grid* g, int batch, int dtype, const void* rh
       (prec == KX_PREC_FP16X3 && (!w.tmax || w.omax_cap < w.slots)))
     return KX_ERR_STATE;
 
+  if (checks_block_capture(g)) return KX_ERR_STATE;
+  const Range range("kx_apply_fL_multipole");
+  const long long nel = (long long)batch * g->geom.N;
+  st = check_finite(g, rho_dev, dtype, nel);
+  if (st != KX_OK) return st;
+  kx_logf("apply_fL_multipole batch=%d prec=%s lmax=%d centre=(%g, %g, %g)", batch,
+          prec_name(prec), lmax, centre[0], centre[1], centre[2]);
   double wfd[13];
   fd_weights_closed_form(g->order, wfd);
   hipStream_t s = g->stream;
@@ -1573,7 +1672,7 @@ kx_status kx_apply_fL_multipole(kx_grid* g, int batch, int dtype, const void* rh
   }
   g->recording = false;
   KX_HIP(e);
-  return KX_OK;
+  return check_finite(g, phi_dev, dtype, nel);
 }
 
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
@@ -1584,13 +1683,22 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
   kx_status st = plan_exchange(g, g->ws, kernel, omega, norb, dtype, psi_dev, occ_host, vxpsi_dev,
                                prec, xp);
   if (st != KX_OK) return st;
+  if (checks_block_capture(g)) return KX_ERR_STATE;
+  const Range range("kx_apply_exchange");
+  const long long nel = (long long)norb * g->geom.N;
+  st = check_finite(g, psi_dev, dtype, nel);
+  if (st != KX_OK) return st;
+  kx_logf("apply_exchange norb=%d prec=%s storage=%s kernel=%d batches=%zu", norb,
+          prec_name(prec), dtype == KX_F64 ? "f64" : "f32", kernel,
+          xp.offsets.empty() ? (size_t)0 : xp.offsets.size() - 1);
   g->recording = stream_capturing(g->stream);
   const hipError_t e = enqueue_exchange(g, xp, g->ws, g->stream);
   g->recording = false;
   KX_HIP(e);
   g->last_norb = norb;
   g->last_pairE = g->ws.pairE;
-  return KX_OK;
+  st = check_finite(g, vxpsi_dev, dtype, nel);
+  return st != KX_OK ? st : check_finite(g, g->dEx, KX_F64, norb > 0 ? 1 : 0);
 }
 
 kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int norb, int dtype,
@@ -1604,6 +1712,12 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
   XPlan xp;
   st = plan_exchange(g, w, kernel, omega, norb, dtype, psi_dev, occ_host, vxpsi_dev, prec, xp);
   if (st != KX_OK) return st;
+  if (checks_block_capture(g)) return KX_ERR_STATE;
+  const Range range("kx_apply_exchange_noalloc");
+  const long long nel = (long long)norb * g->geom.N;
+  st = check_finite(g, psi_dev, dtype, nel);
+  if (st != KX_OK) return st;
+  kx_logf("apply_exchange_noalloc norb=%d prec=%s launch slots=%d", norb, prec_name(prec), w.slots);
   hipStream_t s = g->stream;
   // earlier calls on this device left other shapes in the shared array: the
   // intermediates' padded rows must read as zero
@@ -1618,7 +1732,8 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
   KX_HIP(e);
   g->last_norb = norb;
   g->last_pairE = w.pairE;
-  return KX_OK;
+  st = check_finite(g, vxpsi_dev, dtype, nel);
+  return st != KX_OK ? st : check_finite(g, g->dEx, KX_F64, norb > 0 ? 1 : 0);
 }
 
 kx_status kx_set_cell(kx_grid* g, const double lattice[9]) {
@@ -1672,6 +1787,20 @@ kx_status kx_set_cell(kx_grid* g, const double lattice[9]) {
     for (int b = 0; b < 3; ++b) g->cell_g[a][b] = gm[a][b];
   g->cell_jac = jac;
   ++g->gen;  // recorded work carries the metric in its kernel arguments
+  kx_logf("cell %s g=[%g %g %g; %g %g %g; %g %g %g] |det E|=%g",
+          nonorth ? "non-orthogonal" : "orthogonal", gm[0][0], gm[0][1], gm[0][2], gm[1][0],
+          gm[1][1], gm[1][2], gm[2][0], gm[2][1], gm[2][2], jac);
+  return KX_OK;
+}
+
+kx_status kx_set_checks(kx_grid* g, int flags) {
+  if (!g || (flags & ~KX_CHECK_FINITE)) return KX_ERR_INVALID_ARG;
+  if ((flags & KX_CHECK_FINITE) && !g->dFlag) {
+    const kx_status st = dev_alloc((void**)&g->dFlag, sizeof(unsigned));
+    if (st != KX_OK) return st;
+  }
+  g->checks = flags;
+  kx_logf("checks 0x%x", flags);
   return KX_OK;
 }
 
@@ -1725,6 +1854,13 @@ kx_status kx_apply_fL_bloch(kx_grid* g, int kernel, double omega, int batch, con
   if (!rho_dev || !phi_dev || rho_dev == phi_dev) return KX_ERR_INVALID_ARG;
   if ((double)batch * (double)g->geom.N > 1.0e18) return KX_ERR_INVALID_ARG;
   if (!bloch_reserved(g, 0, 0)) return KX_ERR_STATE;
+  if (checks_block_capture(g)) return KX_ERR_STATE;
+  const Range range("kx_apply_fL_bloch");
+  const long long nel = 2LL * batch * g->geom.N;
+  kx_status st = check_finite(g, rho_dev, KX_F64, nel);
+  if (st != KX_OK) return st;
+  kx_logf("apply_fL_bloch batch=%d theta=(%g, %g, %g) kernel=%d%s", batch, theta[0], theta[1],
+          theta[2], kernel, g->nonorth ? " non-orthogonal cell" : "");
 
   const Geom& G = g->geom;
   hipStream_t s = g->stream;
@@ -1747,7 +1883,7 @@ kx_status kx_apply_fL_bloch(kx_grid* g, int kernel, double omega, int batch, con
   }
   g->recording = false;
   KX_HIP(e);
-  return KX_OK;
+  return check_finite(g, phi_dev, KX_F64, nel);
 }
 
 kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, int norb,
@@ -1786,6 +1922,13 @@ kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, 
   }
   if (!psi_dev || !vxpsi_dev || psi_dev == vxpsi_dev) return KX_ERR_INVALID_ARG;
   if (!bloch_reserved(g, nk, norb)) return KX_ERR_STATE;
+  if (checks_block_capture(g)) return KX_ERR_STATE;
+  const Range range("kx_apply_exchange_bloch");
+  const long long nel = 2 * M * g->geom.N;
+  st = check_finite(g, psi_dev, KX_F64, nel);
+  if (st != KX_OK) return st;
+  kx_logf("apply_exchange_bloch nk=%d norb=%d state pairs=%lld kernel=%d%s", nk, norb,
+          M * (M + 1) / 2, kernel, g->nonorth ? " non-orthogonal cell" : "");
 
   const Geom& G = g->geom;
   auto& B = g->bl;
@@ -1817,13 +1960,15 @@ kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, 
   KX_HIP(e);
   g->last_norb = 0;  // kx_pair_energies covers real orbitals only
   g->last_pairE = nullptr;
-  return KX_OK;
+  st = check_finite(g, vxpsi_dev, KX_F64, nel);
+  return st != KX_OK ? st : check_finite(g, g->dEx, KX_F64, 1);
 }
 
 kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* kernels,
                                   const double* omegas, const int* norbs, int dtype,
                                   const void* const* psi_dev, const double* const* occ_host,
                                   void* const* vxpsi_dev, int prec, double* ex_out) {
+  const Range range("kx_batch_apply_exchange");
   if (nsys < 1 || nsys > 256 || !grids || !kernels || !omegas || !norbs || !psi_dev || !occ_host ||
       !vxpsi_dev)
     return KX_ERR_INVALID_ARG;
@@ -1923,6 +2068,7 @@ kx_status kx_batch_apply_exchange(int nsys, kx_grid* const* grids, const int* ke
 
 kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
                       const char* cache_path) {
+  const Range range("kx_autotune");
   if (!g || dtype < KX_F64 || dtype > KX_F32) return KX_ERR_INVALID_ARG;
   if (prec == KX_PREC_MIXED) {  // its forward and pencil passes are FP64's, its inverse BF16X3's
     const kx_status st = kx_autotune(g, KX_PREC_FP64, dtype, items, verify, cache_path);
@@ -2189,6 +2335,10 @@ kx_status kx_autotune(kx_grid* g, int prec, int dtype, int items, int verify,
   plan.pen = bp;
   plan.inv = bi;
   ++g->gen;  // recorded graphs carry the old launch shapes
+  kx_logf("autotune %s: fwd(qsplit %d, slabs %d, waves %d, kc %d, vlds %d) pen(waves %d, lds %zu, "
+          "per %d) inv(slabs %d, waves %d, kc %d, vlds %d)",
+          prec_name(prec), bf.qsplit, bf.slabs, bf.waves, bf.kc, bf.vlds ? 1 : 0, bp.waves,
+          bp.lds_bytes, bp.per, bi.slabs, bi.waves, bi.kc, bi.vlds ? 1 : 0);
   if (cache_path && !verify) {
     if (FILE* f = std::fopen(cache_path, "a")) {
       std::fprintf(f, "%s | fwd %d %d %d %d %d %llu | pen %d %llu %d | inv %d %d %d %d %llu\n", key,
@@ -2267,6 +2417,7 @@ extern "C" {
 
 kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, const void* w_dev,
                        void* xi_dev) {
+  const Range range("kx_ace_build");
   kx_status st = check_ace_fields(g, norb, dtype, psi_dev, w_dev, xi_dev);
   if (st != KX_OK) return st;
   const long long N = g->geom.N, nn = (long long)norb * norb;
@@ -2312,6 +2463,7 @@ kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, con
 
 kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int nvec,
                        const void* phi_dev, void* out_dev) {
+  const Range range("kx_ace_apply");
   kx_status st = check_ace_fields(g, norb, dtype, xi_dev, phi_dev, out_dev);
   if (st != KX_OK) return st;
   if (nvec < 1 || nvec > kAceMaxVec) return KX_ERR_INVALID_ARG;

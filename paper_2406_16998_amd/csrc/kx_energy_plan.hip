@@ -242,6 +242,32 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+// flag[0] = 1 if any of x[0 .. n) is NaN or infinite (every writer stores 1)
+template <class S>
+__global__ void __launch_bounds__(256) nonfinite_kernel(const S* __restrict__ x, long long n,
+                                                       unsigned* __restrict__ flag) {
+  bool bad = false;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(x[k]);
+  if (bad) flag[0] = 1u;
+}
+}  // namespace
+
+hipError_t launch_nonfinite(const void* x, int storage, long long n, unsigned* flag, hipStream_t s) {
+  hipError_t e = launch_zero(flag, sizeof(unsigned), s);
+  if (e != hipSuccess || n <= 0) return e;
+  const long long blocks = std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192));
+  if (storage == KX_F64)
+    hipLaunchKernelGGL(nonfinite_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const double*)x, n, flag);
+  else
+    hipLaunchKernelGGL(nonfinite_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float*)x, n, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_narrow(const double* a, float* b, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const long long blocks = std::min<long long>((n + 1023) / 1024, 8192);

@@ -235,6 +235,9 @@ void allow_dynamic_lds(const void* fn, size_t lds);
 // zero `bytes` (a multiple of 4, 4-byte aligned) with a kernel, so that the
 // clearing can be recorded into a graph
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// flag[0] = 1 if any of the n values at x (storage KX_F64 / KX_F32) is not
+// finite, else 0 (cleared by a kernel first)
+hipError_t launch_nonfinite(const void* x, int storage, long long n, unsigned* flag, hipStream_t s);
 // tuning helpers: index-hash values in [-1, 1); count of differing words
 hipError_t launch_pattern(void* p, long long n, bool dbl, hipStream_t s);
 hipError_t launch_diff(const void* a, const void* b, size_t bytes, unsigned long long* count,

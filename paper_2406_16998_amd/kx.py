@@ -30,6 +30,7 @@ EXPORTS = (
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
     "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc", "kx_apply_fL_multipole",
     "kx_reserve_bloch", "kx_apply_fL_bloch", "kx_apply_exchange_bloch", "kx_set_cell",
+    "kx_set_checks",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -65,6 +66,7 @@ def lib():
             "kx_apply_fL_multipole": [vp, c_int, c_int, vp, vp, c_int, c_int, dp],
             "kx_reserve_bloch": [vp, c_int, c_int],
             "kx_set_cell": [vp, dp],
+            "kx_set_checks": [vp, c_int],
             "kx_apply_fL_bloch": [vp, c_int, c_double, c_int, dp, vp, vp, c_int],
             "kx_apply_exchange_bloch": [vp, c_int, c_double, c_int, c_int, dp, dp, dp, vp, vp,
                                         c_int],
@@ -328,6 +330,10 @@ class Grid:
                                          int(lmax), _dptr(c))
         _check(st, "kx_apply_fL_multipole")
         return out
+
+    def set_checks(self, finite=True):
+        """kx_set_checks: KX_CHECK_FINITE on or off."""
+        _check(lib().kx_set_checks(self._h, 1 if finite else 0), "kx_set_checks")
 
     def set_cell(self, lattice=None):
         """kx_set_cell: lattice directions as rows (3 x 3), None for the
