@@ -9,7 +9,6 @@ HBM.  Prints one JSON line.
     python bench.py --calibrate-copy     # plain 1 GiB device copy, for counter scaling
 """
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -69,11 +68,15 @@ def phase_bytes(w, prec):
             "inverse": (off * (t + 6 * s) + diag * (t + 3 * s)) * N}
 
 
+# the sources of the exchange's transform kernels and of their launch shapes
+KERNEL_SOURCES = ("kx_fold.inc", "kx_fold_d.hip", "kx_fold_f.hip", "kx_split.hip",
+                  "kx_energy_plan.hip", "kx_internal.h")
+
+
 def kernel_sources_digest():
-    """Digest of the HIP sources and headers: counter figures recorded for
+    """Digest of the transform kernels' sources: counter figures recorded for
     other sources no longer describe the kernels."""
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2406_16998_amd", "csrc", "*")) +
-                   [os.path.join(ROOT, "include", "kx.h")])
+    files = sorted(os.path.join(ROOT, "paper_2406_16998_amd", "csrc", f) for f in KERNEL_SOURCES)
     h = hashlib.sha256()
     for f in files:
         with open(f, "rb") as fh:
