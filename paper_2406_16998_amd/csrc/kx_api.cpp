@@ -1136,7 +1136,9 @@ RepMap bloch_reps(const kx_grid* g) {
 }
 
 // complex items (pairs, or fields) per launch of the Bloch path
-int bloch_batch(const kx_grid* g) { return g->ws.slots / 2; }
+int bloch_batch(const kx_grid* g) {
+  return g->ws.slots / 2 >= kTileR * kTileC ? g->ws.slots / 2 : 0;
+}
 long long bloch_field_stride(const Geom& G) { return std::max(G.N, G.fsize); }
 
 // One launch of nb complex items whose ramp-free real / imaginary parts are
@@ -1872,7 +1874,7 @@ kx_status kx_apply_fL_bloch(kx_grid* g, int kernel, double omega, int batch, con
     e = launch_bloch_table(bloch_axes(g), g->bl.kq, 2, g->bl.pmax, g->bl.tab, s);
   const int chunk = bloch_batch(g);
   const size_t fb = 2 * sizeof(double) * (size_t)G.N;
-  const PairMap pm{0, 0, 1, 2, 1};
+  const PairMap pm{0, 0, 0, 1, 2, 1};
   for (int b0 = 0; b0 < batch && e == hipSuccess; b0 += chunk) {
     const int nb = std::min(chunk, batch - b0);
     const double* src = (const double*)((const char*)rho_dev + fb * b0);
@@ -1938,21 +1940,23 @@ kx_status kx_apply_exchange_bloch(kx_grid* g, int kernel, double omega, int nk, 
   if (e == hipSuccess) e = launch_bloch_table(bloch_axes(g), B.kq, nk, B.pmax, B.tab, s);
   if (e == hipSuccess)
     e = launch_bloch_orbitals(0, G, (int)M, norb, B.kq, (const double*)psi_dev, B.U, B.W, s);
-  const long long np = M * (M + 1) / 2;
-  const int chunk = bloch_batch(g);
   const int nblk = bloch_couple_waves(bloch_reps(g));
   const double dV = cell_dV(g);
-  for (long long t0 = 0; t0 < np && e == hipSuccess; t0 += chunk) {
-    const int nb = (int)std::min<long long>(chunk, np - t0);
-    const PairMap pm{t0, (int)M, norb, nk, 0};
-    e = launch_bloch_products(G, B.U, pm, nb, B.Z, s);
-    if (e == hipSuccess) e = bloch_solve(g, kernel, omega, pm, nb, s);
-    if (e == hipSuccess)
-      e = timed(g, s, KX_PHASE_ENERGY, [&] {
-        return launch_bloch_pair_sums(B.epart, nblk, nb, t0, dV, B.pairE, s);
-      });
-    if (e == hipSuccess) e = launch_bloch_update(G, B.U, B.Z, pm, nb, B.occw, B.W, s);
-  }
+  // one launch per tile of kTileR x kTileC state pairs of the upper triangle,
+  // column blocks outer, row blocks inner
+  for (int c0 = 0; c0 < (int)M && e == hipSuccess; c0 += kTileC)
+    for (int r0 = 0; r0 < std::min((int)M, c0 + kTileC) && e == hipSuccess; r0 += kTileR) {
+      const int nb = tile_pairs(r0, c0, (int)M);
+      if (nb == 0) continue;
+      const PairMap pm{r0, c0, (int)M, norb, nk, 0};
+      e = launch_bloch_products(G, B.U, pm, nb, B.Z, s);
+      if (e == hipSuccess) e = bloch_solve(g, kernel, omega, pm, nb, s);
+      if (e == hipSuccess)
+        e = timed(g, s, KX_PHASE_ENERGY, [&] {
+          return launch_bloch_pair_sums(B.epart, nblk, nb, pm, dV, B.pairE, s);
+        });
+      if (e == hipSuccess) e = launch_bloch_update(G, B.U, B.Z, pm, nb, B.occw, B.W, s);
+    }
   if (e == hipSuccess)
     e = launch_bloch_orbitals(1, G, (int)M, norb, B.kq, nullptr, (double*)vxpsi_dev, B.W, s);
   if (e == hipSuccess) e = launch_bloch_energy(B.pairE, (int)M, B.occw, g->dEx, s);

@@ -133,10 +133,31 @@ __device__ __forceinline__ void pair_of(long long t, int M, int& P1, int& P2) {
   P2 = (int)(r + (t - start(r)));
 }
 
+__device__ __forceinline__ bool tile_valid(const PairMap& pm, int r, int c) {
+  const int P1 = pm.r0 + r, P2 = pm.c0 + c;
+  return P1 < pm.M && P2 < pm.M && P1 <= P2;
+}
+
+// (P1, P2) of item `item` of the tile
+__device__ __forceinline__ void tile_pair(const PairMap& pm, int item, int& P1, int& P2) {
+  int t = 0;
+  P1 = P2 = 0;
+  for (int r = 0; r < kTileR; ++r)
+    for (int c = 0; c < kTileC; ++c)
+      if (tile_valid(pm, r, c)) {
+        if (t == item) {
+          P1 = pm.r0 + r;
+          P2 = pm.c0 + c;
+          return;
+        }
+        ++t;
+      }
+}
+
 __device__ __forceinline__ int class_of(const PairMap& pm, int item) {
   if (pm.M == 0) return pm.cls0;
   int P1, P2;
-  pair_of(pm.t0 + item, pm.M, P1, P2);
+  tile_pair(pm, item, P1, P2);
   return (P2 / pm.norb) * pm.K + (P1 / pm.norb);  // k of the second state, q of the first
 }
 
@@ -160,6 +181,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // representative (per axis an unpaired mode or the even member of a pair);
 // the coefficients c_S are recomputed only when the class changes along the
 // chunk.  Re sum conj(X) Y per wave and item into part[item][wave].
+template <bool NONORTH>
 __global__ void __launch_bounds__(kCoupleThreads)
 bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ tab, int pmax,
                     int kernel, double omega, PairMap pm, int nitems, double* __restrict__ S,
@@ -171,7 +193,7 @@ bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ t
   const int wave = (int)(gi >> 6);
   const int lane = threadIdx.x & 63;
   int idx[3] = {0, 0, 0}, prt[3] = {-1, -1, -1}, pmask = 0;
-  long long off[8];
+  int off[8];  // offsets inside one spectrum (< fsize)
   if (live) {
     const int r2 = (int)(gi % rm.R[1]);
     const int r1 = (int)((gi / rm.R[1]) % rm.R[0]);
@@ -188,7 +210,7 @@ bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ t
     for (int t = 0; t < 8; ++t) {
       const int ja = (t & 1) ? prt[0] : idx[0], jb = (t & 2) ? prt[1] : idx[1];
       const int jc = (t & 4) ? prt[2] : idx[2];
-      off[t] = (long long)jc * g.slab + (long long)ja * g.p2 + jb;
+      off[t] = (int)((long long)jc * g.slab + (long long)ja * g.p2 + jb);
     }
   }
   const int d = __builtin_popcount(pmask);
@@ -212,7 +234,7 @@ bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ t
           Aa[a] = pr ? 0.5 * (tA[idx[a]] + tA[prt[a]]) : tA[idx[a]];
           Ba[a] = pr ? tA[pmax + idx[a]] : 0.0;
           Qa[a] = Ra[a] = 0.0;
-          if (B.nonorth) {
+          if (NONORTH) {
             Qa[a] = pr ? 0.5 * (tA[2 * pmax + idx[a]] + tA[2 * pmax + prt[a]])
                        : tA[2 * pmax + idx[a]];
             Ra[a] = pr ? tA[3 * pmax + idx[a]] : 0.0;
@@ -224,7 +246,7 @@ bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ t
           // sign vector t: bit set = the -1 eigenvalue of s on that axis, where
           // -M acts as A + s b and the first-derivative block as i (Q - s R)
           double lam = 0.0;
-          if (!B.nonorth) {
+          if (!NONORTH) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
               lam += Aa[a] + (((pmask >> a) & 1) ? (((t >> a) & 1) ? -Ba[a] : Ba[a]) : 0.0);
@@ -359,82 +381,130 @@ __global__ void vx_out_kernel(const double* __restrict__ W, int M, int norb, Geo
   }
 }
 
-// Z[2 t] + i Z[2 t + 1] = conj(u_P1) u_P2 for the pairs t0 + t, t < nb
-__global__ void products_kernel(const double* __restrict__ U, PairMap pm, int nb, Geom g,
-                                double* __restrict__ Z) {
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= g.N) return;
-  for (int t = 0; t < nb; ++t) {
-    int P1, P2;
-    pair_of(pm.t0 + t, pm.M, P1, P2);
-    const double ar = U[(size_t)(2 * P1) * g.N + x], ai = U[(size_t)(2 * P1 + 1) * g.N + x];
-    const double br = U[(size_t)(2 * P2) * g.N + x], bi = U[(size_t)(2 * P2 + 1) * g.N + x];
-    Z[(size_t)(2 * t) * g.N + x] = ar * br + ai * bi;
-    Z[(size_t)(2 * t + 1) * g.N + x] = ar * bi - ai * br;
-  }
+// The tile's states: its kTileC columns c0 + c in slots c, and its kTileR rows
+// r0 + r in slots kTileC + r, or, on a tile of the diagonal (rows inside the
+// columns), in the columns' slots.
+__device__ __forceinline__ int row_slot(const PairMap& pm, int r) {
+  return pm.r0 >= pm.c0 && pm.r0 < pm.c0 + kTileC ? pm.r0 - pm.c0 + r : kTileC + r;
 }
+constexpr int kSlots = kTileC + kTileR;
 
-// For the pairs t0 + t in order, with phi' = Z[2 t] + i Z[2 t + 1]:
-//   W_P2 -= occw_P1 u_P1 phi',  and for P1 != P2  W_P1 -= occw_P2 u_P2 conj(phi').
-// Each thread owns one grid point of every state, so the updates of a state
-// arrive in the global pair order whatever the batches; the first state of a
-// row is held in registers while its row lasts (the same sequence of
-// operations as through memory).
-__global__ void update_kernel(const double* __restrict__ U, const double* __restrict__ Z,
-                              PairMap pm, int nb, Geom g, const double* __restrict__ occw,
-                              double* __restrict__ W) {
+// Z[2 t] + i Z[2 t + 1] = conj(u_P1) u_P2 for the tile's pairs t; the tile's
+// states are read once per grid point
+__global__ void __launch_bounds__(256)
+products_kernel(const double* __restrict__ U, PairMap pm, Geom g, double* __restrict__ Z) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= g.N) return;
   const size_t N = (size_t)g.N;
-  int cur = -1;
-  double wr = 0.0, wi = 0.0, ur = 0.0, ui = 0.0, oc = 0.0;
-  for (int t = 0; t < nb; ++t) {
-    int P1, P2;
-    pair_of(pm.t0 + t, pm.M, P1, P2);
-    if (P1 != cur) {
-      if (cur >= 0) {
-        W[2 * cur * N + x] = wr;
-        W[(2 * cur + 1) * N + x] = wi;
-      }
-      cur = P1;
-      wr = W[2 * cur * N + x];
-      wi = W[(2 * cur + 1) * N + x];
-      ur = U[2 * cur * N + x];
-      ui = U[(2 * cur + 1) * N + x];
-      oc = occw[cur];
-    }
-    const double pr = Z[(size_t)(2 * t) * N + x], pi = Z[(size_t)(2 * t + 1) * N + x];
-    // W_P2 -= occw_P1 u_P1 phi'
-    const double tr = oc * (ur * pr - ui * pi), ti = oc * (ur * pi + ui * pr);
-    if (P2 == cur) {
-      wr -= tr;
-      wi -= ti;
-      continue;
-    }
-    W[2 * (size_t)P2 * N + x] -= tr;
-    W[(2 * (size_t)P2 + 1) * N + x] -= ti;
-    // W_P1 -= occw_P2 u_P2 conj(phi')
-    const double vr = U[2 * (size_t)P2 * N + x], vi = U[(2 * (size_t)P2 + 1) * N + x];
-    const double o2 = occw[P2];
-    wr -= o2 * (vr * pr + vi * pi);
-    wi -= o2 * (vi * pr - vr * pi);
+  double ur[kSlots], ui[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    const int P = k < kTileC ? pm.c0 + k : pm.r0 + (k - kTileC);
+    const bool ok = P < pm.M && (k < kTileC || row_slot(pm, k - kTileC) == k);
+    ur[k] = ok ? U[2 * (size_t)P * N + x] : 0.0;
+    ui[k] = ok ? U[(2 * (size_t)P + 1) * N + x] : 0.0;
   }
-  if (cur >= 0) {
-    W[2 * cur * N + x] = wr;
-    W[(2 * cur + 1) * N + x] = wi;
+  int t = 0;
+#pragma unroll
+  for (int r = 0; r < kTileR; ++r) {
+    const int rs = row_slot(pm, r);
+#pragma unroll
+    for (int c = 0; c < kTileC; ++c) {
+      if (!tile_valid(pm, r, c)) continue;
+      double ar = 0.0, ai = 0.0;
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k)  // the row's slot (a register, not an indexed array)
+        if (k == rs) {
+          ar = ur[k];
+          ai = ui[k];
+        }
+      Z[(size_t)(2 * t) * N + x] = ar * ur[c] + ai * ui[c];
+      Z[(size_t)(2 * t + 1) * N + x] = ar * ui[c] - ai * ur[c];
+      ++t;
+    }
   }
 }
 
-// pairE[t0 + t] = dV * sum of the coupling kernel's partials of item t (in order)
+// For the tile's pairs t in order, with phi' = Z[2 t] + i Z[2 t + 1]:
+//   W_P2 -= occw_P1 u_P1 phi',  and for P1 != P2  W_P1 -= occw_P2 u_P2 conj(phi').
+// Each thread owns one grid point of every state and holds the tile's
+// states (u and the W accumulators) in registers, so every state receives
+// its contributions in one fixed order (the tiles in launch order, the
+// pairs of a tile in row-major order) whatever the batch size.
+__global__ void __launch_bounds__(256)
+update_kernel(const double* __restrict__ U, const double* __restrict__ Z, PairMap pm, Geom g,
+              const double* __restrict__ occw, double* __restrict__ W) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.N) return;
+  const size_t N = (size_t)g.N;
+  double ur[kSlots], ui[kSlots], wr[kSlots], wi[kSlots], oc[kSlots];
+  bool live[kSlots];
+  int st[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    const int P = k < kTileC ? pm.c0 + k : pm.r0 + (k - kTileC);
+    live[k] = P < pm.M && (k < kTileC || row_slot(pm, k - kTileC) == k);
+    st[k] = P;
+    ur[k] = live[k] ? U[2 * (size_t)P * N + x] : 0.0;
+    ui[k] = live[k] ? U[(2 * (size_t)P + 1) * N + x] : 0.0;
+    wr[k] = live[k] ? W[2 * (size_t)P * N + x] : 0.0;
+    wi[k] = live[k] ? W[(2 * (size_t)P + 1) * N + x] : 0.0;
+    oc[k] = live[k] ? occw[P] : 0.0;
+  }
+  int t = 0;
+#pragma unroll
+  for (int r = 0; r < kTileR; ++r) {
+    const int rs = row_slot(pm, r);
+#pragma unroll
+    for (int c = 0; c < kTileC; ++c) {
+      if (!tile_valid(pm, r, c)) continue;
+      const double pr = Z[(size_t)(2 * t) * N + x], pi = Z[(size_t)(2 * t + 1) * N + x];
+      ++t;
+      double ar = 0.0, ai = 0.0, o1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k)
+        if (k == rs) {
+          ar = ur[k];
+          ai = ui[k];
+          o1 = oc[k];
+        }
+      // W_P2 -= occw_P1 u_P1 phi'
+      wr[c] -= o1 * (ar * pr - ai * pi);
+      wi[c] -= o1 * (ar * pi + ai * pr);
+      if (pm.r0 + r == pm.c0 + c) continue;
+      // W_P1 -= occw_P2 u_P2 conj(phi')
+      const double dr = oc[c] * (ur[c] * pr + ui[c] * pi);
+      const double di = oc[c] * (ui[c] * pr - ur[c] * pi);
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k)
+        if (k == rs) {
+          wr[k] -= dr;
+          wi[k] -= di;
+        }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k)
+    if (live[k]) {
+      W[2 * (size_t)st[k] * N + x] = wr[k];
+      W[(2 * (size_t)st[k] + 1) * N + x] = wi[k];
+    }
+}
+
+// pairE[index(P1, P2)] = dV * sum of the coupling kernel's partials of item t (in order)
 __global__ void __launch_bounds__(256) pair_sum_kernel(const double* __restrict__ part, int nblk,
-                                                      long long t0, double dV,
+                                                      PairMap pm, double dV,
                                                       double* __restrict__ pairE) {
   __shared__ double red[4];
   const int t = blockIdx.x;
   double s = 0.0;
   for (int k = threadIdx.x; k < nblk; k += blockDim.x) s += part[(size_t)t * nblk + k];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) pairE[t0 + t] = dV * s;
+  if (threadIdx.x == 0) {
+    int P1, P2;
+    tile_pair(pm, t, P1, P2);
+    pairE[(long long)P1 * pm.M - (long long)P1 * (P1 - 1) / 2 + (P2 - P1)] = dV * s;
+  }
 }
 
 // E = -1/4 sum over ordered pairs of occw_P1 occw_P2 (rho, phi)_h: the
@@ -477,8 +547,12 @@ hipError_t launch_bloch_couple(const BlochAxes& B, const Geom& g, const RepMap& 
   if (nitems <= 0) return hipSuccess;
   const dim3 grid((unsigned)(bloch_couple_waves(rm) / (kCoupleThreads / 64)),
                   (unsigned)((nitems + kCoupleChunk - 1) / kCoupleChunk));
-  hipLaunchKernelGGL(bloch_couple_kernel, grid, dim3(kCoupleThreads), 0, s, B, g, rm, tab, pmax,
-                     kernel, omega, pm, nitems, S, part);
+  if (B.nonorth)
+    hipLaunchKernelGGL(bloch_couple_kernel<true>, grid, dim3(kCoupleThreads), 0, s, B, g, rm, tab,
+                       pmax, kernel, omega, pm, nitems, S, part);
+  else
+    hipLaunchKernelGGL(bloch_couple_kernel<false>, grid, dim3(kCoupleThreads), 0, s, B, g, rm,
+                       tab, pmax, kernel, omega, pm, nitems, S, part);
   return hipGetLastError();
 }
 
@@ -506,21 +580,21 @@ hipError_t launch_bloch_orbitals(int dir, const Geom& g, int M, int norb, const 
 hipError_t launch_bloch_products(const Geom& g, const double* U, const PairMap& pm, int nb,
                                  double* Z, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(products_kernel, pts_grid(g), dim3(256), 0, s, U, pm, nb, g, Z);
+  hipLaunchKernelGGL(products_kernel, pts_grid(g), dim3(256), 0, s, U, pm, g, Z);
   return hipGetLastError();
 }
 
 hipError_t launch_bloch_update(const Geom& g, const double* U, const double* Z, const PairMap& pm,
                                int nb, const double* occw, double* W, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(update_kernel, pts_grid(g), dim3(256), 0, s, U, Z, pm, nb, g, occw, W);
+  hipLaunchKernelGGL(update_kernel, pts_grid(g), dim3(256), 0, s, U, Z, pm, g, occw, W);
   return hipGetLastError();
 }
 
-hipError_t launch_bloch_pair_sums(const double* part, int nblk, int nitems, long long t0,
+hipError_t launch_bloch_pair_sums(const double* part, int nblk, int nitems, const PairMap& pm,
                                   double dV, double* pairE, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pair_sum_kernel, dim3(nitems), dim3(256), 0, s, part, nblk, t0, dV, pairE);
+  hipLaunchKernelGGL(pair_sum_kernel, dim3(nitems), dim3(256), 0, s, part, nblk, pm, dV, pairE);
   return hipGetLastError();
 }
 

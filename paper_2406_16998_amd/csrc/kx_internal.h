@@ -292,13 +292,26 @@ struct BlochAxes {
 struct BlochT {
   double t[3];
 };
-// The items of one coupling / update launch: pairs t0 + item of the row-major
-// upper triangle of M states (k-point P / norb, band P % norb), whose class is
-// k(P2) * K + k(P1); or, with M == 0, fields of class cls0.
+// The items of one launch of the k-point exchange: the state pairs
+// (P1, P2), P1 <= P2 < M, of one tile of kTileR rows (P1 = r0 + r) and
+// kTileC columns (P2 = c0 + c), numbered in row-major order over the tile's
+// valid pairs; states are P = k-point * norb + band, and a pair's class is
+// k(P2) * K + k(P1).  With M == 0 the items are fields of class cls0.
+constexpr int kTileR = 4, kTileC = 8;  // r0 a multiple of kTileR, c0 of kTileC
 struct PairMap {
-  long long t0;
+  int r0, c0;
   int M, norb, K, cls0;
 };
+// valid pairs of the tile at (r0, c0)
+__host__ __device__ inline int tile_pairs(int r0, int c0, int M) {
+  int n = 0;
+  for (int r = 0; r < kTileR; ++r)
+    for (int c = 0; c < kTileC; ++c) {
+      const int P1 = r0 + r, P2 = c0 + c;
+      n += (P1 < M && P2 < M && P1 <= P2) ? 1 : 0;
+    }
+  return n;
+}
 // the representative blocked indices per axis (unpaired modes and the even
 // member of each coupled pair): one coupling group each, R[a] per axis
 struct RepMap {
@@ -332,7 +345,8 @@ hipError_t launch_bloch_products(const Geom& g, const double* U, const PairMap& 
                                  double* Z, hipStream_t s);
 hipError_t launch_bloch_update(const Geom& g, const double* U, const double* Z, const PairMap& pm,
                                int nb, const double* occw, double* W, hipStream_t s);
-hipError_t launch_bloch_pair_sums(const double* part, int nblk, int nitems, long long t0,
+// pairE[index(P1, P2)] (row-major upper triangle of M states) of the launch's items
+hipError_t launch_bloch_pair_sums(const double* part, int nblk, int nitems, const PairMap& pm,
                                   double dV, double* pairE, hipStream_t s);
 hipError_t launch_bloch_energy(const double* pairE, int M, const double* occw, double* ex,
                                hipStream_t s);
