@@ -453,6 +453,24 @@ void plan_candidates(const Geom& g, size_t max_lds, int kind, std::vector<SlabPl
         }
       }
     }
+    // FP64 operands: the b parities on separate waves, twice the waves a slab
+    if (kind == 0) {
+      const int maxb = inv_bsplit_mt(nty) / 64;
+      for (int slabs = 1; 2 * slabs * wps <= maxb; ++slabs) {
+        for (int vl : {0, 1}) {
+          const size_t lds =
+              (size_t)slabs * inv_slab_elems(g, inv_kc(esize), true) * esize + (vl ? vb : 0);
+          if (lds > max_lds) continue;
+          SlabPlan p;
+          p.slabs = slabs;
+          p.waves = 2 * slabs * wps;
+          p.kc = inv_kc(esize);
+          p.vlds = vl != 0;
+          p.lds_bytes = lds;
+          inv.push_back(p);
+        }
+      }
+    }
   }
 }
 

@@ -79,6 +79,9 @@ constexpr int fwd_mt(int nt) { return nt <= 3 ? 1024 : (nt == 4 ? 768 : 640); }
 // other's products
 constexpr int fwd_min_waves(int nt) { return nt <= 3 ? 6 : 1; }
 constexpr int inv_mt(int nt) { return nt <= 2 ? 1024 : (nt == 3 ? 768 : 512); }
+// the FP64 inverse pass with the b parities on separate waves (inverse_bsplit):
+// selected by waves = 2 * (pe1 / 16) * slabs
+constexpr int inv_bsplit_mt(int nt) { return nt <= 3 ? 768 : 640; }
 constexpr int pen_mt(int nt) { return nt <= 2 ? 1024 : 512; }
 constexpr int pen_min_waves(int nt) { return nt <= 3 ? 3 : 1; }
 
