@@ -19,6 +19,7 @@ from .kx_oracle import (  # noqa: F401
     exchange,
     exchange_bloch,
     exchange_cell,
+    exchange_multipole,
     fd_weights,
     fd_weights_d1,
     forward_transform,

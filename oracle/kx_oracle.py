@@ -396,6 +396,28 @@ def apply_coulomb_multipole(rho, grid, centre, lmax):
     return apply_fL(np.asarray(rho, dtype=np.float64) + c / FOUR_PI, grid, "coulomb")
 
 
+def exchange_multipole(psi, occ, grid, centre, lmax):
+    """The unscreened exact exchange of an isolated system (Sec. II with the
+    boundary values of Sec. IV): for every symmetric pair i <= j,
+    phi_ij = apply_coulomb_multipole(psi_i psi_j), (Vx psi)_j -= occ_i phi_ij psi_i
+    and, for i != j, (Vx psi)_i -= occ_j phi_ij psi_j;
+    E_x = -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h.  Returns (vx, E_x)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    norb = psi.shape[0]
+    vx = np.zeros_like(psi)
+    ex = 0.0
+    for i in range(norb):
+        for j in range(i, norb):
+            rho = psi[i] * psi[j]
+            phi = apply_coulomb_multipole(rho, grid, centre, lmax)
+            e = grid.dV * float(np.sum(rho * phi))
+            vx[j] -= occ[i] * phi * psi[i]
+            if i != j:
+                vx[i] -= occ[j] * phi * psi[j]
+            ex -= 0.25 * occ[i] * occ[j] * e * (1.0 if i == j else 2.0)
+    return vx, ex
+
+
 # --------------------------------------------------------------------------
 # Sec. II with Brillouin-zone sampling: the Poisson problem for the pair
 # (m q, n k) carries Bloch boundary conditions at the wavevector k - q along

@@ -153,3 +153,51 @@ def test_rejects_periodic_axes():
     grid = orc.make_grid((6, 6, 6), (0.4,) * 3, 4, ("periodic", "dirichlet", "dirichlet"))
     with pytest.raises(ValueError):
         orc.multipole_rhs_correction(np.ones((6, 6, 6)), grid, (1.0, 1.0, 1.0), 1)
+
+
+def _gaussian_orbitals(n, h, centres, alphas):
+    x1, x2, x3 = orc.node_coords(n, h)
+    Z, Y, X = np.meshgrid(x3, x2, x1, indexing="ij")
+    out = []
+    for c, a in zip(centres, alphas):
+        r2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+        out.append((2 * a / math.pi) ** 0.75 * np.exp(-a * r2))  # unit norm in the continuum
+    return np.array(out)
+
+
+def test_isolated_exchange_matches_the_gaussian_closed_form():
+    # s-type Gaussians psi_i ~ exp(-a_i |r - A_i|^2): every pair density is a
+    # Gaussian charge of exponent p = a_i + a_j and charge Q_ij = int psi_i psi_j,
+    # whose Coulomb self-energy in free space is Q^2 sqrt(2 p / pi).  The
+    # exchange with multipole boundary values approaches the free-space value;
+    # with homogeneous ends it does not.
+    n, h = (36, 34, 38), (0.3, 0.3, 0.3)
+    L = [(n[k] - 1) * h[k] for k in range(3)]
+    mid = [L[k] / 2 for k in range(3)]
+    centres = [(mid[0] - 0.7, mid[1] + 0.2, mid[2] - 0.4), (mid[0] + 0.6, mid[1] - 0.5, mid[2] + 0.3),
+               (mid[0] + 0.1, mid[1] + 0.6, mid[2] + 0.8)]
+    alphas = [0.9, 1.3, 1.1]
+    psi = _gaussian_orbitals(n, h, centres, alphas)
+    occ = np.array([2.0, 1.5, 1.0])
+    exact = 0.0
+    for i in range(3):
+        for j in range(3):
+            p = alphas[i] + alphas[j]
+            mu = alphas[i] * alphas[j] / p
+            d2 = sum((centres[i][k] - centres[j][k]) ** 2 for k in range(3))
+            Q = ((2 * alphas[i] / math.pi) * (2 * alphas[j] / math.pi)) ** 0.75 * (math.pi / p) ** 1.5 \
+                * math.exp(-mu * d2)
+            exact -= 0.25 * occ[i] * occ[j] * Q * Q * math.sqrt(2 * p / math.pi)
+    grid = orc.make_grid(n, h, 12, D3)
+    errs = []
+    for lmax in (0, 2):
+        errs.append(abs(orc.exchange_multipole(psi, occ, grid, mid, lmax)[1] - exact) / abs(exact))
+    vx, ex = orc.exchange_multipole(psi, occ, grid, mid, 6)
+    errs.append(abs(ex - exact) / abs(exact))
+    _, ex0 = orc.exchange(psi, occ, grid, "coulomb")
+    # the error falls as the expansion grows, to the discretisation level
+    assert errs[0] > errs[1] > errs[2] and errs[2] <= 2e-6
+    assert abs(ex0 - exact) >= 1e-2 * abs(exact)
+    # E_x = 1/4 sum_j occ_j <psi_j, (Vx psi)_j>_h
+    ev = 0.25 * sum(occ[j] * grid.dV * float(np.sum(psi[j] * vx[j])) for j in range(3))
+    assert abs(ev - ex) <= 1e-12 * abs(ex)
