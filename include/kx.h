@@ -151,6 +151,24 @@ kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype
 kx_status kx_apply_fL_multipole(kx_grid* g, int batch, int dtype, const void* rho_dev,
                                 void* phi_dev, int prec, int lmax, const double centre[3]);
 
+/* The unscreened exact exchange of an isolated system: kx_apply_exchange
+ * with KX_KERNEL_COULOMB on an all-Dirichlet grid, every pair solve taking
+ * its boundary values from the multipole expansion of its pair density
+ * rho_ij = psi_i psi_j (the problem of kx_apply_fL_multipole: phi_ij =
+ * f(-L_D)(rho_ij + c_ij / (4 pi)), Sec. IV).  The boundary values make the
+ * pair solve non-symmetric, so E_x is taken from the operator,
+ *   E_x = 1/4 sum_j occ_j <psi_j, (Vx psi)_j>_h,
+ * which equals -1/4 sum_{i,j} occ_i occ_j (rho_ij, phi_ij)_h; read it with
+ * kx_exchange_energy (kx_pair_energies then holds no pairs).
+ *   norb, dtype, psi_dev, occ_host, vxpsi_dev  as for kx_apply_exchange
+ *   prec         KX_PREC_FP64 (others: KX_ERR_UNSUPPORTED)
+ *   lmax, centre as for kx_apply_fL_multipole
+ * KX_ERR_UNSUPPORTED unless every axis is Dirichlet.  Enqueues kernels only
+ * (KX_ERR_STATE without kx_reserve(g, norb, KX_PREC_FP64, dtype)). */
+kx_status kx_apply_exchange_multipole(kx_grid* g, int norb, int dtype, const void* psi_dev,
+                                      const double* occ_host, void* vxpsi_dev, int prec, int lmax,
+                                      const double centre[3]);
+
 /* Exact-exchange operator on norb real orbitals (Sec. II, Eqs. (3), (8)):
  *   (Vx psi)_j = - sum_i occ_i phi_ij psi_i,   phi_ij = f(-L)(psi_i psi_j),
  * evaluated over the norb(norb+1)/2 symmetric pairs i <= j; each pair

@@ -178,6 +178,9 @@ struct Work {
   Item* fitems = nullptr;    // (b, -1), b < slots: the items of a batch of fields
   double* mpart = nullptr;   // multipole moment partials (all-Dirichlet grids), per slot
   double* mmom = nullptr;    // multipole moments, per slot
+  double* fields = nullptr;  // pair densities of the isolated-system exchange, slots * N
+  double* dpart = nullptr;   // its energy partials, norb * vx_energy_parts()
+  long long dpart_cap = 0;
   int slots = 0;             // items per launch
   size_t tbytes = 0;         // bytes per slot of T (8- or 4-byte values)
   Item* items = nullptr;     // pair schedule
@@ -521,11 +524,13 @@ kx_status reserve_slots(kx_grid* g, int slots, bool t2, bool aux16) {
     dev_free(w.fitems);
     dev_free(w.mpart);
     dev_free(w.mmom);
+    dev_free(w.fields);
     w.T = nullptr;
     w.epart = nullptr;
     w.fitems = nullptr;
     w.mpart = nullptr;
     w.mmom = nullptr;
+    w.fields = nullptr;
     w.slots = 0;
     const size_t tb = sizeof(double) * (size_t)G.slot * ns;
     kx_status st = dev_alloc(&w.T, tb);
@@ -542,6 +547,8 @@ kx_status reserve_slots(kx_grid* g, int slots, bool t2, bool aux16) {
       st = dev_alloc((void**)&w.mpart, sizeof(double) * K * multipole_groups(G.N) * ns);
       if (st != KX_OK) return st;
       st = dev_alloc((void**)&w.mmom, sizeof(double) * K * ns);
+      if (st != KX_OK) return st;
+      st = dev_alloc((void**)&w.fields, sizeof(double) * (size_t)G.N * ns);
       if (st != KX_OK) return st;
     }
     w.slots = ns;
@@ -607,6 +614,10 @@ kx_status reserve(kx_grid* g, int norb, int prec, int dtype) {
   st = grow(g, &w.occ, &cap, norb);
   if (st != KX_OK) return st;
   w.occ_cap = (int)cap;
+  if (all_dirichlet(g)) {  // the isolated-system exchange's energy partials
+    st = grow(g, &w.dpart, &w.dpart_cap, (long long)norb * vx_energy_parts());
+    if (st != KX_OK) return st;
+  }
   if (prec != KX_PREC_FP64 && dtype == KX_F64) {
     const long long nel = (long long)norb * g->geom.N;
     long long c1 = (long long)w.work32_cap, c2 = (long long)w.work32_cap;
@@ -622,6 +633,8 @@ kx_status reserve(kx_grid* g, int norb, int prec, int dtype) {
 void free_work(Work& w) {
   dev_free(w.mpart);
   dev_free(w.mmom);
+  dev_free(w.fields);
+  dev_free(w.dpart);
   dev_free(w.T);
   dev_free(w.T2);
   dev_free(w.epart);
@@ -1675,6 +1688,82 @@ kx_status kx_apply_fL_multipole(kx_grid* g, int batch, int dtype, const void* rh
   g->recording = false;
   KX_HIP(e);
   return check_finite(g, phi_dev, dtype, nel);
+}
+
+kx_status kx_apply_exchange_multipole(kx_grid* g, int norb, int dtype, const void* psi_dev,
+                                      const double* occ_host, void* vxpsi_dev, int prec, int lmax,
+                                      const double centre[3]) {
+  if (!g || !centre) return KX_ERR_INVALID_ARG;
+  if (lmax < 0 || lmax > kMaxMultipoleL) return KX_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(centre[k])) return KX_ERR_INVALID_ARG;
+  if (!all_dirichlet(g)) return KX_ERR_UNSUPPORTED;
+  XPlan xp;
+  const Work& w = g->ws;
+  kx_status st = plan_exchange(g, w, KX_KERNEL_COULOMB, 0.0, norb, dtype, psi_dev, occ_host,
+                               vxpsi_dev, prec, xp);
+  if (st != KX_OK) return st;
+  if (prec != KX_PREC_FP64) return KX_ERR_UNSUPPORTED;
+  hipStream_t s = g->stream;
+  if (norb == 0) {
+    KX_HIP(launch_zero(g->dEx, sizeof(double), s));
+    g->last_norb = 0;
+    g->last_pairE = nullptr;
+    return KX_OK;
+  }
+  if (!w.fields || w.dpart_cap < (long long)norb * vx_energy_parts()) return KX_ERR_STATE;
+  if (checks_block_capture(g)) return KX_ERR_STATE;
+  const Range range("kx_apply_exchange_multipole");
+  const long long nel = (long long)norb * g->geom.N;
+  st = check_finite(g, psi_dev, dtype, nel);
+  if (st != KX_OK) return st;
+  kx_logf("apply_exchange_multipole norb=%d lmax=%d centre=(%g, %g, %g) batches=%zu", norb, lmax,
+          centre[0], centre[1], centre[2], xp.offsets.size() - 1);
+  const Geom& G = g->geom;
+  const EigR<double> E = eig_of(g);
+  double wfd[13];
+  fd_weights_closed_form(g->order, wfd);
+  double* T = (double*)w.T;
+  g->recording = stream_capturing(s);
+  hipError_t e = fill_ftable(g, KX_KERNEL_COULOMB, 0.0, s);
+  if (e == hipSuccess) e = launch_schedule(norb, w.items, s);
+  if (e == hipSuccess) e = launch_put_doubles(xp.occ.data(), norb, w.occ, s);
+  if (e == hipSuccess) e = launch_zero(vxpsi_dev, elem_size(dtype) * (size_t)nel, s);
+  for (size_t b = 0; e == hipSuccess && b + 1 < xp.offsets.size(); ++b) {
+    const int o0 = xp.offsets[b], nb = xp.offsets[b + 1] - o0;
+    if (nb <= 0) continue;
+    const Item* it = w.items + o0;
+    // rho_ij + c_ij / (4 pi) per pair, then the homogeneous solve and the
+    // Vx psi update of the exchange's inverse pass
+    e = launch_pair_fields(dtype, psi_dev, it, nb, G.N, w.fields, s);
+    if (e == hipSuccess)
+      e = launch_multipole_rhs(KX_F64, w.fields, w.fields, nb, G, g->h, centre, wfd,
+                               g->order / 2, lmax, w.mpart, w.mmom, s);
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_FORWARD, [&] {
+        return launch_forward_d(KX_F64, 0, G, g->plan_d.fwd, E, w.fields, w.fitems, nb, T, s);
+      });
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_PENCIL, [&] {
+        return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, nullptr, s);
+      });
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_INVERSE, [&] {
+        return launch_inverse_d(dtype, 1, G, g->plan_d.inv, E, T, it, nb, psi_dev, w.occ,
+                                vxpsi_dev, s);
+      });
+  }
+  // E_x = 1/4 sum_j occ_j <psi_j, (Vx psi)_j>_h (the boundary values make the
+  // pair solve non-symmetric, so the energy is taken from the operator)
+  if (e == hipSuccess)
+    e = launch_vx_energy(dtype, psi_dev, vxpsi_dev, norb, G.N, w.occ,
+                         g->h[0] * g->h[1] * g->h[2], w.dpart, g->dEx, s);
+  g->recording = false;
+  KX_HIP(e);
+  g->last_norb = 0;  // no per-pair energies on this path
+  g->last_pairE = nullptr;
+  st = check_finite(g, vxpsi_dev, dtype, nel);
+  return st != KX_OK ? st : check_finite(g, g->dEx, KX_F64, 1);
 }
 
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,

@@ -354,6 +354,16 @@ hipError_t launch_bloch_pair_sums(const double* part, int nblk, int nitems, cons
 hipError_t launch_bloch_energy(const double* pairE, int M, const double* occw, double* ex,
                                hipStream_t s);
 
+// the isolated-system exchange (kx_multipole.hip): Z[b] = psi_i psi_j for
+// items[b] (FP64); E_x = 1/4 dV sum_j occ_j <psi_j, vx_j> into ex, with
+// part holding norb * vx_energy_parts() partial sums
+hipError_t launch_pair_fields(int storage, const void* psi, const Item* items, int nb, long long N,
+                              double* Z, hipStream_t s);
+int vx_energy_parts();
+hipError_t launch_vx_energy(int storage, const void* psi, const void* vx, int norb, long long N,
+                            const double* occ, double dV, double* part, double* ex,
+                            hipStream_t s);
+
 // ---- compressed exchange algebra (kx_ace.hip); fields are rows of N values
 // point-range groups for a gram of na x nb (partials <= 128 MB)
 long long ace_groups(long long N, int na, int nb);

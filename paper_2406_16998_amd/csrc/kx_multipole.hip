@@ -286,3 +286,96 @@ hipError_t launch_multipole_rhs(int storage, const void* rho, void* dst, int nb,
 }
 
 }  // namespace kx
+
+// ---- the isolated-system exchange: pair fields and its energy
+namespace kx {
+namespace {
+
+// Z[b] = psi_i psi_j for the pairs items[b] (FP64 fields of N values)
+template <class S>
+__global__ void __launch_bounds__(256) pair_fields_kernel(const S* __restrict__ psi,
+                                                         const Item* __restrict__ items, int nb,
+                                                         long long N, double* __restrict__ Z) {
+  const int b = blockIdx.y;
+  const Item it = items[b];
+  const S* __restrict__ pi = psi + (long long)it.i * N;
+  const S* __restrict__ pj = psi + (long long)it.j * N;
+  double* __restrict__ zb = Z + (long long)b * N;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < N;
+       x += (long long)gridDim.x * blockDim.x)
+    zb[x] = (double)pi[x] * (double)pj[x];
+}
+
+constexpr int kDotBlocks = 512;
+
+// part[j * kDotBlocks + blk] = sum over this block's points of psi_j vx_j
+template <class S>
+__global__ void __launch_bounds__(256) vx_dot_kernel(const S* __restrict__ psi,
+                                                    const S* __restrict__ vx, long long N,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4];
+  const int j = blockIdx.y;
+  const S* __restrict__ a = psi + (long long)j * N;
+  const S* __restrict__ v = vx + (long long)j * N;
+  double s = 0.0;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < N;
+       x += (long long)gridDim.x * blockDim.x)
+    s += (double)a[x] * (double)v[x];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ex = 1/4 dV sum_j occ_j sum_blk part[j][blk]  (= E_x of the applied operator)
+__global__ void __launch_bounds__(256) vx_energy_kernel(const double* __restrict__ part, int nblk,
+                                                       int norb, const double* __restrict__ occ,
+                                                       double dV, double* __restrict__ ex) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long t = threadIdx.x; t < (long long)norb * nblk; t += blockDim.x)
+    s += occ[t / nblk] * part[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *ex = 0.25 * dV * red[0];
+}
+
+}  // namespace
+
+hipError_t launch_pair_fields(int storage, const void* psi, const Item* items, int nb, long long N,
+                              double* Z, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  const dim3 grid((unsigned)std::min<long long>((N + 255) / 256, 1024), (unsigned)nb);
+  if (storage == KX_F64)
+    hipLaunchKernelGGL(pair_fields_kernel<double>, grid, dim3(256), 0, s, (const double*)psi, items,
+                       nb, N, Z);
+  else
+    hipLaunchKernelGGL(pair_fields_kernel<float>, grid, dim3(256), 0, s, (const float*)psi, items,
+                       nb, N, Z);
+  return hipGetLastError();
+}
+
+int vx_energy_parts() { return kDotBlocks; }
+
+hipError_t launch_vx_energy(int storage, const void* psi, const void* vx, int norb, long long N,
+                            const double* occ, double dV, double* part, double* ex,
+                            hipStream_t s) {
+  if (norb <= 0) return hipSuccess;
+  const dim3 grid(kDotBlocks, (unsigned)norb);
+  if (storage == KX_F64)
+    hipLaunchKernelGGL(vx_dot_kernel<double>, grid, dim3(256), 0, s, (const double*)psi,
+                       (const double*)vx, N, part);
+  else
+    hipLaunchKernelGGL(vx_dot_kernel<float>, grid, dim3(256), 0, s, (const float*)psi,
+                       (const float*)vx, N, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(vx_energy_kernel, dim3(1), dim3(256), 0, s, part, kDotBlocks, norb, occ, dV, ex);
+  return hipGetLastError();
+}
+
+}  // namespace kx

@@ -30,7 +30,7 @@ EXPORTS = (
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
     "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc", "kx_apply_fL_multipole",
     "kx_reserve_bloch", "kx_apply_fL_bloch", "kx_apply_exchange_bloch", "kx_set_cell",
-    "kx_set_checks",
+    "kx_set_checks", "kx_apply_exchange_multipole",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -67,6 +67,7 @@ def lib():
             "kx_reserve_bloch": [vp, c_int, c_int],
             "kx_set_cell": [vp, dp],
             "kx_set_checks": [vp, c_int],
+            "kx_apply_exchange_multipole": [vp, c_int, c_int, vp, dp, vp, c_int, c_int, dp],
             "kx_apply_fL_bloch": [vp, c_int, c_double, c_int, dp, vp, vp, c_int],
             "kx_apply_exchange_bloch": [vp, c_int, c_double, c_int, c_int, dp, dp, dp, vp, vp,
                                         c_int],
@@ -412,6 +413,24 @@ class Grid:
         st = lib().kx_apply_exchange(self._h, KERNEL[kernel], float(omega), norb, dt, _ptr(psi),
                                      _dptr(occ_a), _ptr(out), PREC[prec])
         _check(st, "kx_apply_exchange")
+        return out
+
+    def apply_exchange_multipole(self, psi, occ, centre=None, lmax=6, prec="fp64", out=None,
+                                 reserve=True):
+        """The unscreened exchange of an isolated system: every pair solve with
+        boundary values from the multipole expansion about centre (default:
+        the grid's centre).  E_x: exchange_energy()."""
+        import numpy as np
+        dt, occ_a, out = self._exchange_args(psi, occ, out)
+        if centre is None:
+            centre = [(self.n[k] - 1) * self.h[k] / 2 for k in range(3)]
+        c = np.ascontiguousarray(np.asarray(centre, dtype=np.float64).reshape(3))
+        norb = psi.shape[0]
+        if reserve:
+            self.reserve(norb, prec, "f64" if dt == DTYPE["f64"] else "f32")
+        st = lib().kx_apply_exchange_multipole(self._h, norb, dt, _ptr(psi), _dptr(occ_a), _ptr(out),
+                                               PREC[prec], int(lmax), _dptr(c))
+        _check(st, "kx_apply_exchange_multipole")
         return out
 
     def apply_exchange_noalloc(self, psi, occ, kernel, omega=0.0, prec="fp64", out=None):

@@ -124,3 +124,59 @@ def test_multipole_errors(kx):
     c = (np.ctypeslib.as_ctypes(np.array([1.0, float("nan"), 1.0])))
     assert L.kx_apply_fL_multipole(g._h, 1, 0, rho.data_ptr(), phi.data_ptr(), 0, 2, c) == 1
     g.close()
+
+
+# ---- the isolated-system exchange: every pair with multipole boundary values
+
+@pytest.mark.parametrize("n,h,order,norb,lmax,centre,storage", [
+    ((20, 18, 22), (0.4, 0.45, 0.35), 8, 5, 4, (3.5, 4.1, 3.3), "f64"),
+    ((16, 16, 16), (0.45, 0.45, 0.45), 12, 13, 6, None, "f64"),   # 91 pairs: several launches
+    ((18, 21, 17), (0.4, 0.4, 0.4), 6, 4, 2, None, "f32"),
+])
+def test_isolated_exchange_parity(kx, n, h, order, norb, lmax, centre, storage):
+    import torch
+    from synth.orbitals import gaussian_orbitals, orthonormalise_cgs2
+    print(f"isolated exchange n={n} norb={norb} lmax={lmax} {storage}", flush=True)
+    psi = orthonormalise_cgs2(gaussian_orbitals(n, h, D3, norb, sum(n), 2 * norb, True),
+                              h[0] * h[1] * h[2])
+    occ = np.linspace(2.0, 0.5, norb)
+    c = centre if centre is not None else [(n[k] - 1) * h[k] / 2 for k in range(3)]
+    grid = orc.make_grid(n, h, order, D3)
+    if storage == "f32":
+        psi = psi.astype(np.float32)
+    vx_ref, ex_ref = orc.exchange_multipole(psi.astype(np.float64), occ, grid, c, lmax)
+    g = kx.Grid(n, h, order, D3)
+    vx = g.apply_exchange_multipole(torch.from_numpy(np.ascontiguousarray(psi)).cuda(), occ,
+                                    centre=centre, lmax=lmax)
+    torch.cuda.synchronize()
+    ex = g.exchange_energy()
+    got = vx.cpu().numpy().astype(np.float64)
+    tol = TOL64 if storage == "f64" else 2e-6
+    assert _rel(got, vx_ref) <= tol
+    assert abs(ex - ex_ref) <= tol * abs(ex_ref)
+    # the homogeneous exchange of the same orbitals differs (the boundary values matter)
+    g.apply_exchange(torch.from_numpy(np.ascontiguousarray(psi)).cuda(), occ, "coulomb")
+    torch.cuda.synchronize()
+    assert abs(g.exchange_energy() - ex_ref) > 1e-4 * abs(ex_ref)
+    g.close()
+
+
+def test_isolated_exchange_statuses(kx):
+    import torch
+    psi = torch.from_numpy(random_fields((12, 12, 12), 2, seed=3)).cuda()
+    g = kx.Grid((12, 12, 12), (0.4,) * 3, 4, D3)
+    with pytest.raises(kx.KxError) as e:
+        g.apply_exchange_multipole(psi, [1.0, 1.0], reserve=False)
+    assert e.value.status == 6
+    with pytest.raises(kx.KxError) as e:
+        g.apply_exchange_multipole(psi, [1.0, 1.0], prec="bf16x3")
+    assert e.value.status == 2
+    with pytest.raises(kx.KxError) as e:
+        g.apply_exchange_multipole(psi, [1.0, 1.0], lmax=7)
+    assert e.value.status == 1
+    g.close()
+    gp = kx.Grid((12, 12, 12), (0.4,) * 3, 4, ("dirichlet", "periodic", "dirichlet"))
+    with pytest.raises(kx.KxError) as e:
+        gp.apply_exchange_multipole(psi, [1.0, 1.0])
+    assert e.value.status == 2
+    gp.close()
