@@ -334,8 +334,9 @@ def measure_multipole(nfields=64, lmax=6, reps=5):
     order 12, the grid of the ragged batch's third system): kx_apply_fL with
     homogeneous Dirichlet values against kx_apply_fL_multipole (boundary
     values from the multipole expansion to lmax), FP64, on the pair densities
-    psi_0 psi_j of that system's orbitals; mean of `reps` calls after one
-    warm-up, HIP events on the library's stream."""
+    psi_0 psi_j of that system's orbitals; then the exchange of its orbitals
+    with homogeneous ends against kx_apply_exchange_multipole.  Mean of
+    `reps` calls after one warm-up, HIP events on the library's stream."""
     import numpy as np
     import torch
 
@@ -363,8 +364,30 @@ def measure_multipole(nfields=64, lmax=6, reps=5):
         torch.cuda.synchronize()
         ms = start.elapsed_time(stop) / reps
         res[name] = {"ms_per_call": ms, "solves_per_s": k / (ms * 1e-3)}
+    # the exchange of the same system (its orbitals, occupation 2): homogeneous
+    # ends against multipole boundary values for every pair
+    occ = np.full(w.norb, 2.0)
+    psi_d = torch.from_numpy(psi).cuda()
+    vx = torch.empty_like(psi_d)
+    for name, call in (("exchange_homogeneous",
+                        lambda: g.apply_exchange(psi_d, occ, "coulomb", out=vx)),
+                       ("exchange_multipole",
+                        lambda: g.apply_exchange_multipole(psi_d, occ, lmax=lmax, out=vx))):
+        call()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            start.record(stream)
+            for _ in range(reps):
+                call()
+            stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / reps
+        res[name] = {"ms_per_call": ms, "pair_solves_per_s": w.npairs / (ms * 1e-3),
+                     "E_x": g.exchange_energy()}
     g.close()
-    res.update({"grid": list(w.n), "fields": k, "lmax": lmax, "prec": "fp64"})
+    res.update({"grid": list(w.n), "fields": k, "orbitals": w.norb, "lmax": lmax, "prec": "fp64"})
     return res
 
 
@@ -493,6 +516,8 @@ def main():
                     help="skip the k-point exchange timing")
     ap.add_argument("--bloch-only", action="store_true",
                     help="time only the k-point exchange (for profiling)")
+    ap.add_argument("--multipole-only", action="store_true",
+                    help="time only the isolated-system solves and exchange (for profiling)")
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of replays of a recorded graph")
     args = ap.parse_args()
@@ -511,6 +536,9 @@ def main():
     from synth import make_workload
 
     torch.cuda.set_device(0)
+    if args.multipole_only:
+        print(json.dumps({"multipole": measure_multipole()}))
+        return
     if args.bloch_only:
         print(json.dumps({"bloch": measure_bloch(tune=not args.no_tune,
                                                   tune_cache=args.tune_cache)}))

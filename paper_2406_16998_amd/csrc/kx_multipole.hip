@@ -52,7 +52,8 @@ __device__ __forceinline__ void solid_harmonics(double x, double y, double z, do
     for (int l = m; l <= L; ++l) {
       double q = q1;
       if (l > m) {
-        q = ((double)(2 * l - 1) * z * q1 - (double)(l + m - 1) * r2 * q2) / (double)(l - m);
+        // 1 / (l - m) folds to a constant of the unrolled recursion
+        q = ((double)(2 * l - 1) * z * q1 - (double)(l + m - 1) * r2 * q2) * (1.0 / (double)(l - m));
         q2 = q1;
         q1 = q;
       }
@@ -227,8 +228,10 @@ hipError_t launch_typed(const S* rho, S* dst, int nb, const Geom& g, const Coord
   if (e != hipSuccess) return e;
   const long long tot = (long long)nb * g.N;
   const long long blocks = std::min<long long>((tot + 255) / 256, 8192);
-  hipLaunchKernelGGL(copy_fields<S>, dim3((unsigned)blocks), dim3(256), 0, s, rho, dst, tot);
-  e = hipGetLastError();
+  if (rho != dst) {  // (in place: rho is already there)
+    hipLaunchKernelGGL(copy_fields<S>, dim3((unsigned)blocks), dim3(256), 0, s, rho, dst, tot);
+    e = hipGetLastError();
+  }
   const int n[3] = {g.n1, g.n2, g.n3};
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
     const long long lines = (long long)n[k == 0 ? 1 : 0] * n[k == 2 ? 1 : 2];
