@@ -24,6 +24,7 @@ from .kx_oracle import (  # noqa: F401
     fd_weights_d1,
     forward_transform,
     kernel_values,
+    kernel_values_zero_mode,
     laplacian_1d,
     laplacian_1d_bloch,
     laplacian_cell,

@@ -166,6 +166,23 @@ def kernel_values(lam: np.ndarray, kernel: str, omega: float = 0.0) -> np.ndarra
     raise ValueError(kernel)
 
 
+def kernel_values_zero_mode(lam: np.ndarray, kernel: str, omega: float = 0.0,
+                            zero_mode: float | None = None) -> np.ndarray:
+    """kernel_values, except that with the unscreened kernel and zero_mode
+    given, f at the zero eigenvalue (|lam| <= 1e-9 max |lam|: the constant
+    mode of an all-periodic grid at the Gamma point) is zero_mode.  For 3D
+    bulk systems the paper takes that value from auxiliary functions (Sec.
+    IV); here it is an input."""
+    lam = np.asarray(lam, dtype=np.float64)
+    if kernel != "coulomb" or zero_mode is None:
+        return kernel_values(lam, kernel, omega)
+    zero = np.abs(lam) <= 1e-9 * np.max(np.abs(lam))
+    out = np.empty_like(lam)
+    out[~zero] = kernel_values(lam[~zero], kernel, omega)
+    out[zero] = float(zero_mode)
+    return out
+
+
 def _mode(T: np.ndarray, M: np.ndarray, axis: int) -> np.ndarray:
     """out[..., j, ...] = sum_i M[i, j] T[..., i, ...] along ``axis``."""
     out = np.tensordot(T, M, axes=([axis], [0]))
@@ -215,7 +232,7 @@ def pair_energy(psi_i, psi_j, grid, kernel, omega=0.0, F=None):
     return grid.dV * float(np.sum(rho * phi))
 
 
-def exchange(psi, occ, grid, kernel, omega=0.0, pair_energies=False):
+def exchange(psi, occ, grid, kernel, omega=0.0, pair_energies=False, zero_mode=None):
     """All-pairs exact exchange, Eqs. (3)-(4) (unscreened) and (8)-(9)
     (screened), for real orbitals psi of shape (norb, n3, n2, n1).
 
@@ -223,10 +240,11 @@ def exchange(psi, occ, grid, kernel, omega=0.0, pair_energies=False):
     phi = f(-L) rho, (Vx psi)_j -= occ_i phi psi_i and, for i != j,
     (Vx psi)_i -= occ_j phi psi_j.  Returns (vx, E_x[, {(i, j): e_ij}]) with
     e_ij = (rho_ij, phi_ij)_h and E_x = -1/4 sum_{i,j} occ_i occ_j e_ij.
+    zero_mode: see kernel_values_zero_mode.
     """
     psi = np.asarray(psi, dtype=np.float64)
     norb = psi.shape[0]
-    F = kernel_values(grid.lam_sum(), kernel, omega)
+    F = kernel_values_zero_mode(grid.lam_sum(), kernel, omega, zero_mode)
     vx = np.zeros_like(psi)
     ex = 0.0
     es = {}
@@ -457,12 +475,13 @@ def make_grid_bloch(n, h, order, bc, theta) -> Grid:
     return Grid(tuple(n), tuple(h), order, tuple(bc), tuple(lams), tuple(Vs))
 
 
-def apply_fL_bloch(rho: np.ndarray, grid: Grid, kernel: str, omega: float = 0.0) -> np.ndarray:
+def apply_fL_bloch(rho: np.ndarray, grid: Grid, kernel: str, omega: float = 0.0,
+                   zero_mode: float | None = None) -> np.ndarray:
     """phi = f(-L) rho for complex rho (..., n3, n2, n1) with the complex
     eigenbases of a Bloch grid: coefficients V^H rho mode by mode, the Hadamard
     product with f of the summed eigenvalues, then V back (Eqs. (17)-(21))."""
     V1, V2, V3 = grid.V
-    F = kernel_values(grid.lam_sum(), kernel, omega)
+    F = kernel_values_zero_mode(grid.lam_sum(), kernel, omega, zero_mode)
     T = _mode(np.asarray(rho, dtype=np.complex128), V1.conj(), -1)
     T = _mode(T, V2.conj(), -2)
     T = _mode(T, V3.conj(), -3)
@@ -487,7 +506,7 @@ def bloch_phases(kq, bc):
     return tuple(out)
 
 
-def exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, kernel, omega=0.0):
+def exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, kernel, omega=0.0, zero_mode=None):
     """Exact exchange with Brillouin-zone sampling for one spin channel,
     Sec. II, Eqs. (Vx:Poisson), (Ex:Poisson), (Poisson):
       (Vx psi)_{nk} = - sum_{m q} w_q occ_{mq} psi_{mq} phi_{mq,nk},
@@ -497,7 +516,8 @@ def exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, kernel, omega=0.0):
     (the spin-summed convention of `exchange`: occ = 2 g for a closed shell,
     occ = g per spin channel, whose energy is then half the channel's E_X).
     psi: (K, norb, n3, n2, n1) complex grid values; kpts (K, 3) reduced;
-    wk (K,) weights; occ (K, norb).  Every ordered pair is solved."""
+    wk (K,) weights; occ (K, norb).  Every ordered pair is solved.
+    zero_mode: f at the zero mode of the k = q problems (kernel_values_zero_mode)."""
     psi = np.asarray(psi, dtype=np.complex128)
     K, norb = psi.shape[:2]
     dV = h[0] * h[1] * h[2]
@@ -513,7 +533,7 @@ def exchange_bloch(psi, kpts, wk, occ, n, h, order, bc, kernel, omega=0.0):
             for nb in range(norb):
                 for mb in range(norb):
                     rho = np.conj(psi[qi, mb]) * psi[ki, nb]
-                    phi = apply_fL_bloch(rho, grid, kernel, omega)
+                    phi = apply_fL_bloch(rho, grid, kernel, omega, zero_mode)
                     vx[ki, nb] -= wk[qi] * occ[qi][mb] * psi[qi, mb] * phi
                     e = dV * complex(np.sum(np.conj(rho) * phi))
                     ex -= 0.25 * wk[ki] * wk[qi] * occ[ki][nb] * occ[qi][mb] * e.real
