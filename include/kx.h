@@ -247,6 +247,19 @@ kx_status kx_apply_exchange_noalloc(kx_grid* g, int kernel, double omega, int no
  * Work recorded into a graph before the call must not be replayed after it. */
 kx_status kx_set_cell(kx_grid* g, const double lattice[9]);
 
+/* The value of the unscreened kernel at the zero mode (Sec. IV: for 3D bulk
+ * systems the k = q problem is singular, and the paper takes the value from
+ * auxiliary functions; the library applies a value the caller computes).
+ * With enable = 1, KX_KERNEL_COULOMB on a grid whose spectrum contains 0
+ * (every axis periodic; for the Bloch calls, phases that are multiples of
+ * 2 pi) is solved with f = value on the zero mode (the constant, or its
+ * ramp) instead of returning KX_ERR_SINGULAR: phi = (-L)^+ 4 pi rho + value
+ * mean(rho).  The zero mode is recognised as an eigenvalue sum below 1e-9
+ * of the largest.  enable = 0 restores KX_ERR_SINGULAR.  Applies to every
+ * entry point and precision (the f table is FP64).  Work recorded into a
+ * graph before the call must not be replayed after it. */
+kx_status kx_set_zero_mode(kx_grid* g, int enable, double value);
+
 /* Opt-in checks.  KX_CHECK_FINITE: kx_apply_fL, kx_apply_fL_multipole,
  * kx_apply_exchange, kx_apply_exchange_noalloc, kx_apply_fL_bloch and
  * kx_apply_exchange_bloch scan their input fields before enqueueing any work

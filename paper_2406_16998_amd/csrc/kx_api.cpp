@@ -238,6 +238,8 @@ struct kx_grid {
   // the cell: lattice-coordinate metric and |det E| of a non-orthogonal
   // all-periodic cell (kx_set_cell); identity and 1 otherwise
   bool nonorth = false;
+  // the value of the unscreened kernel at the zero mode (kx_set_zero_mode)
+  ZeroMode zero;
   // opt-in checks (kx_set_checks) and their device flag
   int checks = 0;
   unsigned* dFlag = nullptr;
@@ -445,7 +447,8 @@ double lam_min_host(const kx_grid* g) {
 kx_status check_kernel_args(const kx_grid* g, int kernel, double omega) {
   if (kernel != KX_KERNEL_COULOMB && kernel != KX_KERNEL_ERFC) return KX_ERR_INVALID_ARG;
   if (kernel == KX_KERNEL_ERFC && !(std::isfinite(omega) && omega > 0.0)) return KX_ERR_INVALID_ARG;
-  if (kernel == KX_KERNEL_COULOMB && (all_periodic(g) || !(lam_min_host(g) > 0.0)))
+  if (kernel == KX_KERNEL_COULOMB && !g->zero.on &&
+      (all_periodic(g) || !(lam_min_host(g) > 0.0)))
     return KX_ERR_SINGULAR;
   return KX_OK;
 }
@@ -493,7 +496,7 @@ hipError_t fill_ftable(kx_grid* g, int kernel, double omega, hipStream_t s) {
   const double om = (kernel == KX_KERNEL_ERFC) ? omega : 0.0;
   const double* le[3] = {g->dLamE[0], g->dLamE[1], g->dLamE[2]};
   const double* lo[3] = {g->dLamO[0], g->dLamO[1], g->dLamO[2]};
-  return launch_ftable(le, lo, g->geom, kernel, om, g->dF, s);
+  return launch_ftable(le, lo, g->geom, kernel, om, g->dF, s, g->zero);
 }
 
 // Bytes of one slot of the intermediate for precision prec.
@@ -1131,9 +1134,21 @@ BlochAxes bloch_axes(const kx_grid* g) {
   fd_weights_d1_closed_form(g->order, B.d);
   B.m = g->order / 2;
   B.nonorth = g->nonorth ? 1 : 0;
+  B.zero = g->zero;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) B.gm[a][b] = g->cell_g[a][b];
   return B;
+}
+
+// The zero mode sits at rounding level; the smallest non-zero eigenvalue of
+// a periodic axis is (2 pi / (n h))^2 and far above 1e-9 of the largest.
+double zero_tolerance(const kx_grid* g) {
+  double lam_max = 0.0;
+  for (int a = 0; a < 3; ++a) lam_max += g->lam_host[a].back();
+  double gs = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) gs += std::fabs(g->cell_g[a][b]);
+  return 1e-9 * lam_max * std::max(1.0, gs);
 }
 
 // the volume element h1 h2 h3 |det E| of the cell
@@ -1877,10 +1892,21 @@ kx_status kx_set_cell(kx_grid* g, const double lattice[9]) {
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) g->cell_g[a][b] = gm[a][b];
   g->cell_jac = jac;
+  g->zero.tol = zero_tolerance(g);
   ++g->gen;  // recorded work carries the metric in its kernel arguments
   kx_logf("cell %s g=[%g %g %g; %g %g %g; %g %g %g] |det E|=%g",
           nonorth ? "non-orthogonal" : "orthogonal", gm[0][0], gm[0][1], gm[0][2], gm[1][0],
           gm[1][1], gm[1][2], gm[2][0], gm[2][1], gm[2][2], jac);
+  return KX_OK;
+}
+
+kx_status kx_set_zero_mode(kx_grid* g, int enable, double value) {
+  if (!g || (enable && !std::isfinite(value))) return KX_ERR_INVALID_ARG;
+  g->zero.on = enable ? 1 : 0;
+  g->zero.val = enable ? value : 0.0;
+  g->zero.tol = zero_tolerance(g);
+  ++g->gen;  // recorded work carries the value in its kernel arguments
+  kx_logf("zero mode %s value %g tolerance %g", enable ? "on" : "off", value, g->zero.tol);
   return KX_OK;
 }
 
@@ -1939,7 +1965,7 @@ kx_status kx_apply_fL_bloch(kx_grid* g, int kernel, double omega, int batch, con
       zero_mode = false;
     }
   }
-  if (kernel == KX_KERNEL_COULOMB && zero_mode) return KX_ERR_SINGULAR;
+  if (kernel == KX_KERNEL_COULOMB && zero_mode && !g->zero.on) return KX_ERR_SINGULAR;
   if (prec != KX_PREC_FP64) return KX_ERR_UNSUPPORTED;
   if (batch == 0) return KX_OK;
   if (!rho_dev || !phi_dev || rho_dev == phi_dev) return KX_ERR_INVALID_ARG;

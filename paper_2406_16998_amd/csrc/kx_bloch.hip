@@ -261,7 +261,10 @@ bloch_couple_kernel(BlochAxes B, Geom g, RepMap rm, const double* __restrict__ t
             lam += 2.0 * (B.gm[0][1] * q[0] * q[1] + B.gm[0][2] * q[0] * q[2] +
                           B.gm[1][2] * q[1] * q[2]);
           }
-          f[t] = (t & ~pmask) ? 0.0 : f_of(kernel, omega, lam);
+          f[t] = (t & ~pmask) ? 0.0
+                 : (kernel == KX_KERNEL_COULOMB && B.zero.on && lam <= B.zero.tol)
+                     ? B.zero.val
+                     : f_of(kernel, omega, lam);
         }
 #pragma unroll
         for (int Sm = 0; Sm < 8; ++Sm) {

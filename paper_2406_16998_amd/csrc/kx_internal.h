@@ -176,8 +176,15 @@ hipError_t launch_jacobi(double* A, double* V, int n, int max_sweeps, double rs,
                          double* lam_pad, double* Vpad, double* VTpad, int np, double* diag_out,
                          hipStream_t s);
 // f of the summed eigenvalues in the blocked [c][a][b] order, zero on padding
+// zero: for KX_KERNEL_COULOMB with zero.on, every eigenvalue sum lam <= zero.tol
+// (the zero mode) takes the value zero.val instead of 4 pi / lam
+struct ZeroMode {
+  int on = 0;
+  double val = 0.0, tol = 0.0;
+};
 hipError_t launch_ftable(const double* const lamE[3], const double* const lamO[3], const Geom& g,
-                         int kernel, double omega, double* F, hipStream_t s);
+                         int kernel, double omega, double* F, hipStream_t s,
+                         const ZeroMode& zero = ZeroMode());
 
 // ---- transform kernels (kx_fold_d.hip: double operands, kx_fold_f.hip: float)
 // mode: 0 = apply_fL (rho -> phi), 1 = exchange (psi -> vxpsi);
@@ -290,6 +297,7 @@ struct BlochAxes {
   // -L = sum_a g_aa (-L_a) - sum_{a != b} g_ab D_a D_b
   double gm[3][3];
   int nonorth;
+  ZeroMode zero;  // the unscreened kernel's zero-mode value
 };
 // reduced phases theta_a / (2 pi) of a batch of fields, per axis
 struct BlochT {

@@ -158,7 +158,8 @@ __device__ __forceinline__ bool blocked_lam(const LamPtrs& L, int axis, int idx,
   return true;
 }
 
-__global__ void ftable_kernel(LamPtrs L, Geom g, int kernel, double omega, double* __restrict__ F) {
+__global__ void ftable_kernel(LamPtrs L, Geom g, int kernel, double omega, ZeroMode zero,
+                              double* __restrict__ F) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.fsize) return;
   const int b = (int)(idx % g.p2);
@@ -169,7 +170,7 @@ __global__ void ftable_kernel(LamPtrs L, Geom g, int kernel, double omega, doubl
       blocked_lam(L, 2, c, g.me3, g.mo3, g.pe3, l3)) {
     const double lam = l1 + l2 + l3;
     if (kernel == KX_KERNEL_COULOMB) {
-      f = 4.0 * M_PI / lam;
+      f = (zero.on && lam <= zero.tol) ? zero.val : 4.0 * M_PI / lam;
     } else {
       const double x = lam / (4.0 * omega * omega);
       const double gx = (x == 0.0) ? 1.0 : -expm1(-x) / x;
@@ -190,7 +191,7 @@ hipError_t launch_jacobi(double* A, double* V, int n, int max_sweeps, double rs,
 }
 
 hipError_t launch_ftable(const double* const lamE[3], const double* const lamO[3], const Geom& g,
-                         int kernel, double omega, double* F, hipStream_t s) {
+                         int kernel, double omega, double* F, hipStream_t s, const ZeroMode& zero) {
   LamPtrs L;
   for (int k = 0; k < 3; ++k) {
     L.e[k] = lamE[k];
@@ -200,7 +201,7 @@ hipError_t launch_ftable(const double* const lamE[3], const double* const lamO[3
   const int threads = 256;
   const long long blocks = (total + threads - 1) / threads;
   hipLaunchKernelGGL(ftable_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, L, g, kernel,
-                     omega, F);
+                     omega, zero, F);
   return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "kx_batch_apply_exchange", "kx_autotune", "kx_get_plan", "kx_ace_build", "kx_ace_apply",
     "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc", "kx_apply_fL_multipole",
     "kx_reserve_bloch", "kx_apply_fL_bloch", "kx_apply_exchange_bloch", "kx_set_cell",
-    "kx_set_checks", "kx_apply_exchange_multipole",
+    "kx_set_checks", "kx_apply_exchange_multipole", "kx_set_zero_mode",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -67,6 +67,7 @@ def lib():
             "kx_reserve_bloch": [vp, c_int, c_int],
             "kx_set_cell": [vp, dp],
             "kx_set_checks": [vp, c_int],
+            "kx_set_zero_mode": [vp, c_int, c_double],
             "kx_apply_exchange_multipole": [vp, c_int, c_int, vp, dp, vp, c_int, c_int, dp],
             "kx_apply_fL_bloch": [vp, c_int, c_double, c_int, dp, vp, vp, c_int],
             "kx_apply_exchange_bloch": [vp, c_int, c_double, c_int, c_int, dp, dp, dp, vp, vp,
@@ -331,6 +332,12 @@ class Grid:
                                          int(lmax), _dptr(c))
         _check(st, "kx_apply_fL_multipole")
         return out
+
+    def set_zero_mode(self, value=None):
+        """kx_set_zero_mode: f at the zero mode of the unscreened kernel (None:
+        off, the singular case is refused)."""
+        _check(lib().kx_set_zero_mode(self._h, 0 if value is None else 1,
+                                      0.0 if value is None else float(value)), "kx_set_zero_mode")
 
     def set_checks(self, finite=True):
         """kx_set_checks: KX_CHECK_FINITE on or off."""
