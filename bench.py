@@ -69,8 +69,8 @@ def phase_bytes(w, prec):
 
 
 # the sources of the exchange's transform kernels and of their launch shapes
-KERNEL_SOURCES = ("kx_fold.inc", "kx_fold_d.hip", "kx_fold_f.hip", "kx_split.hip",
-                  "kx_energy_plan.hip", "kx_internal.h")
+KERNEL_SOURCES = ("kx_fold.inc", "kx_epilogue.inc", "kx_fold_d.hip", "kx_fold_f.hip",
+                  "kx_split.hip", "kx_energy_plan.hip", "kx_internal.h")
 
 
 def kernel_sources_digest():
