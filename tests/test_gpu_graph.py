@@ -109,3 +109,54 @@ def test_apply_without_reserve_reports_state(env):
     torch.cuda.synchronize()
     assert torch.isfinite(vx).all()
     g.close()
+
+
+def test_bloch_and_isolated_exchange_graph_replays_equal_eager(env):
+    # the k-point exchange and the isolated-system exchange also enqueue
+    # kernels only once reserved (k-points, weights and occupations travel as
+    # kernel arguments)
+    torch, kx = env
+    from synth import bloch_orbitals
+    from synth.orbitals import gaussian_orbitals, orthonormalise_cgs2
+    print("graph bloch + isolated exchange", flush=True)
+    n, h, P3 = (12, 10, 9), (0.5, 0.5, 0.5), ("periodic",) * 3
+    kpts = [(0.0, 0.0, 0.0), (0.5, 0.25, 0.0)]
+    psi = bloch_orbitals(n, h, P3, kpts, 3, seed=12, n_centres=6)
+    wk, occ = [0.5, 0.5], [[1.0, 0.8, 0.6], [0.9, 0.7, 0.5]]
+    D3 = ("dirichlet",) * 3
+    nd, hd = (16, 14, 18), (0.45, 0.45, 0.45)
+    psi_r = orthonormalise_cgs2(gaussian_orbitals(nd, hd, D3, 4, 3, 8, True), hd[0] * hd[1] * hd[2])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = kx.Grid(n, h, 6, P3, stream=s)
+        gd = kx.Grid(nd, hd, 8, D3, stream=s)
+        p = torch.from_numpy(psi).cuda()
+        pr = torch.from_numpy(psi_r).cuda()
+        g.reserve_bloch(2, 3)
+        gd.reserve(4, "fp64", "f64")
+        eager = g.apply_exchange_bloch(p, kpts, wk, occ, "erfc", 0.3).clone()
+        ex_eager = g.exchange_energy()
+        eager_d = gd.apply_exchange_multipole(pr, [2.0, 1.5, 1.0, 0.5], lmax=4).clone()
+        exd_eager = gd.exchange_energy()
+        out = torch.empty_like(p)
+        out_d = torch.empty_like(pr)
+    s.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        g.apply_exchange_bloch(p, kpts, wk, occ, "erfc", 0.3, out=out, reserve=False)
+        gd.apply_exchange_multipole(pr, [2.0, 1.5, 1.0, 0.5], lmax=4, out=out_d, reserve=False)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            g.apply_exchange_bloch(p, kpts, [0.3, 0.7], occ, "erfc", 0.5)
+            gd.apply_exchange_multipole(pr, [1.0, 1.0, 1.0, 1.0], lmax=2)
+            out.fill_(float("nan"))
+            out_d.fill_(float("nan"))
+        s.synchronize()
+        graph.replay()
+        s.synchronize()
+        assert torch.equal(out, eager), rep
+        assert torch.equal(out_d, eager_d), rep
+        assert g.exchange_energy() == ex_eager and gd.exchange_energy() == exd_eager, rep
+    del graph
+    g.close()
+    gd.close()
