@@ -177,3 +177,40 @@ def test_bloch_errors(kx):
         ref = orc.apply_fL_bloch(rho.cpu().numpy(), orc.make_grid_bloch(n, h, 4, P3, (0.5, 0.0, 0.0)),
                                  "coulomb")
         assert _rel(out.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("n,bc,theta", [
+    ((1, 7, 160), ("periodic", "periodic", "periodic"), (0.0, 1.3, -0.7)),   # one-node axis, the largest axis
+    ((2, 33, 5), ("periodic", "dirichlet", "periodic"), (2.1, 0.0, math.pi)),
+    ((160, 3, 4), ("periodic", "periodic", "dirichlet"), (0.9, -2.0, 0.0)),
+])
+def test_fL_bloch_edge_shapes(kx, n, bc, theta):
+    import torch
+    print(f"bloch edge n={n} bc={bc}", flush=True)
+    h = (0.4, 0.45, 0.35)
+    rho = _cfields(n, 2, seed=sum(n))
+    ref = orc.apply_fL_bloch(rho, orc.make_grid_bloch(n, h, 8, bc, theta), "erfc", 0.3)
+    with kx.Grid(n, h, 8, bc) as g:
+        out = g.apply_fL_bloch(torch.from_numpy(rho).cuda(), theta, "erfc", 0.3)
+        torch.cuda.synchronize()
+        assert _rel(out.cpu().numpy(), ref) <= TOL
+
+
+def test_exchange_bloch_degenerate_counts(kx):
+    import torch
+    n, h = (8, 9, 10), (0.5, 0.5, 0.5)
+    with kx.Grid(n, h, 4, P3) as g:
+        # no bands: E_x = 0, nothing else touched
+        empty = torch.zeros((2, 0, n[2], n[1], n[0]), dtype=torch.complex128, device="cuda")
+        g.apply_exchange_bloch(empty, [(0.0, 0.0, 0.0), (0.5, 0.0, 0.0)], [0.5, 0.5],
+                               np.zeros((2, 0)), "erfc", 0.3)
+        assert g.exchange_energy() == 0.0
+        # one state: the diagonal pair only
+        psi = bloch_orbitals(n, h, P3, [(0.25, 0.0, 0.5)], 1, seed=2, n_centres=3)
+        vx_ref, ex_ref = orc.exchange_bloch(psi, [(0.25, 0.0, 0.5)], [1.0], [[2.0]], n, h, 4, P3,
+                                            "erfc", 0.3)
+        vx = g.apply_exchange_bloch(torch.from_numpy(psi).cuda(), [(0.25, 0.0, 0.5)], [1.0],
+                                    [[2.0]], "erfc", 0.3)
+        torch.cuda.synchronize()
+        assert _rel(vx.cpu().numpy(), vx_ref) <= TOL
+        assert abs(g.exchange_energy() - ex_ref) <= TOL * abs(ex_ref)
