@@ -8,7 +8,9 @@ obviously correct, slow implementation written directly from the paper.
 from .kx_oracle import (  # noqa: F401
     Grid,
     ace_apply,
+    ace_apply_complex,
     ace_build,
+    ace_build_complex,
     apply_coulomb_multipole,
     apply_fL,
     apply_fL_bloch,

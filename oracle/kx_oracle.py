@@ -312,6 +312,38 @@ def ace_apply(xi, phi, dV):
     return (-(G.T @ X)).reshape(phi.shape)
 
 
+def ace_build_complex(psi, W, dV):
+    """The compressed exchange of one k-point (complex Bloch orbitals psi and
+    W = (Vx psi) at that k, both (norb, n3, n2, n1) complex):
+
+      M = (psi_j, W_k)_h = dV sum conj(psi_j) W_k    (Hermitian, negative definite)
+      -M = L L^H                                      (Cholesky)
+      xi = L^{-*} W, i.e. xi_k = sum_j conj((L^{-1})_kj) W_j
+
+    so that V_ACE phi = -sum_k xi_k (xi_k, phi)_h (ace_apply_complex)
+    reproduces Vx on the span of the orbitals."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    W = np.asarray(W, dtype=np.complex128)
+    norb = psi.shape[0]
+    P = psi.reshape(norb, -1)
+    Wm = W.reshape(norb, -1)
+    M = dV * (np.conj(P) @ Wm.T)
+    L = np.linalg.cholesky(-M)
+    xi = np.linalg.solve(np.conj(L), Wm)
+    return xi.reshape(W.shape)
+
+
+def ace_apply_complex(xi, phi, dV):
+    """V_ACE phi = -sum_k xi_k (xi_k, phi_v)_h for complex fields phi (nvec, ...)."""
+    xi = np.asarray(xi, dtype=np.complex128)
+    phi = np.asarray(phi, dtype=np.complex128)
+    norb, nvec = xi.shape[0], phi.shape[0]
+    X = xi.reshape(norb, -1)
+    F = phi.reshape(nvec, -1)
+    G = dV * (np.conj(X) @ F.T)          # (xi_k, phi_v)_h
+    return (-(G.T @ X)).reshape(phi.shape)
+
+
 # --------------------------------------------------------------------------
 # Sec. IV: isolated systems.  The unscreened problem on an all-Dirichlet grid
 # takes its boundary values from the multipole expansion of the Coulomb

@@ -163,3 +163,40 @@ def test_bloch_orbitals_are_orthonormal_bloch_functions():
     dV = 0.4 ** 3
     P = psi[0].reshape(4, -1)
     assert np.max(np.abs(dV * P.conj() @ P.T - np.eye(4))) <= 1e-12
+
+
+def test_complex_ace_reproduces_the_kpoint_exchange():
+    # the compressed exchange of one k-point (Sec. IV, with the Bloch
+    # exchange of Sec. II): V_ACE psi_nk = (Vx psi)_nk on the orbitals; as a
+    # matrix on a tiny grid it is Hermitian, negative semidefinite, of rank
+    # norb, equal to the projector form W M^{-1} W^H (explicit inverse), and
+    # zero on fields orthogonal to every W.
+    n, h, order = (5, 4, 6), (0.5, 0.5, 0.5), 4
+    kpts = [(0.25, 0.0, 0.0), (-0.25, 0.5, 0.0)]
+    psi = bloch_orbitals(n, h, P3, kpts, 3, seed=31, n_centres=4)
+    wk, occ = [0.5, 0.5], [[1.0, 0.7, 0.4], [0.9, 0.6, 0.3]]
+    vx, _ = orc.exchange_bloch(psi, kpts, wk, occ, n, h, order, P3, "erfc", 0.3)
+    dV = h[0] * h[1] * h[2]
+    N = n[0] * n[1] * n[2]
+    for k in range(2):
+        xi = orc.ace_build_complex(psi[k], vx[k], dV)
+        got = orc.ace_apply_complex(xi, psi[k], dV)
+        assert np.max(np.abs(got - vx[k])) <= 1e-12 * np.max(np.abs(vx[k]))
+        # dense matrix of the operator
+        E = np.eye(N).reshape(N, n[2], n[1], n[0]).astype(np.complex128)
+        A = orc.ace_apply_complex(xi, E, dV).reshape(N, N).T
+        assert np.allclose(A, A.conj().T, atol=1e-12 * np.max(np.abs(A)))
+        ev = np.linalg.eigvalsh(A)
+        assert ev.max() <= 1e-12 * abs(ev.min())
+        assert np.sum(np.abs(ev) > 1e-9 * abs(ev.min())) == 3
+        Wm = vx[k].reshape(3, N)
+        M = dV * np.conj(psi[k].reshape(3, N)) @ Wm.T
+        P = -Wm.T @ np.linalg.inv(M) @ np.conj(Wm) * dV
+        assert np.allclose(A, -P, atol=1e-10 * np.max(np.abs(A)))
+        # a field orthogonal to every W
+        rng = np.random.default_rng(k)
+        f = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        Q, _ = np.linalg.qr(Wm.T)  # orthonormal basis of span{W_j}
+        f -= Q @ (np.conj(Q.T) @ f)
+        out = orc.ace_apply_complex(xi, f.reshape(1, n[2], n[1], n[0]), dV)
+        assert np.max(np.abs(out)) <= 1e-10 * np.max(np.abs(f))
