@@ -127,7 +127,8 @@ kx_status kx_reserve(kx_grid* g, int norb, int prec, int dtype);
  * Enqueues kernels only (no allocation, host transfer or synchronisation), so
  * the call can be recorded into a caller's HIP graph.  KX_ERR_STATE if
  * kx_reserve was not called for prec and dtype.
- * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic. */
+ * KX_ERR_SINGULAR for KX_KERNEL_COULOMB when every axis is periodic, unless
+ * kx_set_zero_mode gave the zero mode a value. */
 kx_status kx_apply_fL(kx_grid* g, int kernel, double omega, int batch, int dtype,
                       const void* rho_dev, void* phi_dev, int prec);
 
@@ -388,6 +389,28 @@ kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, con
  * KX_ERR_STATE if no kx_ace_build on this handle had at least norb orbitals. */
 kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int nvec,
                        const void* phi_dev, void* out_dev);
+
+/* The compressed exchange of one k-point (Sec. IV with the k-point exchange
+ * of Sec. II): complex Bloch orbitals psi_nk and W = (Vx psi)_nk of that k
+ * (from kx_apply_exchange_bloch), norb interleaved complex fields each.
+ *   M = (psi_j, W_k)_h (Hermitian, negative definite), -M = L L^H,
+ *   xi = W L^{-H},  V_ACE phi = -sum_k xi_k (xi_k, phi)_h.
+ * The algebra runs on the real form: a complex field of N values is a real
+ * vector of 2 N, the span of the orbitals is spanned by the 2 norb real
+ * vectors {psi_j, i psi_j}, and the real compressed operator built on them
+ * (kx_ace_build's kernels) is the complex one.  xi_dev receives those
+ * 2 norb real vectors, i.e. 2 norb complex fields (pass them to
+ * kx_ace_apply_complex with the same norb).  FP64; 1 <= norb <= 512.
+ * Grows its buffers (the real forms, 64 bytes per grid point and orbital)
+ * and synchronises once, as kx_ace_build. */
+kx_status kx_ace_build_complex(kx_grid* g, int norb, const void* psi_dev, const void* w_dev,
+                               void* xi_dev);
+
+/* out_v = V_ACE phi_v for nvec interleaved complex fields (1 .. 4096), with
+ * xi_dev from kx_ace_build_complex (2 norb complex fields).  Enqueued only;
+ * KX_ERR_STATE if no build covered norb. */
+kx_status kx_ace_apply_complex(kx_grid* g, int norb, const void* xi_dev, int nvec,
+                               const void* phi_dev, void* out_dev);
 
 /* Copy lam_axis (n_axis values, ascending) and V_axis (n_axis x n_axis,
  * row-major, V[i*n + a] = component i of eigenvector a) to the host.  Either

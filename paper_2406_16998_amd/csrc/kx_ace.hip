@@ -16,8 +16,10 @@
 // arithmetic throughout; fields stored as double or float.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
+#include "kx_aux.h"
 #include "kx_internal.h"
 
 namespace kx {
@@ -374,6 +376,35 @@ hipError_t launch_combine(int storage, const double* C, long long ldv, long long
   else
     hipLaunchKernelGGL((combine<float>), grid, dim3(256), 0, s, C, ldv, ldk, m, n,
                        (const float*)X, N, alpha, (float*)Out);
+  return hipGetLastError();
+}
+
+}  // namespace kx
+
+// ---- real form of complex fields (the compressed exchange of k-points)
+
+namespace kx {
+namespace {
+
+__global__ void __launch_bounds__(256) realify_kernel(const double2* __restrict__ src, int n,
+                                                     long long N, double2* __restrict__ dst) {
+  const long long tot = (long long)n * N;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < tot;
+       k += (long long)gridDim.x * blockDim.x) {
+    const double2 z = src[k];
+    dst[k] = z;
+    dst[tot + k] = make_double2(-z.y, z.x);  // i z
+  }
+}
+
+}  // namespace
+
+hipError_t launch_realify(const double* src, int n, long long N, double* dst, hipStream_t s) {
+  const long long tot = (long long)n * N;
+  if (tot <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((tot + 255) / 256, 8192);
+  hipLaunchKernelGGL(realify_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     (const double2*)src, n, N, (double2*)dst);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@
 #include <utility>
 #include <vector>
 
+#include "kx_aux.h"
 #include "kx_internal.h"
 
 using namespace kx;
@@ -286,6 +287,11 @@ struct kx_grid {
   long long ace_mat_cap = 0;
   double* dAceG = nullptr;
   long long ace_g_cap = 0;
+  // real forms of complex orbitals and W for the compressed exchange of k-points
+  double* dAceU = nullptr;
+  long long ace_u_cap = 0;
+  double* dAceW = nullptr;
+  long long ace_w_cap = 0;
   int ace_norb = 0;  // largest orbital count kx_ace_apply is reserved for
   int* dAceStatus = nullptr;
   int last_norb = -1;
@@ -1593,6 +1599,8 @@ kx_status kx_destroy(kx_grid* g) {
   dev_free(g->dAceA);
   dev_free(g->dAceLinv);
   dev_free(g->dAceG);
+  dev_free(g->dAceU);
+  dev_free(g->dAceW);
   dev_free(g->dAceStatus);
   for (hipEvent_t ev : g->prof_ev) (void)hipEventDestroy(ev);
   (void)hipGetLastError();
@@ -2530,6 +2538,13 @@ kx_status check_ace_fields(const kx_grid* g, int norb, int dtype, const void* a,
   return KX_OK;
 }
 
+// the compressed exchange's algebra on norb fields of N values of storage
+// dtype (the real fields of a grid, or the real forms of complex fields)
+kx_status ace_build_core(kx_grid* g, int norb, int dtype, long long N, const void* psi_dev,
+                         const void* w_dev, void* xi_dev);
+kx_status ace_apply_core(kx_grid* g, int norb, int dtype, long long N, const void* xi_dev, int nvec,
+                         const void* phi_dev, void* out_dev);
+
 }  // namespace
 
 extern "C" {
@@ -2539,7 +2554,44 @@ kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, con
   const Range range("kx_ace_build");
   kx_status st = check_ace_fields(g, norb, dtype, psi_dev, w_dev, xi_dev);
   if (st != KX_OK) return st;
-  const long long N = g->geom.N, nn = (long long)norb * norb;
+  return ace_build_core(g, norb, dtype, g->geom.N, psi_dev, w_dev, xi_dev);
+}
+
+kx_status kx_ace_build_complex(kx_grid* g, int norb, const void* psi_dev, const void* w_dev,
+                               void* xi_dev) {
+  const Range range("kx_ace_build_complex");
+  if (!g || norb < 1 || 2 * norb > kAceMaxOrb || 2LL * norb > 2 * g->geom.N)
+    return KX_ERR_INVALID_ARG;
+  if (!psi_dev || !w_dev || !xi_dev || xi_dev == psi_dev || xi_dev == w_dev)
+    return KX_ERR_INVALID_ARG;
+  // the real forms [psi, i psi] and [W, i W]: 2 norb vectors of 2 N doubles each
+  const long long N2 = 2 * g->geom.N, len = 2LL * norb * N2;
+  kx_status st = ensure_doubles(g, &g->dAceU, &g->ace_u_cap, len);
+  if (st == KX_OK) st = ensure_doubles(g, &g->dAceW, &g->ace_w_cap, len);
+  if (st != KX_OK) return st;
+  KX_HIP(launch_realify((const double*)psi_dev, norb, g->geom.N, g->dAceU, g->stream));
+  KX_HIP(launch_realify((const double*)w_dev, norb, g->geom.N, g->dAceW, g->stream));
+  return ace_build_core(g, 2 * norb, KX_F64, N2, g->dAceU, g->dAceW, xi_dev);
+}
+
+kx_status kx_ace_apply_complex(kx_grid* g, int norb, const void* xi_dev, int nvec,
+                               const void* phi_dev, void* out_dev) {
+  const Range range("kx_ace_apply_complex");
+  if (!g || norb < 1 || 2 * norb > kAceMaxOrb) return KX_ERR_INVALID_ARG;
+  if (!xi_dev || !phi_dev || !out_dev || out_dev == xi_dev || out_dev == phi_dev)
+    return KX_ERR_INVALID_ARG;
+  if (nvec < 1 || nvec > kAceMaxVec) return KX_ERR_INVALID_ARG;
+  return ace_apply_core(g, 2 * norb, KX_F64, 2 * g->geom.N, xi_dev, nvec, phi_dev, out_dev);
+}
+
+}  // extern "C"
+
+namespace {
+
+kx_status ace_build_core(kx_grid* g, int norb, int dtype, long long N, const void* psi_dev,
+                         const void* w_dev, void* xi_dev) {
+  const long long nn = (long long)norb * norb;
+  kx_status st;
   const long long grp = ace_groups(N, norb, norb);
   // partial sums for this build and for every later kx_ace_apply on up to
   // kAceMaxVec fields, and the apply's coefficients: kx_ace_apply allocates
@@ -2580,13 +2632,9 @@ kx_status kx_ace_build(kx_grid* g, int norb, int dtype, const void* psi_dev, con
   return KX_OK;
 }
 
-kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int nvec,
-                       const void* phi_dev, void* out_dev) {
-  const Range range("kx_ace_apply");
-  kx_status st = check_ace_fields(g, norb, dtype, xi_dev, phi_dev, out_dev);
-  if (st != KX_OK) return st;
-  if (nvec < 1 || nvec > kAceMaxVec) return KX_ERR_INVALID_ARG;
-  const long long N = g->geom.N, nk = (long long)norb * nvec;
+kx_status ace_apply_core(kx_grid* g, int norb, int dtype, long long N, const void* xi_dev, int nvec,
+                         const void* phi_dev, void* out_dev) {
+  const long long nk = (long long)norb * nvec;
   const long long grp = ace_groups(N, norb, nvec);
   // buffers reserved by kx_ace_build
   if (norb > g->ace_norb || grp * nk > g->ace_part_cap || nk > g->ace_g_cap) return KX_ERR_STATE;
@@ -2597,6 +2645,19 @@ kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int 
   KX_HIP(launch_combine(dtype, g->dAceG, 1, nvec, nvec, norb, xi_dev, N, -1.0, out_dev,
                         g->stream));
   return KX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kx_status kx_ace_apply(kx_grid* g, int norb, int dtype, const void* xi_dev, int nvec,
+                       const void* phi_dev, void* out_dev) {
+  const Range range("kx_ace_apply");
+  kx_status st = check_ace_fields(g, norb, dtype, xi_dev, phi_dev, out_dev);
+  if (st != KX_OK) return st;
+  if (nvec < 1 || nvec > kAceMaxVec) return KX_ERR_INVALID_ARG;
+  return ace_apply_core(g, norb, dtype, g->geom.N, xi_dev, nvec, phi_dev, out_dev);
 }
 
 kx_status kx_pair_energies(kx_grid* g, int npairs, const int* pairs_host, double* e_out_host) {

@@ -31,6 +31,7 @@ EXPORTS = (
     "kx_profile_phases", "kx_reserve", "kx_apply_exchange_noalloc", "kx_apply_fL_multipole",
     "kx_reserve_bloch", "kx_apply_fL_bloch", "kx_apply_exchange_bloch", "kx_set_cell",
     "kx_set_checks", "kx_apply_exchange_multipole", "kx_set_zero_mode",
+    "kx_ace_build_complex", "kx_ace_apply_complex",
 )
 PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
 
@@ -68,6 +69,8 @@ def lib():
             "kx_set_cell": [vp, dp],
             "kx_set_checks": [vp, c_int],
             "kx_set_zero_mode": [vp, c_int, c_double],
+            "kx_ace_build_complex": [vp, c_int, vp, vp, vp],
+            "kx_ace_apply_complex": [vp, c_int, vp, c_int, vp, vp],
             "kx_apply_exchange_multipole": [vp, c_int, c_int, vp, dp, vp, c_int, c_int, dp],
             "kx_apply_fL_bloch": [vp, c_int, c_double, c_int, dp, vp, vp, c_int],
             "kx_apply_exchange_bloch": [vp, c_int, c_double, c_int, c_int, dp, dp, dp, vp, vp,
@@ -331,6 +334,49 @@ class Grid:
         st = lib().kx_apply_fL_multipole(self._h, rho.shape[0], dt, _ptr(rho), _ptr(out), PREC[prec],
                                          int(lmax), _dptr(c))
         _check(st, "kx_apply_fL_multipole")
+        return out
+
+    def ace_build_complex(self, psi, w, out=None):
+        """Compressed exchange of one k-point: psi and W = (Vx psi) complex128
+        of shape (norb, n3, n2, n1); returns xi, 2 norb complex fields (the
+        real form of the operator's vectors)."""
+        import torch
+        check_complex_fields(psi, self.shape3, self.device, "psi")
+        check_complex_fields(w, self.shape3, self.device, "w")
+        if w.shape != psi.shape:
+            raise ValueError("w: must match psi's shape")
+        norb = psi.shape[0]
+        if out is None:
+            out = torch.empty((2 * norb,) + tuple(psi.shape[1:]), dtype=psi.dtype, device=psi.device)
+        check_complex_fields(out, self.shape3, self.device, "out")
+        if out.shape[0] != 2 * norb:
+            raise ValueError("out: must hold 2 norb fields")
+        for src, name in ((psi, "psi"), (w, "w")):
+            a0, a1 = _span(src)
+            b0, b1 = _span(out)
+            if a0 < b1 and b0 < a1:
+                raise ValueError(f"out: overlaps {name}")
+        _check(lib().kx_ace_build_complex(self._h, norb, _ptr(psi), _ptr(w), _ptr(out)),
+               "kx_ace_build_complex")
+        return out
+
+    def ace_apply_complex(self, xi, phi, out=None):
+        """V_ACE phi for complex128 phi (nvec, n3, n2, n1), xi from
+        ace_build_complex."""
+        import torch
+        check_complex_fields(xi, self.shape3, self.device, "xi")
+        check_complex_fields(phi, self.shape3, self.device, "phi")
+        if xi.shape[0] % 2:
+            raise ValueError("xi: must hold 2 norb fields")
+        if out is None:
+            out = torch.empty_like(phi)
+        check_out(out, phi)
+        a0, a1 = _span(xi)
+        b0, b1 = _span(out)
+        if a0 < b1 and b0 < a1:
+            raise ValueError("out: overlaps xi")
+        _check(lib().kx_ace_apply_complex(self._h, xi.shape[0] // 2, _ptr(xi), phi.shape[0],
+                                          _ptr(phi), _ptr(out)), "kx_ace_apply_complex")
         return out
 
     def set_zero_mode(self, value=None):

@@ -108,6 +108,8 @@ def test_null_handle_and_host_helper_validation():
     assert L.kx_set_cell(None, dp) == 1
     assert L.kx_set_checks(None, 1) == 1
     assert L.kx_set_zero_mode(None, 1, 1.0) == 1
+    assert L.kx_ace_build_complex(None, 2, None, None, None) == 1
+    assert L.kx_ace_apply_complex(None, 2, None, 1, None, None) == 1
     assert L.kx_apply_exchange_multipole(None, 1, 0, None, None, None, 0, 2, dp) == 1
     assert L.kx_apply_fL_bloch(None, 1, 0.2, 1, dp, None, None, 0) == 1
     assert L.kx_apply_exchange_bloch(None, 1, 0.2, 1, 1, dp, dp, dp, None, None, 0) == 1

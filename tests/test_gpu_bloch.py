@@ -214,3 +214,30 @@ def test_exchange_bloch_degenerate_counts(kx):
         torch.cuda.synchronize()
         assert _rel(vx.cpu().numpy(), vx_ref) <= TOL
         assert abs(g.exchange_energy() - ex_ref) <= TOL * abs(ex_ref)
+
+
+def test_complex_ace_on_the_kpoint_exchange(kx):
+    # the compressed exchange of each k-point, built from the GPU's Vx psi:
+    # it reproduces Vx psi on the orbitals and matches the oracle's operator
+    # (built from the oracle's Vx psi) on other fields
+    import torch
+    n, h, order = (10, 9, 8), (0.5, 0.5, 0.5), 6
+    kpts = [(0.0, 0.0, 0.0), (0.5, 0.25, 0.0)]
+    norb = 4
+    psi = bloch_orbitals(n, h, P3, kpts, norb, seed=41, n_centres=6)
+    wk, occ = [0.5, 0.5], [[1.0, 0.9, 0.7, 0.5], [0.9, 0.8, 0.6, 0.4]]
+    vx_ref, _ = orc.exchange_bloch(psi, kpts, wk, occ, n, h, order, P3, "erfc", 0.3)
+    dV = h[0] * h[1] * h[2]
+    phi = _cfields(n, 5, seed=3)
+    with kx.Grid(n, h, order, P3) as g:
+        p = torch.from_numpy(psi).cuda()
+        vx = g.apply_exchange_bloch(p, kpts, wk, occ, "erfc", 0.3)
+        for k in range(2):
+            xi = g.ace_build_complex(p[k].contiguous(), vx[k].contiguous())
+            assert xi.shape[0] == 2 * norb
+            back = g.ace_apply_complex(xi, p[k].contiguous())
+            other = g.ace_apply_complex(xi, torch.from_numpy(phi).cuda())
+            torch.cuda.synchronize()
+            assert _rel(back.cpu().numpy(), vx[k].cpu().numpy()) <= 1e-10
+            ref = orc.ace_apply_complex(orc.ace_build_complex(psi[k], vx_ref[k], dV), phi, dV)
+            assert _rel(other.cpu().numpy(), ref) <= 1e-9
