@@ -33,20 +33,21 @@ __host__ __device__ inline int mom_index(int l, int m, int part) {
   return l * l + (m == 0 ? 0 : 2 * m - 1 + part);
 }
 
-// R^c_lm, R^s_lm of d for l <= L into out[mom_index]
-template <int L>
+// R^c_lm, R^s_lm of d for l <= L and M0 <= m <= M1 into out[mom_index]
+template <int L, int M0 = 0, int M1 = L>
 __device__ __forceinline__ void solid_harmonics(double x, double y, double z, double* out) {
   const double r2 = x * x + y * y + z * z;
   double cm = 1.0, sm = 0.0;  // (x + i y)^m
   double dfac = 1.0;          // (2m - 1)!!
 #pragma unroll
-  for (int m = 0; m <= L; ++m) {
+  for (int m = 0; m <= M1; ++m) {
     if (m > 0) {
       const double c2 = x * cm - y * sm, s2 = y * cm + x * sm;
       cm = c2;
       sm = s2;
       dfac *= (double)(2 * m - 1);
     }
+    if (m < M0) continue;
     double q2 = 0.0, q1 = dfac;  // Q_{m-1}^m = 0, Q_m^m = (2m-1)!!
 #pragma unroll
     for (int l = m; l <= L; ++l) {
@@ -68,53 +69,94 @@ struct Coords {
   double c[3];  // expansion centre
 };
 
-// partial moments of points [g * span, (g + 1) * span) of field b
-template <class S, int L>
+// the moment indices of orders M0 <= m <= M1 (l <= L): [lo, lo + count)
+// is not contiguous in mom_index, so kernels enumerate (l, m, part)
+template <int L, int M0, int M1>
+struct MRange {
+  static constexpr int count() {
+    int c = 0;
+    for (int m = M0; m <= M1; ++m) c += (L - m + 1) * (m == 0 ? 1 : 2);
+    return c;
+  }
+};
+
+// partial moments of points [g * span, (g + 1) * span) of field b, for the
+// orders M0 <= m <= M1 (a kernel per range keeps the harmonics and sums of
+// one thread in few registers)
+template <class S, int L, int M0, int M1>
 __global__ void __launch_bounds__(kMomThreads)
 moments_partial(const S* __restrict__ rho, Geom g, Coords cc, long long span,
                 double* __restrict__ part) {
   constexpr int K = (L + 1) * (L + 1);
-  __shared__ double red[kMomThreads / 64][K];
+  constexpr int KR = MRange<L, M0, M1>::count();
+  __shared__ double red[kMomThreads / 64][KR];
   const int grp = blockIdx.x, b = blockIdx.y, ngrp = gridDim.x;
   const S* __restrict__ f = rho + (long long)b * g.N;
-  double acc[K];
+  // the range's moment indices, in (m, l, part) order
+  int kidx[KR];
+  {
+    int t = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int m = M0; m <= M1; ++m)
+#pragma unroll
+      for (int l = m; l <= L; ++l) {
+        kidx[t++] = mom_index(l, m, 0);
+        if (m > 0) kidx[t++] = mom_index(l, m, 1);
+      }
+  }
+  double acc[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) acc[k] = 0.0;
   const long long p0 = (long long)grp * span, p1 = p0 + span < g.N ? p0 + span : g.N;
+  // 32-bit node arithmetic (N <= 160^3): 64-bit division dominated the loop
+  const unsigned n1 = (unsigned)g.n1, n12 = (unsigned)(g.n1 * g.n2);
   for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    const int i1 = (int)(p % g.n1);
-    const int i2 = (int)((p / g.n1) % g.n2);
-    const int i3 = (int)(p / ((long long)g.n1 * g.n2));
+    const unsigned pu = (unsigned)p;
+    const unsigned i3 = pu / n12, r12 = pu - i3 * n12;
+    const unsigned i2 = r12 / n1, i1 = r12 - i2 * n1;
     const double v = (double)f[p];
     double R[K];
-    solid_harmonics<L>(i1 * cc.h[0] - cc.c[0], i2 * cc.h[1] - cc.c[1], i3 * cc.h[2] - cc.c[2], R);
+    solid_harmonics<L, M0, M1>(i1 * cc.h[0] - cc.c[0], i2 * cc.h[1] - cc.c[1],
+                               i3 * cc.h[2] - cc.c[2], R);
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += v * R[k];
+    for (int k = 0; k < KR; ++k) acc[k] += v * R[kidx[k]];
   }
   // fixed-shape reduction: wave trees, then the waves in index order
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < KR; ++k) {
     double v = acc[k];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if (lane == 0) red[wave][k] = v;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+  for (int k = threadIdx.x; k < KR; k += blockDim.x) {
     double s = 0.0;
     for (int w = 0; w < kMomThreads / 64; ++w) s += red[w][k];
-    part[((long long)b * ngrp + grp) * K + k] = s;
+    part[((long long)b * ngrp + grp) * K + kidx[k]] = s;
   }
 }
 
 // moments[b][k] = dV * sum over groups in order
-__global__ void __launch_bounds__(64) moments_reduce(const double* __restrict__ part, int ngrp,
-                                                     int K, double dV, double* __restrict__ mom) {
-  const int b = blockIdx.x;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    double s = 0.0;
-    for (int q = 0; q < ngrp; ++q) s += part[((long long)b * ngrp + q) * K + k];
-    mom[(long long)b * K + k] = dV * s;
+// moments[b][k] = dV * sum over groups: four fixed segments of the groups,
+// each summed in order, then the segments in order
+constexpr int kRedSeg = 4;
+__global__ void __launch_bounds__(64 * kRedSeg) moments_reduce(const double* __restrict__ part,
+                                                               int ngrp, int K, double dV,
+                                                               double* __restrict__ mom) {
+  __shared__ double seg[kRedSeg][64];
+  const int b = blockIdx.x, k = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int per = (ngrp + kRedSeg - 1) / kRedSeg;
+  const int q0 = sg * per, q1 = min(ngrp, q0 + per);
+  double s = 0.0;
+  if (k < K)
+    for (int q = q0; q < q1; ++q) s += part[((long long)b * ngrp + q) * K + k];
+  seg[sg][k] = s;
+  __syncthreads();
+  if (sg == 0 && k < K) {
+    double t = 0.0;
+    for (int i = 0; i < kRedSeg; ++i) t += seg[i][k];
+    mom[(long long)b * K + k] = dV * t;
   }
 }
 
@@ -219,11 +261,19 @@ hipError_t launch_typed(const S* rho, S* dst, int nb, const Geom& g, const Coord
                         hipStream_t s) {
   constexpr int K = (L + 1) * (L + 1);
   const long long span = (g.N + ngrp - 1) / ngrp;
-  hipLaunchKernelGGL((moments_partial<S, L>), dim3(ngrp, nb), dim3(kMomThreads), 0, s, rho, g, cc,
-                     span, part);
+  // the orders m in two ranges of about equal size from L = 3 on
+  constexpr int MS = L >= 3 ? (L + 1) / 2 - (L == 6 ? 1 : 0) : L;
+  hipLaunchKernelGGL((moments_partial<S, L, 0, MS>), dim3(ngrp, nb), dim3(kMomThreads), 0, s, rho,
+                     g, cc, span, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(moments_reduce, dim3(nb), dim3(64), 0, s, part, ngrp, K, dV, mom);
+  if constexpr (MS < L) {
+    hipLaunchKernelGGL((moments_partial<S, L, MS + 1, L>), dim3(ngrp, nb), dim3(kMomThreads), 0, s,
+                       rho, g, cc, span, part);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(moments_reduce, dim3(nb), dim3(64 * kRedSeg), 0, s, part, ngrp, K, dV, mom);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long tot = (long long)nb * g.N;
