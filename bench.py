@@ -391,6 +391,55 @@ def measure_multipole(nfields=64, lmax=6, reps=5):
     return res
 
 
+def measure_solve_scaling(sizes=(32, 48, 64, 80, 96, 112, 128, 144, 160), nfields=64, reps=5,
+                          precs=("fp64", "mixed")):
+    """Single solves phi = f(-L) rho against the grid size (the paper's
+    solve-time comparison, Fig. 1, for this library alone): cubic periodic
+    grids of n^3 nodes, h = 0.3, order 12, erfc with omega = 0.106, a batch
+    of `nfields` N(0, 1) fields per call, planner launch shapes; mean of
+    `reps` calls after one warm-up, HIP events on the library's stream.
+    Reports ms per solve and the exponent of a fit t ~ N^a over the grids of
+    64^3 and more (the Kronecker solve costs O(N^(4/3)) flops)."""
+    import numpy as np
+    import torch
+
+    from paper_2406_16998_amd import kx
+    from synth import random_fields
+    out = {"grids": list(sizes), "fields": nfields, "kernel": "erfc", "omega": 0.106}
+    stream = torch.cuda.Stream()
+    for prec in precs:
+        rows = []
+        for n in sizes:
+            rho = torch.from_numpy(random_fields((n, n, n), nfields, seed=n)).cuda()
+            res = torch.empty_like(rho)
+            torch.cuda.synchronize()
+            g = kx.Grid((n, n, n), (0.3,) * 3, 12, ("periodic",) * 3, stream=stream)
+            g.apply_fL(rho, "erfc", 0.106, prec=prec, out=res)
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                start.record(stream)
+                for _ in range(reps):
+                    g.apply_fL(rho, "erfc", 0.106, prec=prec, out=res, reserve=False)
+                stop.record(stream)
+            torch.cuda.synchronize()
+            ms = start.elapsed_time(stop) / reps / nfields
+            rows.append({"n": n, "N": n ** 3, "ms_per_solve": ms})
+            g.close()
+            del rho, res
+        # below 64^3 a batch is too small to fill the GPU: fit the larger grids
+        big = [r for r in rows if r["n"] >= 64] or rows
+        logN = np.log([r["N"] for r in big])
+        logt = np.log([r["ms_per_solve"] for r in big])
+        a = float(np.polyfit(logN, logt, 1)[0])
+        out[prec] = {"rows": rows, "fit_exponent": a}
+        print(f"# solve scaling {prec}: t ~ N^{a:.2f}; " +
+              ", ".join(f"{r['n']}^3 {r['ms_per_solve']:.3f} ms" for r in rows),
+              file=sys.stderr, flush=True)
+    return out
+
+
 BLOCH_KMESH = [(a, b, c) for c in (0.0, 0.5) for b in (0.0, 0.5) for a in (0.0, 0.5)]
 
 
@@ -516,6 +565,8 @@ def main():
                     help="skip the k-point exchange timing")
     ap.add_argument("--bloch-only", action="store_true",
                     help="time only the k-point exchange (for profiling)")
+    ap.add_argument("--solve-scaling", action="store_true",
+                    help="time single solves against the grid size and exit")
     ap.add_argument("--multipole-only", action="store_true",
                     help="time only the isolated-system solves and exchange (for profiling)")
     ap.add_argument("--eager", action="store_true",
@@ -536,6 +587,9 @@ def main():
     from synth import make_workload
 
     torch.cuda.set_device(0)
+    if args.solve_scaling:
+        print(json.dumps({"solve_scaling": measure_solve_scaling()}))
+        return
     if args.multipole_only:
         print(json.dumps({"multipole": measure_multipole()}))
         return
