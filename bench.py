@@ -33,11 +33,32 @@ def mode_flops(N, n):
 
 
 def phase_flops(w):
-    """Algorithmic flops per item (pair) of each transform phase."""
+    """Algorithmic flops per item (pair) of each transform phase (the FP64
+    exchange's accumulation of Vx psi from stored potentials is VALU work,
+    counted as none)."""
     n1, n2, n3 = w.n
     N = w.N
     fw = mode_flops(N, n1) + mode_flops(N, n2)
-    return {"forward": fw, "pencil": 2 * mode_flops(N, n3), "inverse": fw}
+    return {"forward": fw, "pencil": 2 * mode_flops(N, n3), "inverse": fw, "accum": 0}
+
+
+XTILE = 8             # orbital tile edge of the FP64 exchange (two-stage)
+XTILE_MAX_ORB = 4096  # above it the FP64 exchange keeps the fused inverse pass
+
+
+def xtiles(norb):
+    """(pairs, orbitals) of every tile of the FP64 exchange: rows of block a,
+    columns of block b >= a; a diagonal tile holds its i <= j pairs."""
+    nbk = (norb + XTILE - 1) // XTILE
+    size = [min(XTILE, norb - XTILE * a) for a in range(nbk)]
+    out = []
+    for a in range(nbk):
+        for b in range(a, nbk):
+            if a == b:
+                out.append((size[a] * (size[a] + 1) // 2, size[a]))
+            else:
+                out.append((size[a] * size[b], size[a] + size[b]))
+    return out
 
 
 T_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "fp16x3": 4, "mixed": 8}
@@ -50,6 +71,11 @@ def phase_bytes(w, prec):
       pencil   reads and writes T                       2t N  (+ the f table once a launch)
       inverse  reads T, psi_i, psi_j, read-modify-writes Vx psi_i, Vx psi_j   (t + 6s) N
     A diagonal pair (i = i) touches one orbital: (s + t), 2t, (t + 3s) N.
+    The FP64 exchange (up to 4096 orbitals) runs in two stages instead: its
+    inverse pass reads T and writes the potential phi_ij in FP64, (t + 8) N,
+    and per tile of pairs the accumulation reads the tile's potentials (8 N
+    each) and reads psi and read-modify-writes Vx psi of each of its orbitals
+    once (3 s N each).
     Reduced precision on FP64 storage runs on FP32 working copies (s = 4).
     The mixed path reads the stored orbitals in its FP64 forward pass, writes
     an FP32 intermediate from the pencil pass (8 + 4 bytes there) and runs
@@ -62,10 +88,15 @@ def phase_bytes(w, prec):
     if prec == "mixed":
         return {"forward": (off * (2 * s_store + 8) + diag * (s_store + 8)) * N,
                 "pencil": (off + diag) * 12 * N,
-                "inverse": (off * (4 + 6 * s) + diag * (4 + 3 * s)) * N}
+                "inverse": (off * (4 + 6 * s) + diag * (4 + 3 * s)) * N, "accum": 0}
+    if prec == "fp64" and w.norb <= XTILE_MAX_ORB:
+        acc = sum(nb * 8 + orbs * 3 * s for nb, orbs in xtiles(w.norb)) * N
+        return {"forward": (off * (2 * s + t) + diag * (s + t)) * N,
+                "pencil": (off + diag) * 2 * t * N,
+                "inverse": (off + diag) * (t + 8) * N, "accum": acc}
     return {"forward": (off * (2 * s + t) + diag * (s + t)) * N,
             "pencil": (off + diag) * 2 * t * N,
-            "inverse": (off * (t + 6 * s) + diag * (t + 3 * s)) * N}
+            "inverse": (off * (t + 6 * s) + diag * (t + 3 * s)) * N, "accum": 0}
 
 
 # the sources of the exchange's transform kernels and of their launch shapes
@@ -167,7 +198,7 @@ def roofline(w, prec, phases, launches_per_step):
     the summed time and count of the timed launches of that phase."""
     pf = phase_flops(w)
     pb = phase_bytes(w, prec)
-    dom = max(pf, key=lambda p: phases[p]["ms"])
+    dom = max((p for p in pf if p in phases), key=lambda p: phases[p]["ms"])
     avg_ms = phases[dom]["ms"] / max(phases[dom]["launches"], 1)
     flops_launch = pf[dom] * w.npairs / launches_per_step
     bytes_launch = pb[dom] / launches_per_step
@@ -226,11 +257,11 @@ def measure(g, w, psi_d, occ, vx, prec, steps, warmup, tune, tune_cache=None, gr
         g.exchange_energy()
         print(f"# {prec} warmup {k + 1}/{max(warmup, 1)} done", file=sys.stderr, flush=True)
     phases1 = {}
-    for ph in ("forward", "pencil", "inverse", "energy"):
+    for ph in ("forward", "pencil", "inverse", "accum", "energy"):
         ms, cnt = g.profile_read(ph)
         phases1[ph] = {"ms": ms, "launches": cnt}
     g.profile(False)
-    dom = max(("forward", "pencil", "inverse"), key=lambda p: phases1[p]["ms"])
+    dom = max(("forward", "pencil", "inverse", "accum"), key=lambda p: phases1[p]["ms"])
     # one eager step creates the dominant phase's events; recording the step
     # into the graph then records them as graph nodes
     g.profile_phases([dom])

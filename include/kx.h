@@ -110,7 +110,10 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
  * in precision prec on storage dtype; earlier reservations are kept (a call
  * never shrinks them).  Per launch slot the intermediates take 8 bytes per
  * value of the padded grid (plus 4 for KX_PREC_MIXED); an exchange reservation
- * adds the pair schedule and pair energies (16 bytes per pair) and, for
+ * adds the pair schedule and pair energies (16 bytes per pair), for
+ * KX_PREC_FP64 with up to 4096 orbitals the potentials of one tile of pairs
+ * (64 fields of N FP64 values: the exchange then runs in two stages, see
+ * kx_apply_exchange), and, for
  * reduced precision on KX_F64 storage, FP32 copies of psi and Vx psi
  * (8*norb*N bytes).  Synchronises the stream when a buffer grows; a grown
  * buffer replaces the old one, so work recorded earlier into a graph must
@@ -194,7 +197,11 @@ kx_status kx_apply_exchange_multipole(kx_grid* g, int norb, int dtype, const voi
  * nothing, makes no host transfer or synchronisation and can be recorded
  * into a caller's HIP graph (the recorded work carries occ_host's values).
  * KX_ERR_STATE if kx_reserve was not called for at least norb orbitals in
- * prec and dtype. */
+ * prec and dtype.  * With KX_PREC_FP64 (up to 4096 orbitals) the pairs run in tiles of 8 x 8
+ * orbitals in two stages: the transforms write the tile's potentials, and
+ * one kernel applies them to Vx psi, reading and writing each orbital of the
+ * tile once.  Results do not depend on the batch size (the tiles are fixed).
+ */
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
                             const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                             int prec);
@@ -426,12 +433,13 @@ typedef enum {
   KX_PHASE_FORWARD = 0,  /* pair product + modes 2, 1 (per z-slab)          */
   KX_PHASE_PENCIL = 1,   /* mode 3, f(Lambda) scaling + energy, mode 3 back  */
   KX_PHASE_INVERSE = 2,  /* modes 1, 2 back + Vx psi accumulation            */
-  KX_PHASE_ENERGY = 3    /* deterministic energy reductions                  */
+  KX_PHASE_ENERGY = 3,   /* deterministic energy reductions                  */
+  KX_PHASE_ACCUM = 4     /* Vx psi from the stored potentials (FP64 exchange) */
 } kx_phase;
 kx_status kx_profile(kx_grid* g, int enable);
 kx_status kx_profile_read(kx_grid* g, int phase, double* total_ms, long long* launches);
 /* As kx_profile(g, 1), but brackets only the launches of the phases whose bit
- * (1 << KX_PHASE_*) is set in mask (1..15).  Each pair of events makes the
+ * (1 << KX_PHASE_*) is set in mask (1..31).  Each pair of events makes the
  * stream drain between the launches it separates, so timing one phase
  * disturbs a run less than timing all of them. */
 kx_status kx_profile_phases(kx_grid* g, int mask);

@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libkx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_SOURCES = ["kx_setup.hip", "kx_fold_d.hip", "kx_fold_f.hip", "kx_split.hip", "kx_energy_plan.hip",
-               "kx_ace.hip", "kx_multipole.hip", "kx_bloch.hip"]
+               "kx_ace.hip", "kx_multipole.hip", "kx_bloch.hip", "kx_accum.hip"]
 HOST_SOURCES = ["kx_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

@@ -195,6 +195,8 @@ struct Work {
   float* psi32 = nullptr;    // FP32 working copies of psi and Vx psi
   float* vx32 = nullptr;
   size_t work32_cap = 0;
+  double* phi = nullptr;     // the FP64 exchange's potentials of one tile of pairs
+  long long phi_cap = 0;     // (fields of N values)
 };
 
 }  // namespace
@@ -297,7 +299,7 @@ struct kx_grid {
   int last_norb = -1;
   // optional per-launch timing (hipEvents on the handle's stream)
   bool prof_on = false;
-  int prof_mask = 0xF;  // phases whose launches are bracketed (1 << KX_PHASE_*)
+  int prof_mask = 0x1F;  // phases whose launches are bracketed (1 << KX_PHASE_*)
   bool capturing = false;  // no timing events (the batch graph, the no-allocation path)
   bool recording = false;  // a caller records this call into a graph: timing events are
                            // recorded as graph nodes, but none is created
@@ -623,6 +625,10 @@ kx_status reserve(kx_grid* g, int norb, int prec, int dtype) {
   st = grow(g, &w.occ, &cap, norb);
   if (st != KX_OK) return st;
   w.occ_cap = (int)cap;
+  if (prec == KX_PREC_FP64 && norb <= kXTileMaxOrb) {  // the two-stage exchange's potentials
+    st = grow(g, &w.phi, &w.phi_cap, (long long)kXTile * kXTile * g->geom.N);
+    if (st != KX_OK) return st;
+  }
   if (all_dirichlet(g)) {  // the isolated-system exchange's energy partials
     st = grow(g, &w.dpart, &w.dpart_cap, (long long)norb * vx_energy_parts());
     if (st != KX_OK) return st;
@@ -640,6 +646,7 @@ kx_status reserve(kx_grid* g, int norb, int prec, int dtype) {
 }
 
 void free_work(Work& w) {
+  dev_free(w.phi);
   dev_free(w.mpart);
   dev_free(w.mmom);
   dev_free(w.fields);
@@ -932,12 +939,68 @@ kx_status plan_exchange(const kx_grid* g, const Work& w, int kernel, double omeg
   return KX_OK;
 }
 
+// The two-stage FP64 exchange: per tile of kXTile x kXTile orbital pairs the
+// forward pass (pair products), the pencil with the pair energies, the inverse
+// pass writing the tile's potentials phi_ij, and one accumulation kernel that
+// applies them to Vx psi, reading and writing each orbital of the tile once
+// (the fused inverse pass read-modify-writes two orbitals per pair).
+bool tiled_exchange(const kx_grid* g, const XPlan& xp, const Work& w) {
+  return xp.prec == KX_PREC_FP64 && w.phi && xp.norb <= kXTileMaxOrb &&
+         w.phi_cap >= (long long)kXTile * kXTile * g->geom.N && w.slots >= kXTile * kXTile;
+}
+
+hipError_t enqueue_exchange_tiled(kx_grid* g, const XPlan& xp, const Work& w, hipStream_t s) {
+  const Geom& G = g->geom;
+  const EigR<double> E = eig_of(g);
+  const int norb = xp.norb;
+  const int nstrips = (int)(G.slab / kTile);
+  double* T = (double*)w.T;
+  hipError_t e = fill_ftable(g, xp.kernel, xp.omega, s);
+  if (e == hipSuccess) e = launch_tile_schedule(norb, w.items, s);
+  if (e == hipSuccess) e = launch_put_doubles(xp.occ.data(), norb, w.occ, s);
+  if (e == hipSuccess) e = launch_zero(xp.vx, elem_size(xp.dtype) * xp.nel, s);
+  const int nbk = (norb + kXTile - 1) / kXTile;
+  long long off = 0;
+  for (int a = 0; a < nbk && e == hipSuccess; ++a)
+    for (int b = a; b < nbk && e == hipSuccess; ++b) {
+      const int nb = xtile_pairs(a, b, norb);
+      const Item* it = w.items + off;
+      off += nb;
+      e = timed(g, s, KX_PHASE_FORWARD, [&] {
+        return launch_forward_d(xp.dtype, 1, G, g->plan_d.fwd, E, xp.psi, it, nb, T, s);
+      });
+      if (e == hipSuccess)
+        e = timed(g, s, KX_PHASE_PENCIL, [&] {
+          return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, w.epart, s);
+        });
+      if (e == hipSuccess)
+        e = timed(g, s, KX_PHASE_ENERGY, [&] {
+          return launch_pair_energy(w.epart, nstrips, it, nb, norb, xp.dV, w.pairE, s);
+        });
+      if (e == hipSuccess)
+        e = timed(g, s, KX_PHASE_INVERSE, [&] {
+          return launch_inverse_d(KX_F64, 0, G, g->plan_d.inv, E, T, w.fitems, nb, nullptr,
+                                  nullptr, w.phi, s);
+        });
+      if (e == hipSuccess)
+        e = timed(g, s, KX_PHASE_ACCUM, [&] {
+          return launch_tile_accumulate(xp.dtype, w.phi, a, b, norb, G.N, xp.psi, w.occ, xp.vx,
+                                        s);
+        });
+    }
+  if (e != hipSuccess) return e;
+  return timed(g, s, KX_PHASE_ENERGY, [&] {
+    return launch_exchange_energy(w.pairE, w.occ, norb, g->dEx, s);
+  });
+}
+
 // The device work of one planned exchange application on stream s: kernels
 // only (no allocation, host transfer, memset or synchronisation), so it can
 // be recorded into a graph.  The f table, the pair schedule and the
 // occupations are written by kernels first.
 hipError_t enqueue_exchange(kx_grid* g, const XPlan& xp, const Work& w, hipStream_t s) {
   if (xp.norb == 0) return launch_zero(g->dEx, sizeof(double), s);
+  if (tiled_exchange(g, xp, w)) return enqueue_exchange_tiled(g, xp, w, s);
   hipError_t e = fill_ftable(g, xp.kernel, xp.omega, s);
   if (e == hipSuccess) e = launch_schedule(xp.norb, w.items, s);
   if (e == hipSuccess) e = launch_put_doubles(xp.occ.data(), xp.norb, w.occ, s);
@@ -2703,13 +2766,13 @@ kx_status kx_profile(kx_grid* g, int enable) {
     return KX_ERR_DEVICE;
   }
   g->prof_on = enable == 1;
-  g->prof_mask = 0xF;
+  g->prof_mask = 0x1F;
   g->prof_kind.clear();
   return KX_OK;
 }
 
 kx_status kx_profile_phases(kx_grid* g, int mask) {
-  if (!g || mask < 1 || mask > 0xF) return KX_ERR_INVALID_ARG;
+  if (!g || mask < 1 || mask > 0x1F) return KX_ERR_INVALID_ARG;
   if (hipStreamSynchronize(g->stream) != hipSuccess) {
     (void)hipGetLastError();
     return KX_ERR_DEVICE;
@@ -2721,7 +2784,7 @@ kx_status kx_profile_phases(kx_grid* g, int mask) {
 }
 
 kx_status kx_profile_read(kx_grid* g, int phase, double* total_ms, long long* launches) {
-  if (!g || !total_ms || !launches || phase < 0 || phase > KX_PHASE_ENERGY) return KX_ERR_INVALID_ARG;
+  if (!g || !total_ms || !launches || phase < 0 || phase > KX_PHASE_ACCUM) return KX_ERR_INVALID_ARG;
   if (hipStreamSynchronize(g->stream) != hipSuccess) {
     (void)hipGetLastError();
     return KX_ERR_DEVICE;

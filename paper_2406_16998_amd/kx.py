@@ -33,7 +33,7 @@ EXPORTS = (
     "kx_set_checks", "kx_apply_exchange_multipole", "kx_set_zero_mode",
     "kx_ace_build_complex", "kx_ace_apply_complex",
 )
-PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3}
+PHASE = {"forward": 0, "pencil": 1, "inverse": 2, "energy": 3, "accum": 4}
 
 
 class KxError(RuntimeError):

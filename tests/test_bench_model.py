@@ -43,18 +43,36 @@ def test_phase_bytes_sum_over_pairs(prec, storage):
     s_store = 8 if storage == "f64" else 4
     s = s_store if prec == "fp64" else 4
     t = {"fp64": 8, "fp32": 4, "bf16x3": 4, "fp16x3": 4, "mixed": 8}[prec]
-    tot = {"forward": 0, "pencil": 0, "inverse": 0}
+    tot = {"forward": 0, "pencil": 0, "inverse": 0, "accum": 0}
     for i, j in itertools.combinations_with_replacement(range(w.norb), 2):
         orbs = 1 if i == j else 2
         if prec == "mixed":
             tot["forward"] += (orbs * s_store + 8) * w.N
             tot["pencil"] += (8 + 4) * w.N
             tot["inverse"] += (4 + 3 * orbs * s) * w.N
+        elif prec == "fp64":
+            # two stages: the inverse pass writes phi_ij (FP64) ...
+            tot["forward"] += (orbs * s + t) * w.N
+            tot["pencil"] += 2 * t * w.N
+            tot["inverse"] += (t + 8) * w.N
+            tot["accum"] += 8 * w.N  # ... which the accumulation reads once
         else:
             tot["forward"] += (orbs * s + t) * w.N
             tot["pencil"] += 2 * t * w.N
             tot["inverse"] += (t + 3 * orbs * s) * w.N
+    if prec == "fp64":
+        # plus psi read and Vx psi read-modify-written once per orbital and
+        # tile: a tile of 8 x 8 orbitals, here 4 orbitals, is one diagonal tile
+        tot["accum"] += w.norb * 3 * s * w.N
     assert bench.phase_bytes(w, prec) == tot
+
+
+def test_xtiles_cover_every_pair_once():
+    for norb in (1, 7, 8, 9, 16, 33, 128):
+        tiles = bench.xtiles(norb)
+        assert sum(nb for nb, _ in tiles) == norb * (norb + 1) // 2
+        nbk = (norb + 7) // 8
+        assert len(tiles) == nbk * (nbk + 1) // 2
 
 
 def test_roofline_picks_the_bound_and_the_dominant_phase():
