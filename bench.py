@@ -71,7 +71,8 @@ def phase_bytes(w, prec):
       pencil   reads and writes T                       2t N  (+ the f table once a launch)
       inverse  reads T, psi_i, psi_j, read-modify-writes Vx psi_i, Vx psi_j   (t + 6s) N
     A diagonal pair (i = i) touches one orbital: (s + t), 2t, (t + 3s) N.
-    The FP64 exchange (up to 4096 orbitals) runs in two stages instead: its
+    The FP64 exchange on FP64 storage (up to 4096 orbitals) runs in two
+    stages instead: its
     inverse pass reads T and writes the potential phi_ij in FP64, (t + 8) N,
     and per tile of pairs the accumulation reads the tile's potentials (8 N
     each) and reads psi and read-modify-writes Vx psi of each of its orbitals
@@ -89,7 +90,7 @@ def phase_bytes(w, prec):
         return {"forward": (off * (2 * s_store + 8) + diag * (s_store + 8)) * N,
                 "pencil": (off + diag) * 12 * N,
                 "inverse": (off * (4 + 6 * s) + diag * (4 + 3 * s)) * N, "accum": 0}
-    if prec == "fp64" and w.norb <= XTILE_MAX_ORB:
+    if prec == "fp64" and w.storage == "f64" and w.norb <= XTILE_MAX_ORB:
         acc = sum(nb * 8 + orbs * 3 * s for nb, orbs in xtiles(w.norb)) * N
         return {"forward": (off * (2 * s + t) + diag * (s + t)) * N,
                 "pencil": (off + diag) * 2 * t * N,

@@ -111,7 +111,8 @@ kx_status kx_setup_laplacian(const int n[3], const double h[3], int fd_order,
  * never shrinks them).  Per launch slot the intermediates take 8 bytes per
  * value of the padded grid (plus 4 for KX_PREC_MIXED); an exchange reservation
  * adds the pair schedule and pair energies (16 bytes per pair), for
- * KX_PREC_FP64 with up to 4096 orbitals the potentials of one tile of pairs
+ * KX_PREC_FP64 on KX_F64 storage with up to 4096 orbitals the potentials of
+ * one tile of pairs
  * (64 fields of N FP64 values: the exchange then runs in two stages, see
  * kx_apply_exchange), and, for
  * reduced precision on KX_F64 storage, FP32 copies of psi and Vx psi
@@ -197,11 +198,13 @@ kx_status kx_apply_exchange_multipole(kx_grid* g, int norb, int dtype, const voi
  * nothing, makes no host transfer or synchronisation and can be recorded
  * into a caller's HIP graph (the recorded work carries occ_host's values).
  * KX_ERR_STATE if kx_reserve was not called for at least norb orbitals in
- * prec and dtype.  * With KX_PREC_FP64 (up to 4096 orbitals) the pairs run in tiles of 8 x 8
- * orbitals in two stages: the transforms write the tile's potentials, and
- * one kernel applies them to Vx psi, reading and writing each orbital of the
- * tile once.  Results do not depend on the batch size (the tiles are fixed).
- */
+ * prec and dtype.
+ * With KX_PREC_FP64 on KX_F64 storage (up to 4096 orbitals) the pairs run in
+ * tiles of 8 x 8 orbitals in two stages: the transforms write the tile's
+ * potentials, and one kernel applies them to Vx psi, reading and writing
+ * each orbital of the tile once (the other cases update Vx psi in the
+ * inverse pass, two orbitals per pair).  Either way results do not depend
+ * on the batch size. */
 kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int dtype,
                             const void* psi_dev, const double* occ_host, void* vxpsi_dev,
                             int prec);

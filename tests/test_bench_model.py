@@ -50,7 +50,7 @@ def test_phase_bytes_sum_over_pairs(prec, storage):
             tot["forward"] += (orbs * s_store + 8) * w.N
             tot["pencil"] += (8 + 4) * w.N
             tot["inverse"] += (4 + 3 * orbs * s) * w.N
-        elif prec == "fp64":
+        elif prec == "fp64" and storage == "f64":
             # two stages: the inverse pass writes phi_ij (FP64) ...
             tot["forward"] += (orbs * s + t) * w.N
             tot["pencil"] += 2 * t * w.N
@@ -60,7 +60,7 @@ def test_phase_bytes_sum_over_pairs(prec, storage):
             tot["forward"] += (orbs * s + t) * w.N
             tot["pencil"] += 2 * t * w.N
             tot["inverse"] += (t + 3 * orbs * s) * w.N
-    if prec == "fp64":
+    if prec == "fp64" and storage == "f64":
         # plus psi read and Vx psi read-modify-written once per orbital and
         # tile: a tile of 8 x 8 orbitals, here 4 orbitals, is one diagonal tile
         tot["accum"] += w.norb * 3 * s * w.N
