@@ -949,7 +949,7 @@ kx_status plan_exchange(const kx_grid* g, const Work& w, int kernel, double omeg
 // is 24 of 32 bytes and the fused pass stays faster (measured at 144^3).
 bool tiled_exchange(const kx_grid* g, const XPlan& xp, const Work& w) {
   return xp.prec == KX_PREC_FP64 && xp.dtype == KX_F64 && w.phi && xp.norb <= kXTileMaxOrb &&
-         w.phi_cap >= (long long)kXTile * kXTile * g->geom.N && w.slots >= kXTile * kXTile;
+         w.phi_cap >= (long long)kXTile * kXTile * g->geom.N && w.slots >= 1;
 }
 
 hipError_t enqueue_exchange_tiled(kx_grid* g, const XPlan& xp, const Work& w, hipStream_t s) {
@@ -966,25 +966,29 @@ hipError_t enqueue_exchange_tiled(kx_grid* g, const XPlan& xp, const Work& w, hi
   long long off = 0;
   for (int a = 0; a < nbk && e == hipSuccess; ++a)
     for (int b = a; b < nbk && e == hipSuccess; ++b) {
-      const int nb = xtile_pairs(a, b, norb);
-      const Item* it = w.items + off;
-      off += nb;
-      e = timed(g, s, KX_PHASE_FORWARD, [&] {
-        return launch_forward_d(xp.dtype, 1, G, g->plan_d.fwd, E, xp.psi, it, nb, T, s);
-      });
-      if (e == hipSuccess)
-        e = timed(g, s, KX_PHASE_PENCIL, [&] {
-          return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, w.epart, s);
+      const int npt = xtile_pairs(a, b, norb);
+      // the tile's pairs through the transforms in launches of up to `slots`
+      for (int p0 = 0; p0 < npt && e == hipSuccess; p0 += w.slots) {
+        const int nb = std::min(w.slots, npt - p0);
+        const Item* it = w.items + off + p0;
+        e = timed(g, s, KX_PHASE_FORWARD, [&] {
+          return launch_forward_d(xp.dtype, 1, G, g->plan_d.fwd, E, xp.psi, it, nb, T, s);
         });
-      if (e == hipSuccess)
-        e = timed(g, s, KX_PHASE_ENERGY, [&] {
-          return launch_pair_energy(w.epart, nstrips, it, nb, norb, xp.dV, w.pairE, s);
-        });
-      if (e == hipSuccess)
-        e = timed(g, s, KX_PHASE_INVERSE, [&] {
-          return launch_inverse_d(KX_F64, 0, G, g->plan_d.inv, E, T, w.fitems, nb, nullptr,
-                                  nullptr, w.phi, s);
-        });
+        if (e == hipSuccess)
+          e = timed(g, s, KX_PHASE_PENCIL, [&] {
+            return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, w.epart, s);
+          });
+        if (e == hipSuccess)
+          e = timed(g, s, KX_PHASE_ENERGY, [&] {
+            return launch_pair_energy(w.epart, nstrips, it, nb, norb, xp.dV, w.pairE, s);
+          });
+        if (e == hipSuccess)
+          e = timed(g, s, KX_PHASE_INVERSE, [&] {
+            return launch_inverse_d(KX_F64, 0, G, g->plan_d.inv, E, T, w.fitems, nb, nullptr,
+                                    nullptr, w.phi + (long long)p0 * G.N, s);
+          });
+      }
+      off += npt;
       if (e == hipSuccess)
         e = timed(g, s, KX_PHASE_ACCUM, [&] {
           return launch_tile_accumulate(xp.dtype, w.phi, a, b, norb, G.N, xp.psi, w.occ, xp.vx,

@@ -44,9 +44,11 @@ def test_noalloc_matches_apply_exchange_twice(prec):
         pe = g.pair_energies(pairs)
         torch.cuda.synchronize()
         if prec == "fp64":
-            # same arithmetic in the same order: bitwise equal
-            assert torch.equal(out, ref)
+            # the pair energies come from the same transforms: bitwise equal;
+            # Vx psi is accumulated per tile by kx_apply_exchange (two-stage
+            # form) and per pair by the fused pass here: equal to rounding
             assert ex == ex_ref and np.array_equal(pe, pe_ref)
+            assert _rel(out.cpu().numpy(), ref.cpu().numpy()) <= 1e-12
         else:
             # reduced precision reads and accumulates the FP64 arrays directly
             # instead of FP32 working copies
