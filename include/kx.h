@@ -217,8 +217,11 @@ kx_status kx_apply_exchange(kx_grid* g, int kernel, double omega, int norb, int 
  * fixed device array of KX_SCRATCH_BYTES per device instead of the handle's
  * workspace; kx_reserve is not needed.  No FP32 working copies: reduced
  * precisions on KX_F64 storage read and update the caller's FP64 arrays
- * directly, and Vx psi accumulates in FP64.  Launches take as many pairs as
- * fit in the array (up to the handle's batch size).
+ * directly, and Vx psi accumulates in FP64.  The FP64 path keeps the fused
+ * inverse pass (no room for a tile's potentials), so its Vx psi equals
+ * kx_apply_exchange's to rounding (the pair energies and E_x bitwise).
+ * Launches take as many pairs as fit in the array (up to the handle's batch
+ * size).
  * KX_ERR_OUT_OF_MEMORY if the schedule, pair energies and one launch slot
  * (at 96^3 about 7 MB in FP64) do not fit in KX_SCRATCH_BYTES.
  * Every call on one device shares that device's array and leaves its
