@@ -64,6 +64,11 @@ def xtiles(norb):
 T_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "fp16x3": 4, "mixed": 8}
 
 
+def max_tiles(w):
+    """16-row tiles of the largest parity block of the grid's axes."""
+    return max((((n + 1) // 2 + 15) // 16) for n in w.n)
+
+
 def phase_bytes(w, prec):
     """Algorithmic HBM bytes of each phase summed over all pairs of one step
     (N values per field; s bytes per orbital value, t per intermediate value):
@@ -71,12 +76,13 @@ def phase_bytes(w, prec):
       pencil   reads and writes T                       2t N  (+ the f table once a launch)
       inverse  reads T, psi_i, psi_j, read-modify-writes Vx psi_i, Vx psi_j   (t + 6s) N
     A diagonal pair (i = i) touches one orbital: (s + t), 2t, (t + 3s) N.
-    The FP64 exchange on FP64 storage (up to 4096 orbitals) runs in two
-    stages instead: its
-    inverse pass reads T and writes the potential phi_ij in FP64, (t + 8) N,
-    and per tile of pairs the accumulation reads the tile's potentials (8 N
-    each) and reads psi and read-modify-writes Vx psi of each of its orbitals
-    once (3 s N each).
+    The FP64 exchange on FP64 storage, and the mixed, FP32 and BF16x3 ones
+    on grids of up to three tiles per parity block (up to 4096 orbitals), run
+    in two stages instead: the inverse pass reads T and writes the potential
+    phi_ij (FP64 for fp64, else FP32: p bytes), (t + p) N, and per tile of
+    pairs the accumulation reads the tile's potentials (p N each) and reads
+    psi and read-modify-writes Vx psi of each of its orbitals once (3 s N
+    each).
     Reduced precision on FP64 storage runs on FP32 working copies (s = 4).
     The mixed path reads the stored orbitals in its FP64 forward pass, writes
     an FP32 intermediate from the pencil pass (8 + 4 bytes there) and runs
@@ -86,15 +92,20 @@ def phase_bytes(w, prec):
     t = T_BYTES[prec]
     off, diag = w.norb * (w.norb - 1) // 2, w.norb
     N = w.N
+    two = w.norb <= XTILE_MAX_ORB and (
+        (prec == "fp64" and w.storage == "f64") or
+        (prec in ("mixed", "fp32", "bf16x3") and max_tiles(w) <= 3))
+    # two stages: the potentials in FP64 (fp64) or FP32, read back once
+    phi_b = 8 if prec == "fp64" else 4
+    acc = sum(nb * phi_b + orbs * 3 * s for nb, orbs in xtiles(w.norb)) * N if two else 0
     if prec == "mixed":
+        inv = ((off + diag) * (4 + phi_b) if two else off * (4 + 6 * s) + diag * (4 + 3 * s)) * N
         return {"forward": (off * (2 * s_store + 8) + diag * (s_store + 8)) * N,
-                "pencil": (off + diag) * 12 * N,
-                "inverse": (off * (4 + 6 * s) + diag * (4 + 3 * s)) * N, "accum": 0}
-    if prec == "fp64" and w.storage == "f64" and w.norb <= XTILE_MAX_ORB:
-        acc = sum(nb * 8 + orbs * 3 * s for nb, orbs in xtiles(w.norb)) * N
+                "pencil": (off + diag) * 12 * N, "inverse": inv, "accum": acc}
+    if two:
         return {"forward": (off * (2 * s + t) + diag * (s + t)) * N,
                 "pencil": (off + diag) * 2 * t * N,
-                "inverse": (off + diag) * (t + 8) * N, "accum": acc}
+                "inverse": (off + diag) * (t + phi_b) * N, "accum": acc}
     return {"forward": (off * (2 * s + t) + diag * (s + t)) * N,
             "pencil": (off + diag) * 2 * t * N,
             "inverse": (off * (t + 6 * s) + diag * (t + 3 * s)) * N, "accum": 0}

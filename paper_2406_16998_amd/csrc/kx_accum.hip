@@ -1,5 +1,6 @@
-// The two-stage FP64 exchange: the inverse pass writes the potentials phi_ij
-// of one tile of orbital pairs, and the kernels here apply the tile to
+// The two-stage exchange: the inverse pass writes the potentials phi_ij of
+// one tile of orbital pairs (FP64, or FP32 in the reduced precisions), and
+// the kernels here apply the tile to
 // Vx psi (Sec. II, the exchange operator in Poisson form):
 //   (Vx psi)_j -= occ_i phi_ij psi_i,   (Vx psi)_i -= occ_j phi_ij psi_j (i != j).
 // A thread owns one grid point and holds the tile's orbitals (psi and the
@@ -48,9 +49,9 @@ __global__ void tile_schedule_kernel(int norb, Item* __restrict__ out) {
     }
 }
 
-template <class S>
+template <class P, class S>
 __global__ void __launch_bounds__(256)
-tile_accumulate_kernel(const double* __restrict__ phi, int a, int b, int norb, long long N,
+tile_accumulate_kernel(const P* __restrict__ phi, int a, int b, int norb, long long N,
                        const S* __restrict__ psi, const double* __restrict__ occ,
                        S* __restrict__ vx) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -79,7 +80,7 @@ tile_accumulate_kernel(const double* __restrict__ phi, int a, int b, int norb, l
 #pragma unroll
     for (int c = 0; c < kXTile; ++c) {
       if (r >= sa || c >= sb || (diag && r > c)) continue;
-      const double p = phi[(long long)t * N + x];
+      const double p = (double)phi[(long long)t * N + x];
       ++t;
       double ur = 0.0, orr = 0.0;
 #pragma unroll
@@ -115,16 +116,25 @@ hipError_t launch_tile_schedule(int norb, Item* out, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tile_accumulate(int storage, const double* phi, int a, int b, int norb,
-                                  long long N, const void* psi, const double* occ, void* vx,
-                                  hipStream_t s) {
+hipError_t launch_tile_accumulate(int storage, int phi_storage, const void* phi, int a, int b,
+                                  int norb, long long N, const void* psi, const double* occ,
+                                  void* vx, hipStream_t s) {
   const dim3 grid((unsigned)((N + 255) / 256));
-  if (storage == KX_F64)
-    hipLaunchKernelGGL(tile_accumulate_kernel<double>, grid, dim3(256), 0, s, phi, a, b, norb, N,
-                       (const double*)psi, occ, (double*)vx);
-  else
-    hipLaunchKernelGGL(tile_accumulate_kernel<float>, grid, dim3(256), 0, s, phi, a, b, norb, N,
-                       (const float*)psi, occ, (float*)vx);
+#define KX_ACC(P, S)                                                                          \
+  hipLaunchKernelGGL((tile_accumulate_kernel<P, S>), grid, dim3(256), 0, s, (const P*)phi, a, b, \
+                     norb, N, (const S*)psi, occ, (S*)vx)
+  if (phi_storage == KX_F64) {
+    if (storage == KX_F64)
+      KX_ACC(double, double);
+    else
+      KX_ACC(double, float);
+  } else {
+    if (storage == KX_F64)
+      KX_ACC(float, double);
+    else
+      KX_ACC(float, float);
+  }
+#undef KX_ACC
   return hipGetLastError();
 }
 

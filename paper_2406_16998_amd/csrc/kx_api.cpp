@@ -625,7 +625,7 @@ kx_status reserve(kx_grid* g, int norb, int prec, int dtype) {
   st = grow(g, &w.occ, &cap, norb);
   if (st != KX_OK) return st;
   w.occ_cap = (int)cap;
-  if (prec == KX_PREC_FP64 && dtype == KX_F64 && norb <= kXTileMaxOrb) {  // two-stage exchange
+  if (norb <= kXTileMaxOrb && prec != KX_PREC_FP16X3) {  // the two-stage exchange's potentials
     st = grow(g, &w.phi, &w.phi_cap, (long long)kXTile * kXTile * g->geom.N);
     if (st != KX_OK) return st;
   }
@@ -939,29 +939,110 @@ kx_status plan_exchange(const kx_grid* g, const Work& w, int kernel, double omeg
   return KX_OK;
 }
 
-// The two-stage FP64 exchange: per tile of kXTile x kXTile orbital pairs the
+// The two-stage exchange: per tile of kXTile x kXTile orbital pairs the
 // forward pass (pair products), the pencil with the pair energies, the inverse
 // pass writing the tile's potentials phi_ij, and one accumulation kernel that
 // applies them to Vx psi, reading and writing each orbital of the tile once
 // (the fused inverse pass read-modify-writes two orbitals per pair).
-// Taken for FP64 storage, where the fused pass's orbital traffic (48 of its
-// 56 bytes per pair and point) is what bounds it; with FP32 storage that share
-// is 24 of 32 bytes and the fused pass stays faster (measured at 144^3).
+// FP64 takes it on FP64 storage, where the fused pass's orbital traffic (48 of
+// its 56 bytes per pair and point) is what bounds it; with FP32 storage that
+// share is 24 of 32 bytes and the fused pass stays faster (measured at
+// 144^3).  The reduced precisions (FP16x3 aside, whose scales follow the
+// fused pass) take it on grids of up to three tiles per parity block, where
+// their inverse pass is bound by its bytes; the larger grids' inverse passes
+// are latency-bound and keep the fused form.
 bool tiled_exchange(const kx_grid* g, const XPlan& xp, const Work& w) {
-  return xp.prec == KX_PREC_FP64 && xp.dtype == KX_F64 && w.phi && xp.norb <= kXTileMaxOrb &&
-         w.phi_cap >= (long long)kXTile * kXTile * g->geom.N && w.slots >= 1;
+  const Geom& G = g->geom;
+  if (!w.phi || xp.norb > kXTileMaxOrb || w.phi_cap < (long long)kXTile * kXTile * G.N ||
+      w.slots < 1)
+    return false;
+  if (xp.prec == KX_PREC_FP64) return xp.dtype == KX_F64;
+  const int nt = std::max(G.pe1, std::max(G.pe2, G.pe3)) / kTile;
+  return (xp.prec == KX_PREC_MIXED || xp.prec == KX_PREC_FP32 || xp.prec == KX_PREC_BF16X3) &&
+         nt <= 3;
+}
+
+// the transforms of one launch of the two-stage exchange: pair products,
+// forward modes, the pencil with its pair energies and the inverse modes into
+// the potentials phi (FP64 for KX_PREC_FP64, FP32 otherwise)
+hipError_t tiled_transforms(kx_grid* g, const XPlan& xp, const Work& w, hipStream_t s,
+                            const Item* it, int nb, void* phi) {
+  const Geom& G = g->geom;
+  const int nstrips = (int)(G.slab / kTile);
+  auto energy = [&] {
+    return timed(g, s, KX_PHASE_ENERGY, [&] {
+      return launch_pair_energy(w.epart, nstrips, it, nb, xp.norb, xp.dV, w.pairE, s);
+    });
+  };
+  hipError_t e = hipSuccess;
+  if (xp.prec == KX_PREC_FP64 || xp.prec == KX_PREC_MIXED) {
+    const EigR<double> E = eig_of(g);
+    double* T = (double*)w.T;
+    const bool mixed = xp.prec == KX_PREC_MIXED;
+    e = timed(g, s, KX_PHASE_FORWARD, [&] {
+      return launch_forward_d(xp.dtype, 1, G, g->plan_d.fwd, E, xp.psi, it, nb, T, s);
+    });
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_PENCIL, [&] {
+        return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, w.epart, s,
+                               mixed ? w.T2 : nullptr);
+      });
+    if (e == hipSuccess) e = energy();
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_INVERSE, [&] {
+        return mixed ? launch_inverse_s(KX_F32, 0, G, g->plan_s.inv, eigs_of(g), w.T2, w.fitems,
+                                        nb, nullptr, nullptr, phi, s)
+                     : launch_inverse_d(KX_F64, 0, G, g->plan_d.inv, E, T, w.fitems, nb, nullptr,
+                                        nullptr, phi, s);
+      });
+    return e;
+  }
+  float* T = (float*)w.T;
+  if (xp.prec == KX_PREC_FP32) {
+    const EigR<float> E = eigf_of(g);
+    e = timed(g, s, KX_PHASE_FORWARD, [&] {
+      return launch_forward_f(xp.dtype_w, 1, G, g->plan_f.fwd, E, xp.psi_w, it, nb, T, s);
+    });
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_PENCIL, [&] {
+        return launch_pencil_f(G, g->plan_f.pen, E, g->dF, nb, T, w.epart, s);
+      });
+    if (e == hipSuccess) e = energy();
+    if (e == hipSuccess)
+      e = timed(g, s, KX_PHASE_INVERSE, [&] {
+        return launch_inverse_f(KX_F32, 0, G, g->plan_f.inv, E, T, w.fitems, nb, nullptr,
+                                nullptr, phi, s);
+      });
+    return e;
+  }
+  const EigS E = eigs_of(g);  // split BF16
+  e = timed(g, s, KX_PHASE_FORWARD, [&] {
+    return launch_forward_s(xp.dtype_w, 1, G, g->plan_s.fwd, E, xp.psi_w, it, nb, T, s);
+  });
+  if (e == hipSuccess)
+    e = timed(g, s, KX_PHASE_PENCIL, [&] {
+      return launch_pencil_s(G, g->plan_s.pen, E, g->dF, nb, T, w.epart, s);
+    });
+  if (e == hipSuccess) e = energy();
+  if (e == hipSuccess)
+    e = timed(g, s, KX_PHASE_INVERSE, [&] {
+      return launch_inverse_s(KX_F32, 0, G, g->plan_s.inv, E, T, w.fitems, nb, nullptr, nullptr,
+                              phi, s);
+    });
+  return e;
 }
 
 hipError_t enqueue_exchange_tiled(kx_grid* g, const XPlan& xp, const Work& w, hipStream_t s) {
   const Geom& G = g->geom;
-  const EigR<double> E = eig_of(g);
   const int norb = xp.norb;
-  const int nstrips = (int)(G.slab / kTile);
-  double* T = (double*)w.T;
+  const int phi_storage = xp.prec == KX_PREC_FP64 ? KX_F64 : KX_F32;
+  const size_t phi_field = elem_size(phi_storage) * (size_t)G.N;
   hipError_t e = fill_ftable(g, xp.kernel, xp.omega, s);
   if (e == hipSuccess) e = launch_tile_schedule(norb, w.items, s);
   if (e == hipSuccess) e = launch_put_doubles(xp.occ.data(), norb, w.occ, s);
-  if (e == hipSuccess) e = launch_zero(xp.vx, elem_size(xp.dtype) * xp.nel, s);
+  if (e == hipSuccess && xp.narrow)
+    e = launch_narrow((const double*)xp.psi, w.psi32, (long long)xp.nel, s);
+  if (e == hipSuccess) e = launch_zero(xp.vx_w, elem_size(xp.dtype_w) * xp.nel, s);
   const int nbk = (norb + kXTile - 1) / kXTile;
   long long off = 0;
   for (int a = 0; a < nbk && e == hipSuccess; ++a)
@@ -970,31 +1051,17 @@ hipError_t enqueue_exchange_tiled(kx_grid* g, const XPlan& xp, const Work& w, hi
       // the tile's pairs through the transforms in launches of up to `slots`
       for (int p0 = 0; p0 < npt && e == hipSuccess; p0 += w.slots) {
         const int nb = std::min(w.slots, npt - p0);
-        const Item* it = w.items + off + p0;
-        e = timed(g, s, KX_PHASE_FORWARD, [&] {
-          return launch_forward_d(xp.dtype, 1, G, g->plan_d.fwd, E, xp.psi, it, nb, T, s);
-        });
-        if (e == hipSuccess)
-          e = timed(g, s, KX_PHASE_PENCIL, [&] {
-            return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, w.epart, s);
-          });
-        if (e == hipSuccess)
-          e = timed(g, s, KX_PHASE_ENERGY, [&] {
-            return launch_pair_energy(w.epart, nstrips, it, nb, norb, xp.dV, w.pairE, s);
-          });
-        if (e == hipSuccess)
-          e = timed(g, s, KX_PHASE_INVERSE, [&] {
-            return launch_inverse_d(KX_F64, 0, G, g->plan_d.inv, E, T, w.fitems, nb, nullptr,
-                                    nullptr, w.phi + (long long)p0 * G.N, s);
-          });
+        e = tiled_transforms(g, xp, w, s, w.items + off + p0, nb,
+                             static_cast<char*>(static_cast<void*>(w.phi)) + phi_field * p0);
       }
       off += npt;
       if (e == hipSuccess)
         e = timed(g, s, KX_PHASE_ACCUM, [&] {
-          return launch_tile_accumulate(xp.dtype, w.phi, a, b, norb, G.N, xp.psi, w.occ, xp.vx,
-                                        s);
+          return launch_tile_accumulate(xp.dtype_w, phi_storage, w.phi, a, b, norb, G.N, xp.psi_w,
+                                        w.occ, xp.vx_w, s);
         });
     }
+  if (e == hipSuccess && xp.narrow) e = launch_widen(w.vx32, (double*)xp.vx, (long long)xp.nel, s);
   if (e != hipSuccess) return e;
   return timed(g, s, KX_PHASE_ENERGY, [&] {
     return launch_exchange_energy(w.pairE, w.occ, norb, g->dEx, s);

@@ -40,9 +40,10 @@ __host__ __device__ inline int xtile_pairs(int a, int b, int norb) {
 // the items of every tile, in order (norb(norb+1)/2 items)
 hipError_t launch_tile_schedule(int norb, Item* out, hipStream_t s);
 // Vx psi -= the tile (a, b)'s pairs: phi holds its pairs' potentials
-// (field t for the tile's pair t); psi, vx of storage KX_F64 / KX_F32
-hipError_t launch_tile_accumulate(int storage, const double* phi, int a, int b, int norb,
-                                  long long N, const void* psi, const double* occ, void* vx,
-                                  hipStream_t s);
+// (field t for the tile's pair t, storage phi_storage); psi, vx of storage
+// KX_F64 / KX_F32
+hipError_t launch_tile_accumulate(int storage, int phi_storage, const void* phi, int a, int b,
+                                  int norb, long long N, const void* psi, const double* occ,
+                                  void* vx, hipStream_t s);
 
 }  // namespace kx

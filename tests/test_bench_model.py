@@ -46,21 +46,27 @@ def test_phase_bytes_sum_over_pairs(prec, storage):
     tot = {"forward": 0, "pencil": 0, "inverse": 0, "accum": 0}
     for i, j in itertools.combinations_with_replacement(range(w.norb), 2):
         orbs = 1 if i == j else 2
+        # the toy grid is one tile per parity block: every precision but
+        # FP16x3 (and FP64 on FP32 storage) runs in two stages, the inverse
+        # pass writing phi_ij (FP64 for fp64, else FP32) that the
+        # accumulation reads once
+        two = prec != "fp16x3" and not (prec == "fp64" and storage == "f32")
+        pb = 8 if prec == "fp64" else 4
         if prec == "mixed":
             tot["forward"] += (orbs * s_store + 8) * w.N
             tot["pencil"] += (8 + 4) * w.N
-            tot["inverse"] += (4 + 3 * orbs * s) * w.N
-        elif prec == "fp64" and storage == "f64":
-            # two stages: the inverse pass writes phi_ij (FP64) ...
+            tot["inverse"] += (4 + pb) * w.N
+            tot["accum"] += pb * w.N
+        elif two:
             tot["forward"] += (orbs * s + t) * w.N
             tot["pencil"] += 2 * t * w.N
-            tot["inverse"] += (t + 8) * w.N
-            tot["accum"] += 8 * w.N  # ... which the accumulation reads once
+            tot["inverse"] += (t + pb) * w.N
+            tot["accum"] += pb * w.N
         else:
             tot["forward"] += (orbs * s + t) * w.N
             tot["pencil"] += 2 * t * w.N
             tot["inverse"] += (t + 3 * orbs * s) * w.N
-    if prec == "fp64" and storage == "f64":
+    if prec != "fp16x3" and not (prec == "fp64" and storage == "f32"):
         # plus psi read and Vx psi read-modify-written once per orbital and
         # tile: a tile of 8 x 8 orbitals, here 4 orbitals, is one diagonal tile
         tot["accum"] += w.norb * 3 * s * w.N
