@@ -1886,32 +1886,59 @@ kx_status kx_apply_exchange_multipole(kx_grid* g, int norb, int dtype, const voi
   double* T = (double*)w.T;
   g->recording = stream_capturing(s);
   hipError_t e = fill_ftable(g, KX_KERNEL_COULOMB, 0.0, s);
-  if (e == hipSuccess) e = launch_schedule(norb, w.items, s);
   if (e == hipSuccess) e = launch_put_doubles(xp.occ.data(), norb, w.occ, s);
   if (e == hipSuccess) e = launch_zero(vxpsi_dev, elem_size(dtype) * (size_t)nel, s);
-  for (size_t b = 0; e == hipSuccess && b + 1 < xp.offsets.size(); ++b) {
-    const int o0 = xp.offsets[b], nb = xp.offsets[b + 1] - o0;
-    if (nb <= 0) continue;
-    const Item* it = w.items + o0;
-    // rho_ij + c_ij / (4 pi) per pair, then the homogeneous solve and the
-    // Vx psi update of the exchange's inverse pass
-    e = launch_pair_fields(dtype, psi_dev, it, nb, G.N, w.fields, s);
-    if (e == hipSuccess)
-      e = launch_multipole_rhs(KX_F64, w.fields, w.fields, nb, G, g->h, centre, wfd,
+  // rho_ij + c_ij / (4 pi) per pair and the homogeneous solve; with room for
+  // a tile's potentials the pairs run in tiles whose potentials one kernel
+  // applies to Vx psi (as kx_apply_exchange's two-stage form), else in
+  // round-robin batches through the inverse pass's Vx psi epilogue
+  auto solve = [&](const Item* it, int nb, bool tile, void* phi) {
+    hipError_t r = launch_pair_fields(dtype, psi_dev, it, nb, G.N, w.fields, s);
+    if (r == hipSuccess)
+      r = launch_multipole_rhs(KX_F64, w.fields, w.fields, nb, G, g->h, centre, wfd,
                                g->order / 2, lmax, w.mpart, w.mmom, s);
-    if (e == hipSuccess)
-      e = timed(g, s, KX_PHASE_FORWARD, [&] {
+    if (r == hipSuccess)
+      r = timed(g, s, KX_PHASE_FORWARD, [&] {
         return launch_forward_d(KX_F64, 0, G, g->plan_d.fwd, E, w.fields, w.fitems, nb, T, s);
       });
-    if (e == hipSuccess)
-      e = timed(g, s, KX_PHASE_PENCIL, [&] {
+    if (r == hipSuccess)
+      r = timed(g, s, KX_PHASE_PENCIL, [&] {
         return launch_pencil_d(G, g->plan_d.pen, E, g->dF, nb, T, nullptr, s);
       });
-    if (e == hipSuccess)
-      e = timed(g, s, KX_PHASE_INVERSE, [&] {
-        return launch_inverse_d(dtype, 1, G, g->plan_d.inv, E, T, it, nb, psi_dev, w.occ,
-                                vxpsi_dev, s);
+    if (r == hipSuccess)
+      r = timed(g, s, KX_PHASE_INVERSE, [&] {
+        return tile ? launch_inverse_d(KX_F64, 0, G, g->plan_d.inv, E, T, w.fitems, nb, nullptr,
+                                       nullptr, phi, s)
+                    : launch_inverse_d(dtype, 1, G, g->plan_d.inv, E, T, it, nb, psi_dev, w.occ,
+                                       vxpsi_dev, s);
       });
+    return r;
+  };
+  const bool tiles = w.phi && norb <= kXTileMaxOrb &&
+                     w.phi_cap >= (long long)kXTile * kXTile * G.N;
+  if (tiles) {
+    if (e == hipSuccess) e = launch_tile_schedule(norb, w.items, s);
+    const int nbk = (norb + kXTile - 1) / kXTile;
+    long long off = 0;
+    for (int a = 0; a < nbk && e == hipSuccess; ++a)
+      for (int b = a; b < nbk && e == hipSuccess; ++b) {
+        const int npt = xtile_pairs(a, b, norb);
+        for (int p0 = 0; p0 < npt && e == hipSuccess; p0 += w.slots)
+          e = solve(w.items + off + p0, std::min(w.slots, npt - p0), true,
+                    w.phi + (long long)p0 * G.N);
+        off += npt;
+        if (e == hipSuccess)
+          e = timed(g, s, KX_PHASE_ACCUM, [&] {
+            return launch_tile_accumulate(dtype, KX_F64, w.phi, a, b, norb, G.N, psi_dev, w.occ,
+                                          vxpsi_dev, s);
+          });
+      }
+  } else {
+    if (e == hipSuccess) e = launch_schedule(norb, w.items, s);
+    for (size_t b = 0; e == hipSuccess && b + 1 < xp.offsets.size(); ++b) {
+      const int o0 = xp.offsets[b], nb = xp.offsets[b + 1] - o0;
+      if (nb > 0) e = solve(w.items + o0, nb, false, nullptr);
+    }
   }
   // E_x = 1/4 sum_j occ_j <psi_j, (Vx psi)_j>_h (the boundary values make the
   // pair solve non-symmetric, so the energy is taken from the operator)
