@@ -64,11 +64,6 @@ def xtiles(norb):
 T_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "fp16x3": 4, "mixed": 8}
 
 
-def max_tiles(w):
-    """16-row tiles of the largest parity block of the grid's axes."""
-    return max((((n + 1) // 2 + 15) // 16) for n in w.n)
-
-
 def phase_bytes(w, prec):
     """Algorithmic HBM bytes of each phase summed over all pairs of one step
     (N values per field; s bytes per orbital value, t per intermediate value):
@@ -77,8 +72,7 @@ def phase_bytes(w, prec):
       inverse  reads T, psi_i, psi_j, read-modify-writes Vx psi_i, Vx psi_j   (t + 6s) N
     A diagonal pair (i = i) touches one orbital: (s + t), 2t, (t + 3s) N.
     The FP64 exchange on FP64 storage, and the mixed, FP32 and BF16x3 ones
-    on grids of up to three tiles per parity block (up to 4096 orbitals), run
-    in two stages instead: the inverse pass reads T and writes the potential
+    (up to 4096 orbitals), run in two stages instead: the inverse pass reads T and writes the potential
     phi_ij (FP64 for fp64, else FP32: p bytes), (t + p) N, and per tile of
     pairs the accumulation reads the tile's potentials (p N each) and reads
     psi and read-modify-writes Vx psi of each of its orbitals once (3 s N
@@ -93,8 +87,7 @@ def phase_bytes(w, prec):
     off, diag = w.norb * (w.norb - 1) // 2, w.norb
     N = w.N
     two = w.norb <= XTILE_MAX_ORB and (
-        (prec == "fp64" and w.storage == "f64") or
-        (prec in ("mixed", "fp32", "bf16x3") and max_tiles(w) <= 3))
+        (prec == "fp64" and w.storage == "f64") or prec in ("mixed", "fp32", "bf16x3"))
     # two stages: the potentials in FP64 (fp64) or FP32, read back once
     phi_b = 8 if prec == "fp64" else 4
     acc = sum(nb * phi_b + orbs * 3 * s for nb, orbs in xtiles(w.norb)) * N if two else 0

@@ -947,19 +947,16 @@ kx_status plan_exchange(const kx_grid* g, const Work& w, int kernel, double omeg
 // FP64 takes it on FP64 storage, where the fused pass's orbital traffic (48 of
 // its 56 bytes per pair and point) is what bounds it; with FP32 storage that
 // share is 24 of 32 bytes and the fused pass stays faster (measured at
-// 144^3).  The reduced precisions (FP16x3 aside, whose scales follow the
-// fused pass) take it on grids of up to three tiles per parity block, where
-// their inverse pass is bound by its bytes; the larger grids' inverse passes
-// are latency-bound and keep the fused form.
+// 144^3).  The mixed, FP32 and BF16x3 paths, with FP32 potentials, take it
+// everywhere (equal or faster at 96^3 and 144^3); FP16x3 keeps the fused pass
+// (its scales follow the fused pass's items).
 bool tiled_exchange(const kx_grid* g, const XPlan& xp, const Work& w) {
   const Geom& G = g->geom;
   if (!w.phi || xp.norb > kXTileMaxOrb || w.phi_cap < (long long)kXTile * kXTile * G.N ||
       w.slots < 1)
     return false;
   if (xp.prec == KX_PREC_FP64) return xp.dtype == KX_F64;
-  const int nt = std::max(G.pe1, std::max(G.pe2, G.pe3)) / kTile;
-  return (xp.prec == KX_PREC_MIXED || xp.prec == KX_PREC_FP32 || xp.prec == KX_PREC_BF16X3) &&
-         nt <= 3;
+  return xp.prec == KX_PREC_MIXED || xp.prec == KX_PREC_FP32 || xp.prec == KX_PREC_BF16X3;
 }
 
 // the transforms of one launch of the two-stage exchange: pair products,
